@@ -1,0 +1,1174 @@
+/*
+ * FCIQMC oracle (test infrastructure only; see fq_oracle.h).
+ *
+ * Plain single-threaded C, FP64 throughout, built with -ffp-contract=off so
+ * that every product and sum is rounded exactly as written. Lists are sorted
+ * arrays compared as unsigned big integers; spawned walkers are sorted with
+ * qsort and merged with a two-pointer walk. Nothing here is blocked, fused or
+ * reordered beyond the order each step states.
+ */
+#include "fq_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,  */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11). The paper's code   */
+/* uses dSFMT (Sec. 3.1); a counter-based generator keyed by (seed, replica)  */
+/* with counter (tag|attempt, iteration, det hash) makes every draw a pure    */
+/* function of what it is used for, so list order never changes results.    */
+/* ------------------------------------------------------------------------- */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u; /* Weyl increments of the Philox key schedule */
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* 53-bit uniform in [0,1) from two words: top 32 bits from a, 21 from b. */
+static double u53(uint32_t a, uint32_t b)
+{
+    uint64_t m = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
+    return (double)m * 0x1p-53;
+}
+
+/* floor(w * n / 2^32): an integer in [0, n) from one 32-bit word. */
+static uint32_t pick(uint32_t w, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
+}
+
+enum { TAG_SELECT = 0, TAG_SELECT2 = 1, TAG_SPAWN_ROUND = 2, TAG_DEATH = 3, TAG_SEMISTOCH = 4 };
+
+static void draw(const or_run *r, uint32_t tag, uint32_t attempt, uint32_t t, uint64_t h,
+                 uint32_t out[4]);
+
+/* ------------------------------------------------------------------------- */
+/* Determinant hash. The paper hashes bit strings with MurmurHash2 (Sec. 3.1, */
+/* appendix "Parallelization", eq. hash). MurmurHash64A (Appleby, public      */
+/* domain) over the 8W bytes of the words, least significant word first.     */
+/* ------------------------------------------------------------------------- */
+#define OR_HASH_SEED 0x9E3779B97F4A7C15ull
+
+uint64_t or_hash64(const uint64_t *w, int W)
+{
+    const uint64_t m = 0xc6a4a7935bd1e995ull;
+    const int r = 47;
+    uint64_t h = OR_HASH_SEED ^ ((uint64_t)(8 * W) * m);
+    for (int i = 0; i < W; ++i) {
+        uint64_t k = w[i];
+        k *= m;
+        k ^= k >> r;
+        k *= m;
+        h ^= k;
+        h *= m;
+    }
+    h ^= h >> r;
+    h *= m;
+    h ^= h >> r;
+    return h;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Bit strings. Spin-orbital P = 2p + sigma (sigma 0 = alpha, 1 = beta) lives */
+/* in word P/64, bit P%64. |D> = a+_{P1} a+_{P2} ... |0> with P1 < P2 < ...   */
+/* ------------------------------------------------------------------------- */
+static int getbit(const uint64_t *k, int P) { return (int)((k[P >> 6] >> (P & 63)) & 1u); }
+static void setbit(uint64_t *k, int P) { k[P >> 6] |= (uint64_t)1 << (P & 63); }
+static void clrbit(uint64_t *k, int P) { k[P >> 6] &= ~((uint64_t)1 << (P & 63)); }
+
+static int occ_list(const uint64_t *k, int n_so, int *occ)
+{
+    int n = 0;
+    for (int P = 0; P < n_so; ++P)
+        if (getbit(k, P)) occ[n++] = P;
+    return n;
+}
+
+static int key_cmp(const uint64_t *a, const uint64_t *b, int W)
+{
+    for (int i = W - 1; i >= 0; --i) {
+        if (a[i] < b[i]) return -1;
+        if (a[i] > b[i]) return 1;
+    }
+    return 0;
+}
+
+/* (-1)^{number of occupied spin-orbitals strictly between P and A} */
+static double parity_between(const uint64_t *k, int P, int A)
+{
+    int lo = P < A ? P : A, hi = P < A ? A : P, c = 0;
+    for (int X = lo + 1; X < hi; ++X) c += getbit(k, X);
+    return (c & 1) ? -1.0 : 1.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Systems (paper Sec. 4.2: UEG and Hubbard model systems; Sec. 3.1 and the   */
+/* tutorial appendix: molecular integrals h_pq, (pq|rs)).                     */
+/* ------------------------------------------------------------------------- */
+struct or_sys {
+    int kind, n_spatial, n_so, W, nel, na, nb;
+    /* Hubbard ring / chain */
+    int periodic;
+    double t, U;
+    /* uniform electron gas */
+    double rs, L, k2, vc;
+    int ecut, vlen, gmax, gdim;
+    int32_t *nvec;  /* [n_spatial][3] */
+    double *eps;    /* kinetic energy per spatial orbital */
+    double *vtab;   /* v(|dn|^2) */
+    int32_t *grid;  /* momentum -> spatial index, -1 outside the basis */
+    /* molecular */
+    double *h1, *eri;
+    /* heat-bath tables, pair index P*n_so + Q for P < Q */
+    int64_t *hb_off;
+    int32_t *hb_cnt;
+    double *hb_S;
+    int32_t *hb_A, *hb_B;
+    double *hb_cdf;
+    int64_t hb_n;
+    uint64_t ref[OR_MAXW];
+    double H00;
+};
+
+static or_sys *sys_alloc(int kind, int n_spatial, int na, int nb)
+{
+    or_sys *s = (or_sys *)calloc(1, sizeof(or_sys));
+    s->kind = kind;
+    s->n_spatial = n_spatial;
+    s->n_so = 2 * n_spatial;
+    s->W = (s->n_so + 63) / 64;
+    s->na = na;
+    s->nb = nb;
+    s->nel = na + nb;
+    return s;
+}
+
+static double eri_at(const or_sys *s, int p, int q, int r, int t)
+{
+    int n = s->n_spatial;
+    return s->eri[(((size_t)p * n + q) * n + r) * n + t];
+}
+
+static int dn2(const or_sys *s, int p, int q)
+{
+    int d = 0;
+    for (int c = 0; c < 3; ++c) {
+        int x = s->nvec[3 * p + c] - s->nvec[3 * q + c];
+        d += x * x;
+    }
+    return d;
+}
+
+/* ---- Slater-Condon rules, diagonal ---- */
+double or_diag(const or_sys *s, const uint64_t *key)
+{
+    int occ[1024];
+    int n = occ_list(key, s->n_so, occ);
+    double e = 0.0;
+    if (s->kind == OR_HUBBARD) {
+        for (int p = 0; p < s->n_spatial; ++p)
+            if (getbit(key, 2 * p) && getbit(key, 2 * p + 1)) e = e + s->U;
+        return e;
+    }
+    if (s->kind == OR_UEG) {
+        for (int i = 0; i < n; ++i) e = e + s->eps[occ[i] >> 1];
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j)
+                if ((occ[i] & 1) == (occ[j] & 1)) e = e - s->vtab[dn2(s, occ[i] >> 1, occ[j] >> 1)];
+        return e;
+    }
+    for (int i = 0; i < n; ++i) {
+        int p = occ[i] >> 1;
+        e = e + s->h1[(size_t)p * s->n_spatial + p];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            int p = occ[i] >> 1, q = occ[j] >> 1;
+            double x = eri_at(s, p, p, q, q);
+            double y = ((occ[i] & 1) == (occ[j] & 1)) ? eri_at(s, p, q, q, p) : 0.0;
+            e = e + (x - y);
+        }
+    return e;
+}
+
+/* ---- single excitation P -> A out of ket D (A empty, P occupied in D) ---- */
+static double single_element(const or_sys *s, const uint64_t *D, int P, int A)
+{
+    double sign = parity_between(D, P, A);
+    if (s->kind == OR_HUBBARD) {
+        if ((P & 1) != (A & 1)) return 0.0;
+        int p = P >> 1, a = A >> 1, n = s->n_spatial;
+        int d = p > a ? p - a : a - p;
+        int nb = (d == 1) || (s->periodic && d == n - 1);
+        return nb ? (-s->t) * sign : 0.0;
+    }
+    if (s->kind == OR_UEG) return 0.0; /* momentum conservation */
+    if ((P & 1) != (A & 1)) return 0.0;
+    int occ[1024];
+    int n = occ_list(D, s->n_so, occ);
+    int p = P >> 1, a = A >> 1;
+    double v = s->h1[(size_t)a * s->n_spatial + p];
+    for (int i = 0; i < n; ++i) {
+        int Q = occ[i];
+        if (Q == P) continue;
+        int q = Q >> 1;
+        double x = eri_at(s, a, p, q, q);
+        double y = ((A & 1) == (Q & 1)) ? eri_at(s, a, q, q, p) : 0.0;
+        v = v + (x - y);
+    }
+    return sign * v;
+}
+
+/* <AB|PQ> - <AB|QP> in physicists' notation with spin-orbital indices */
+static double antisym(const or_sys *s, int A, int B, int P, int Q)
+{
+    int sa = A & 1, sb = B & 1, sp = P & 1, sq = Q & 1;
+    int a = A >> 1, b = B >> 1, p = P >> 1, q = Q >> 1;
+    if (s->kind == OR_HUBBARD) return 0.0; /* on-site U is diagonal only */
+    if (s->kind == OR_UEG) {
+        for (int c = 0; c < 3; ++c)
+            if (s->nvec[3 * a + c] + s->nvec[3 * b + c] != s->nvec[3 * p + c] + s->nvec[3 * q + c])
+                return 0.0;
+        double x = (sa == sp && sb == sq) ? s->vtab[dn2(s, p, a)] : 0.0;
+        double y = (sa == sq && sb == sp) ? s->vtab[dn2(s, q, a)] : 0.0;
+        return x - y;
+    }
+    double x = (sa == sp && sb == sq) ? eri_at(s, a, p, b, q) : 0.0;
+    double y = (sa == sq && sb == sp) ? eri_at(s, a, q, b, p) : 0.0;
+    return x - y;
+}
+
+/* ---- double excitation: holes P < Q, particles A < B, paired P->A, Q->B ---- */
+static double double_element(const or_sys *s, const uint64_t *D, int P, int Q, int A, int B)
+{
+    uint64_t tmp[OR_MAXW];
+    memcpy(tmp, D, sizeof(uint64_t) * s->W);
+    double s1 = parity_between(tmp, P, A);
+    clrbit(tmp, P);
+    setbit(tmp, A);
+    double s2 = parity_between(tmp, Q, B);
+    return (s1 * s2) * antisym(s, A, B, P, Q);
+}
+
+double or_hij(const or_sys *s, const uint64_t *bra, const uint64_t *ket)
+{
+    int nd = 0;
+    for (int i = 0; i < s->W; ++i) nd += __builtin_popcountll(bra[i] ^ ket[i]);
+    if (nd == 0) return or_diag(s, ket);
+    if (nd != 2 && nd != 4) return 0.0;
+    int holes[2], parts[2], nh = 0, np = 0;
+    for (int X = 0; X < s->n_so; ++X) {
+        int kb = getbit(ket, X), bb = getbit(bra, X);
+        if (kb && !bb) holes[nh++] = X;
+        if (bb && !kb) parts[np++] = X;
+    }
+    if (nh != np) return 0.0;
+    if (nh == 1) return single_element(s, ket, holes[0], parts[0]);
+    return double_element(s, ket, holes[0], holes[1], parts[0], parts[1]);
+}
+
+static void finish_sys(or_sys *s)
+{
+    s->H00 = or_diag(s, s->ref);
+}
+
+or_sys *or_hubbard_new(int n_sites, int periodic, double t, double U, int n_alpha, int n_beta)
+{
+    if (n_sites < 3 || 2 * n_sites > 64 * OR_MAXW || n_alpha > n_sites || n_beta > n_sites ||
+        n_alpha < 0 || n_beta < 0)
+        return NULL;
+    or_sys *s = sys_alloc(OR_HUBBARD, n_sites, n_alpha, n_beta);
+    s->periodic = periodic;
+    s->t = t;
+    s->U = U;
+    /* reference: alpha on sites 0,2,4,... then 1,3,...; beta on 1,3,5,... then 0,2,... */
+    int placed = 0;
+    for (int pass = 0; pass < 2 && placed < n_alpha; ++pass)
+        for (int p = pass; p < n_sites && placed < n_alpha; p += 2, ++placed) setbit(s->ref, 2 * p);
+    placed = 0;
+    for (int pass = 1; pass >= 0 && placed < n_beta; --pass)
+        for (int p = pass; p < n_sites && placed < n_beta; p += 2, ++placed) setbit(s->ref, 2 * p + 1);
+    finish_sys(s);
+    return s;
+}
+
+typedef struct { int n2, x, y, z; } pw_t;
+static int pw_cmp(const void *a, const void *b)
+{
+    const pw_t *u = (const pw_t *)a, *v = (const pw_t *)b;
+    if (u->n2 != v->n2) return u->n2 - v->n2;
+    if (u->x != v->x) return u->x - v->x;
+    if (u->y != v->y) return u->y - v->y;
+    return u->z - v->z;
+}
+
+/* Plane waves n in Z^3 with |n|^2 <= ecut in a simple-cubic box of side
+ * L = rs * cbrt(4 pi N / 3); kinetic (2pi/L)^2 |n|^2 / 2; Coulomb
+ * v(q) = 4 pi / (L^3 |k_q|^2), q = 0 excluded (paper Sec. 4.2, UEG). */
+or_sys *or_ueg_new(double rs, int ecut_n2, int n_alpha, int n_beta)
+{
+    int c = 0;
+    while ((c + 1) * (c + 1) <= ecut_n2) ++c;
+    int side = 2 * c + 1;
+    pw_t *pw = (pw_t *)malloc(sizeof(pw_t) * (size_t)side * side * side);
+    int m = 0;
+    for (int x = -c; x <= c; ++x)
+        for (int y = -c; y <= c; ++y)
+            for (int z = -c; z <= c; ++z) {
+                int n2 = x * x + y * y + z * z;
+                if (n2 <= ecut_n2) {
+                    pw[m].n2 = n2; pw[m].x = x; pw[m].y = y; pw[m].z = z;
+                    ++m;
+                }
+            }
+    qsort(pw, (size_t)m, sizeof(pw_t), pw_cmp);
+    if (2 * m > 64 * OR_MAXW || n_alpha > m || n_beta > m) { free(pw); return NULL; }
+    or_sys *s = sys_alloc(OR_UEG, m, n_alpha, n_beta);
+    s->rs = rs;
+    s->ecut = ecut_n2;
+    s->nvec = (int32_t *)malloc(sizeof(int32_t) * 3 * m);
+    s->eps = (double *)malloc(sizeof(double) * m);
+    for (int i = 0; i < m; ++i) {
+        s->nvec[3 * i] = pw[i].x; s->nvec[3 * i + 1] = pw[i].y; s->nvec[3 * i + 2] = pw[i].z;
+    }
+    double N = (double)(n_alpha + n_beta);
+    s->L = rs * cbrt((4.0 * M_PI * N) / 3.0);
+    double g = (2.0 * M_PI) / s->L;
+    s->k2 = g * g;
+    s->vc = (4.0 * M_PI) / ((s->L * s->L) * s->L);
+    for (int i = 0; i < m; ++i) s->eps[i] = (s->k2 * (double)pw[i].n2) * 0.5;
+    s->vlen = 4 * ecut_n2 + 1;
+    s->vtab = (double *)malloc(sizeof(double) * s->vlen);
+    s->vtab[0] = 0.0;
+    for (int d = 1; d < s->vlen; ++d) s->vtab[d] = s->vc / (s->k2 * (double)d);
+    s->gmax = 3 * c;
+    s->gdim = 2 * s->gmax + 1;
+    size_t gsz = (size_t)s->gdim * s->gdim * s->gdim;
+    s->grid = (int32_t *)malloc(sizeof(int32_t) * gsz);
+    for (size_t i = 0; i < gsz; ++i) s->grid[i] = -1;
+    for (int i = 0; i < m; ++i) {
+        size_t gi = ((size_t)(pw[i].x + s->gmax) * s->gdim + (pw[i].y + s->gmax)) * s->gdim +
+                    (pw[i].z + s->gmax);
+        s->grid[gi] = i;
+    }
+    free(pw);
+    for (int i = 0; i < n_alpha; ++i) setbit(s->ref, 2 * i);
+    for (int i = 0; i < n_beta; ++i) setbit(s->ref, 2 * i + 1);
+    finish_sys(s);
+    return s;
+}
+
+static int ueg_lookup(const or_sys *s, int x, int y, int z)
+{
+    if (x < -s->gmax || x > s->gmax || y < -s->gmax || y > s->gmax || z < -s->gmax || z > s->gmax)
+        return -1;
+    return s->grid[((size_t)(x + s->gmax) * s->gdim + (y + s->gmax)) * s->gdim + (z + s->gmax)];
+}
+
+/* Heat-bath tables for doubles (paper Sec. 2.1 and 4.1: heat-bath excitation
+ * generation): for each spin-orbital pair P < Q the allowed A < B (spin
+ * conserving, A,B not in {P,Q}) in lexicographic order with weight
+ * |<AB|PQ> - <AB|QP>|, and their sequential running sum. */
+static void build_heatbath(or_sys *s)
+{
+    int n = s->n_so;
+    s->hb_off = (int64_t *)calloc((size_t)n * n, sizeof(int64_t));
+    s->hb_cnt = (int32_t *)calloc((size_t)n * n, sizeof(int32_t));
+    s->hb_S = (double *)calloc((size_t)n * n, sizeof(double));
+    int64_t total = 0;
+    for (int P = 0; P < n; ++P)
+        for (int Q = P + 1; Q < n; ++Q) {
+            int cnt = 0;
+            for (int A = 0; A < n; ++A)
+                for (int B = A + 1; B < n; ++B) {
+                    if (A == P || A == Q || B == P || B == Q) continue;
+                    if ((A & 1) + (B & 1) != (P & 1) + (Q & 1)) continue;
+                    ++cnt;
+                }
+            s->hb_off[P * n + Q] = total;
+            s->hb_cnt[P * n + Q] = cnt;
+            total += cnt;
+        }
+    s->hb_n = total;
+    s->hb_A = (int32_t *)malloc(sizeof(int32_t) * (size_t)total);
+    s->hb_B = (int32_t *)malloc(sizeof(int32_t) * (size_t)total);
+    s->hb_cdf = (double *)malloc(sizeof(double) * (size_t)total);
+    for (int P = 0; P < n; ++P)
+        for (int Q = P + 1; Q < n; ++Q) {
+            int64_t e = s->hb_off[P * n + Q];
+            double c = 0.0;
+            for (int A = 0; A < n; ++A)
+                for (int B = A + 1; B < n; ++B) {
+                    if (A == P || A == Q || B == P || B == Q) continue;
+                    if ((A & 1) + (B & 1) != (P & 1) + (Q & 1)) continue;
+                    double w = fabs(antisym(s, A, B, P, Q));
+                    c = c + w;
+                    s->hb_A[e] = A;
+                    s->hb_B[e] = B;
+                    s->hb_cdf[e] = c;
+                    ++e;
+                }
+            s->hb_S[P * n + Q] = c;
+        }
+}
+
+or_sys *or_molecular_new(int n_orb, const double *h1, const double *eri, int n_alpha, int n_beta)
+{
+    if (n_orb <= 0 || 2 * n_orb > 64 * OR_MAXW || n_alpha > n_orb || n_beta > n_orb) return NULL;
+    or_sys *s = sys_alloc(OR_MOLECULAR, n_orb, n_alpha, n_beta);
+    size_t n2 = (size_t)n_orb * n_orb;
+    s->h1 = (double *)malloc(sizeof(double) * n2);
+    s->eri = (double *)malloc(sizeof(double) * n2 * n2);
+    memcpy(s->h1, h1, sizeof(double) * n2);
+    memcpy(s->eri, eri, sizeof(double) * n2 * n2);
+    for (int i = 0; i < n_alpha; ++i) setbit(s->ref, 2 * i);
+    for (int i = 0; i < n_beta; ++i) setbit(s->ref, 2 * i + 1);
+    build_heatbath(s);
+    finish_sys(s);
+    return s;
+}
+
+void or_sys_free(or_sys *s)
+{
+    if (!s) return;
+    free(s->nvec); free(s->eps); free(s->vtab); free(s->grid);
+    free(s->h1); free(s->eri);
+    free(s->hb_off); free(s->hb_cnt); free(s->hb_S); free(s->hb_A); free(s->hb_B); free(s->hb_cdf);
+    free(s);
+}
+
+void or_sys_info(const or_sys *s, int32_t *iout, double *dout)
+{
+    iout[0] = s->kind; iout[1] = s->n_spatial; iout[2] = s->n_so; iout[3] = s->W;
+    iout[4] = s->nel; iout[5] = s->na; iout[6] = s->nb;
+    dout[0] = s->H00; dout[1] = s->L; dout[2] = s->k2; dout[3] = s->vc;
+}
+
+void or_sys_reference(const or_sys *s, uint64_t *key) { memcpy(key, s->ref, sizeof(uint64_t) * s->W); }
+
+void or_ueg_orbitals(const or_sys *s, int32_t *nvec)
+{
+    if (s->nvec) memcpy(nvec, s->nvec, sizeof(int32_t) * 3 * s->n_spatial);
+}
+
+int64_t or_heatbath_size(const or_sys *s) { return s->hb_n; }
+
+/* ------------------------------------------------------------------------- */
+/* Excitation generators ("system-dependent", Sec. 2.4).                     */
+/* ------------------------------------------------------------------------- */
+
+/* Hubbard: uniform over the valid nearest-neighbour hops of either spin. */
+static int gen_hubbard(const or_sys *s, const uint64_t *D, const uint32_t *w, uint64_t *child,
+                       double *pgen, double *hij)
+{
+    int n = s->n_spatial;
+    /* candidate hops in the order: right-alpha, left-alpha, right-beta, left-beta, ascending site */
+    int from[256], to[256], nv = 0;
+    for (int sg = 0; sg < 2; ++sg)
+        for (int dir = 0; dir < 2; ++dir)
+            for (int p = 0; p < n; ++p) {
+                int q;
+                if (dir == 0) {
+                    if (p == n - 1 && !s->periodic) continue;
+                    q = (p + 1) % n;
+                } else {
+                    if (p == 0 && !s->periodic) continue;
+                    q = (p + n - 1) % n;
+                }
+                if (getbit(D, 2 * p + sg) && !getbit(D, 2 * q + sg)) {
+                    from[nv] = 2 * p + sg;
+                    to[nv] = 2 * q + sg;
+                    ++nv;
+                }
+            }
+    if (nv == 0) return 0;
+    uint32_t k = pick(w[0], (uint32_t)nv);
+    int P = from[k], A = to[k];
+    memcpy(child, D, sizeof(uint64_t) * s->W);
+    clrbit(child, P);
+    setbit(child, A);
+    *pgen = 1.0 / (double)nv;
+    *hij = single_element(s, D, P, A);
+    return 1;
+}
+
+/* pair index k in [0, C(N,2)) -> (i, j), i < j, lexicographic */
+static void unrank_pair(int N, uint32_t k, int *i, int *j)
+{
+    int a = 0;
+    uint32_t rem = k;
+    while (rem >= (uint32_t)(N - 1 - a)) { rem -= (uint32_t)(N - 1 - a); ++a; }
+    *i = a;
+    *j = a + 1 + (int)rem;
+}
+
+/* UEG: uniform pair of occupied spin-orbitals, uniform A, B by momentum. */
+static int gen_ueg(const or_sys *s, const uint64_t *D, const uint32_t *w, uint64_t *child,
+                   double *pgen, double *hij)
+{
+    int occ[1024];
+    int N = occ_list(D, s->n_so, occ);
+    uint32_t npairs = (uint32_t)(N * (N - 1) / 2);
+    int i, j;
+    unrank_pair(N, pick(w[0], npairs), &i, &j);
+    int P = occ[i], Q = occ[j];
+    int sP = P & 1, sQ = Q & 1, M = s->n_spatial, A, na;
+    if (sP == sQ) {
+        na = M;
+        A = 2 * (int)pick(w[1], (uint32_t)M) + sP;
+    } else {
+        na = 2 * M;
+        A = (int)pick(w[1], (uint32_t)(2 * M));
+    }
+    int sA = A & 1, sB = sP + sQ - sA;
+    int p = P >> 1, q = Q >> 1, a = A >> 1;
+    int bx = s->nvec[3 * p] + s->nvec[3 * q] - s->nvec[3 * a];
+    int by = s->nvec[3 * p + 1] + s->nvec[3 * q + 1] - s->nvec[3 * a + 1];
+    int bz = s->nvec[3 * p + 2] + s->nvec[3 * q + 2] - s->nvec[3 * a + 2];
+    int b = ueg_lookup(s, bx, by, bz);
+    if (b < 0) return 0;
+    int B = 2 * b + sB;
+    if (A == B || getbit(D, A) || getbit(D, B)) return 0;
+    int lo = A < B ? A : B, hi = A < B ? B : A;
+    memcpy(child, D, sizeof(uint64_t) * s->W);
+    clrbit(child, P); clrbit(child, Q); setbit(child, lo); setbit(child, hi);
+    *pgen = 2.0 / (double)((int64_t)npairs * na);
+    *hij = double_element(s, D, P, Q, lo, hi);
+    return 1;
+}
+
+/* Heat-bath doubles with uniform singles (paper Sec. 2.1 and 4.1). */
+static int gen_heatbath(const or_sys *s, double p_single, const uint64_t *D, const uint32_t *w,
+                        uint64_t *child, double *pgen, double *hij)
+{
+    int occ[1024];
+    int N = occ_list(D, s->n_so, occ);
+    int n = s->n_so;
+    double d = u53(w[0], w[1]);
+    if (d < p_single) {
+        int P = occ[pick(w[2], (uint32_t)N)];
+        int sg = P & 1;
+        int nel_s = sg ? s->nb : s->na;
+        int nvirt = s->n_spatial - nel_s;
+        if (nvirt <= 0) return 0;
+        uint32_t a = pick(w[3], (uint32_t)nvirt);
+        int A = -1;
+        uint32_t seen = 0;
+        for (int X = sg; X < n; X += 2)
+            if (!getbit(D, X)) {
+                if (seen == a) { A = X; break; }
+                ++seen;
+            }
+        if (A < 0) return 0;
+        memcpy(child, D, sizeof(uint64_t) * s->W);
+        clrbit(child, P);
+        setbit(child, A);
+        *pgen = p_single / (double)((int64_t)N * nvirt);
+        *hij = single_element(s, D, P, A);
+        return 1;
+    }
+    double T = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j) T = T + s->hb_S[occ[i] * n + occ[j]];
+    if (!(T > 0.0)) return 0;
+    double u = u53(w[4], w[5]);
+    double x = u * T, cum = 0.0;
+    int P = -1, Q = -1;
+    for (int i = 0; i < N && P < 0; ++i)
+        for (int j = i + 1; j < N; ++j) {
+            cum = cum + s->hb_S[occ[i] * n + occ[j]];
+            if (x < cum) { P = occ[i]; Q = occ[j]; break; }
+        }
+    if (P < 0) return 0;
+    int64_t off = s->hb_off[P * n + Q];
+    int cnt = s->hb_cnt[P * n + Q];
+    double S = s->hb_S[P * n + Q];
+    double y = u53(w[6], w[7]) * S;
+    int e = -1;
+    for (int k = 0; k < cnt; ++k)
+        if (y < s->hb_cdf[off + k]) { e = k; break; }
+    if (e < 0) return 0;
+    int A = s->hb_A[off + e], B = s->hb_B[off + e];
+    if (getbit(D, A) || getbit(D, B)) return 0;
+    double v = double_element(s, D, P, Q, A, B);
+    memcpy(child, D, sizeof(uint64_t) * s->W);
+    clrbit(child, P); clrbit(child, Q); setbit(child, A); setbit(child, B);
+    *pgen = ((1.0 - p_single) * fabs(antisym(s, A, B, P, Q))) / T;
+    *hij = v;
+    return 1;
+}
+
+int or_exgen(const or_sys *s, int exgen, double p_single, const uint64_t *key, const uint32_t *w,
+             uint64_t *child, double *pgen, double *hij)
+{
+    if (exgen == OR_EXGEN_HUB && s->kind == OR_HUBBARD) return gen_hubbard(s, key, w, child, pgen, hij);
+    if (exgen == OR_EXGEN_UEG && s->kind == OR_UEG) return gen_ueg(s, key, w, child, pgen, hij);
+    if (exgen == OR_EXGEN_HEATBATH && s->kind == OR_MOLECULAR)
+        return gen_heatbath(s, p_single, key, w, child, pgen, hij);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The run: main list, one projector iteration per step.                     */
+/* ------------------------------------------------------------------------- */
+struct or_run {
+    const or_sys *s;
+    or_qmc q;
+    int W;
+    int64_t n, cap;
+    uint64_t *keys;
+    int32_t *pops;
+    double *kdiag;
+    int32_t *dslot;
+    double S;
+    int vary;
+    int64_t nprev, t;
+    int64_t cu, thr, target_units;
+    uint32_t rkey[2];
+    or_estimators est;
+    /* spawned walkers of the last iteration */
+    int64_t ns, scap;
+    uint64_t *skeys;
+    int32_t *samps;
+    uint8_t *sinit;
+    /* deterministic space */
+    int ss_active;
+    int64_t nd;
+    uint64_t *dkeys;     /* D order */
+    double *kdd;         /* nd x nd */
+    uint64_t *dsorted;   /* sorted copy of the keys */
+    int32_t *dsorted_ix; /* D index of each sorted key */
+    double *last_y;
+};
+
+static void draw(const or_run *r, uint32_t tag, uint32_t attempt, uint32_t t, uint64_t h,
+                 uint32_t out[4])
+{
+    uint32_t ctr[4] = {(tag << 28) | attempt, t, (uint32_t)h, (uint32_t)(h >> 32)};
+    or_philox4x32_10(ctr, r->rkey, out);
+}
+
+/* stochastic rounding of m >= 0 with uniform u: floor(m) + [u < m - floor(m)] */
+static int64_t sround(double m, double u)
+{
+    double f = floor(m);
+    int64_t k = (int64_t)f;
+    if (u < m - f) k += 1;
+    return k;
+}
+
+static void list_reserve(or_run *r, int64_t need)
+{
+    if (need <= r->cap) return;
+    int64_t c = r->cap ? r->cap : 1024;
+    while (c < need) c *= 2;
+    r->keys = (uint64_t *)realloc(r->keys, sizeof(uint64_t) * (size_t)c * r->W);
+    r->pops = (int32_t *)realloc(r->pops, sizeof(int32_t) * (size_t)c);
+    r->kdiag = (double *)realloc(r->kdiag, sizeof(double) * (size_t)c);
+    r->dslot = (int32_t *)realloc(r->dslot, sizeof(int32_t) * (size_t)c);
+    r->cap = c;
+}
+
+static void push_spawn(or_run *r, const uint64_t *key, int32_t amp, uint8_t init)
+{
+    if (r->ns == r->scap) {
+        r->scap = r->scap ? 2 * r->scap : 4096;
+        r->skeys = (uint64_t *)realloc(r->skeys, sizeof(uint64_t) * (size_t)r->scap * r->W);
+        r->samps = (int32_t *)realloc(r->samps, sizeof(int32_t) * (size_t)r->scap);
+        r->sinit = (uint8_t *)realloc(r->sinit, (size_t)r->scap);
+    }
+    memcpy(r->skeys + (size_t)r->ns * r->W, key, sizeof(uint64_t) * r->W);
+    r->samps[r->ns] = amp;
+    r->sinit[r->ns] = init;
+    r->ns++;
+}
+
+static int64_t dspace_find(const or_run *r, const uint64_t *key)
+{
+    int64_t lo = 0, hi = r->nd;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        int c = key_cmp(r->dsorted + (size_t)mid * r->W, key, r->W);
+        if (c == 0) return r->dsorted_ix[mid];
+        if (c < 0) lo = mid + 1; else hi = mid;
+    }
+    return -1;
+}
+
+static int64_t n_attempts(const or_run *r, int32_t pop)
+{
+    int64_t a = pop < 0 ? -(int64_t)pop : (int64_t)pop;
+    int b = r->q.fixed_point_bits;
+    if (b == 0) return a;
+    return (a + ((int64_t)1 << b) - 1) >> b;
+}
+
+static int is_reference(const or_run *r, const uint64_t *key) { return key_cmp(key, r->s->ref, r->W) == 0; }
+
+/* Fixed-point accumulation of one FP64 term at resolution 2^-64, split into
+ * four 32-bit limbs; the limb sums are exact and order independent. */
+static void acc_term(int64_t limbs[4], double x)
+{
+    if (x == 0.0) return;
+    int neg = x < 0.0;
+    double a = neg ? -x : x;
+    unsigned __int128 X = (unsigned __int128)(a * 0x1p64);
+    for (int k = 0; k < 4; ++k) {
+        int64_t l = (int64_t)(uint32_t)(X >> (32 * k));
+        limbs[k] += neg ? -l : l;
+    }
+}
+
+static double limbs_value(const int64_t limbs[4])
+{
+    __int128 tot = 0;
+    for (int k = 0; k < 4; ++k) tot += (__int128)limbs[k] * ((__int128)1 << (32 * k));
+    return (double)tot * 0x1p-64;
+}
+
+/* Projected energy (tutorial appendix): numerator sum_{j != 0} H_0j N_j
+ * over the determinants at most doubly excited from D_0; N_0 as denominator. */
+static void compute_estimators(or_run *r)
+{
+    or_estimators *e = &r->est;
+    int64_t nw = 0, n0 = 0;
+    int64_t limbs[4] = {0, 0, 0, 0};
+    for (int64_t i = 0; i < r->n; ++i) {
+        const uint64_t *k = r->keys + (size_t)i * r->W;
+        int32_t p = r->pops[i];
+        nw += p < 0 ? -(int64_t)p : p;
+        if (is_reference(r, k)) { n0 = p; continue; }
+        int nd = 0;
+        for (int w = 0; w < r->W; ++w) nd += __builtin_popcountll(k[w] ^ r->s->ref[w]);
+        if (nd != 2 && nd != 4) continue;
+        double h = or_hij(r->s, r->s->ref, k);
+        acc_term(limbs, h * (double)p);
+    }
+    e->iteration = r->t;
+    e->n_walkers_units = nw;
+    e->n_occupied = r->n;
+    e->ref_pop_units = n0;
+    memcpy(e->num_limbs, limbs, sizeof(limbs));
+    double num = limbs_value(limbs);
+    double scale = ldexp(1.0, -r->q.fixed_point_bits);
+    e->proj_numerator = num * scale;
+    e->proj_energy = n0 != 0 ? num / (double)n0 : NAN;
+    e->shift = r->S;
+    e->vary_shift = r->vary;
+    e->e_ref = r->s->H00;
+}
+
+or_run *or_run_new(const or_sys *s, const or_qmc *q)
+{
+    if (!s || !q || !(q->tau > 0.0) || q->fixed_point_bits < 0 || q->fixed_point_bits > 20 ||
+        q->shift_period <= 0)
+        return NULL;
+    if (q->excit_gen == OR_EXGEN_HUB && s->kind != OR_HUBBARD) return NULL;
+    if (q->excit_gen == OR_EXGEN_UEG && s->kind != OR_UEG) return NULL;
+    if (q->excit_gen == OR_EXGEN_HEATBATH && s->kind != OR_MOLECULAR) return NULL;
+    or_run *r = (or_run *)calloc(1, sizeof(or_run));
+    r->s = s;
+    r->q = *q;
+    r->W = s->W;
+    double scale = ldexp(1.0, q->fixed_point_bits);
+    r->cu = q->fixed_point_bits ? (int64_t)floor(q->spawn_cutoff * scale + 0.5) : 0;
+    r->thr = (int64_t)floor(q->initiator_threshold * scale);
+    r->rkey[0] = (uint32_t)q->seed;
+    r->rkey[1] = (uint32_t)(q->seed >> 32) ^ (uint32_t)q->replica_id;
+    list_reserve(r, 1);
+    memcpy(r->keys, s->ref, sizeof(uint64_t) * r->W);
+    r->pops[0] = (int32_t)floor(q->init_pop * scale + 0.5);
+    r->kdiag[0] = 0.0;
+    r->dslot[0] = -1;
+    r->n = 1;
+    r->S = q->initial_shift;
+    compute_estimators(r);
+    return r;
+}
+
+void or_run_free(or_run *r)
+{
+    if (!r) return;
+    free(r->keys); free(r->pops); free(r->kdiag); free(r->dslot);
+    free(r->skeys); free(r->samps); free(r->sinit);
+    free(r->dkeys); free(r->kdd); free(r->dsorted); free(r->dsorted_ix); free(r->last_y);
+    free(r);
+}
+
+/* ---- one spawning attempt (Sec. 2.4 "spawning"; Sec. 2.1 real weights) ---- */
+static int spawn_attempt(or_run *r, const uint64_t *key, uint64_t h, int32_t n0, int64_t nat, int64_t k,
+                         uint8_t init, int parent_in_d)
+{
+    const or_sys *s = r->s;
+    uint32_t w[8], rnd[4];
+    uint32_t t = (uint32_t)r->t;
+    draw(r, TAG_SELECT, (uint32_t)k, t, h, w);
+    draw(r, TAG_SELECT2, (uint32_t)k, t, h, w + 4);
+    uint64_t child[OR_MAXW] = {0};
+    double pgen = 0.0, hij = 0.0;
+    if (!or_exgen(s, r->q.excit_gen, r->q.p_single, key, w, child, &pgen, &hij)) return OR_OK;
+    if (hij == 0.0) return OR_OK;
+    if (parent_in_d && dspace_find(r, child) >= 0) return OR_OK;
+    double ah = fabs(hij);
+    double m;
+    if (r->q.fixed_point_bits == 0) {
+        m = (r->q.tau * ah) / pgen;
+    } else {
+        double an = (double)(n0 < 0 ? -(int64_t)n0 : (int64_t)n0);
+        m = (((r->q.tau * ah) / pgen) * an) / (double)nat;
+    }
+    draw(r, TAG_SPAWN_ROUND, (uint32_t)k, t, h, rnd);
+    double u = u53(rnd[0], rnd[1]);
+    if (!(m < 0x1p31)) return OR_EOVERFLOW;
+    int64_t kk;
+    if (r->q.fixed_point_bits != 0 && m < (double)r->cu)
+        kk = (u * (double)r->cu < m) ? r->cu : 0;
+    else
+        kk = sround(m, u);
+    if (kk == 0) return OR_OK;
+    if (kk > 2147483647) return OR_EOVERFLOW;
+    int sh = hij > 0.0 ? 1 : -1;
+    int sn = n0 > 0 ? 1 : -1;
+    int32_t amp = (int32_t)(-(sh * sn) * kk);
+    push_spawn(r, child, amp, init);
+    return OR_OK;
+}
+
+typedef struct { const uint64_t *keys; int W; } sort_ctx_t;
+static sort_ctx_t g_sort;
+static int idx_cmp(const void *a, const void *b)
+{
+    int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    int c = key_cmp(g_sort.keys + (size_t)i * g_sort.W, g_sort.keys + (size_t)j * g_sort.W, g_sort.W);
+    if (c) return c;
+    return (i > j) - (i < j);
+}
+
+/* Deterministic projection on D (Sec. 2.1 semi-stochastic propagation):
+ * y_i = sum_j K_ij n_j with 64 interleaved partial sums (j = l mod 64) each
+ * taken in increasing j, then combined by a fixed halving tree. */
+static double det_row(const double *row, const double *c, int64_t nd)
+{
+    double part[64];
+    for (int l = 0; l < 64; ++l) part[l] = 0.0;
+    for (int64_t j = 0; j < nd; ++j) part[j & 63] = part[j & 63] + row[j] * c[j];
+    for (int step = 32; step >= 1; step >>= 1)
+        for (int l = 0; l < step; ++l) part[l] = part[l] + part[l + step];
+    return part[0];
+}
+
+static struct { const or_run *r; } g_top;
+static int top_cmp(const void *a, const void *b)
+{
+    const or_run *r = g_top.r;
+    int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    int64_t ai = r->pops[i] < 0 ? -(int64_t)r->pops[i] : r->pops[i];
+    int64_t aj = r->pops[j] < 0 ? -(int64_t)r->pops[j] : r->pops[j];
+    if (ai != aj) return ai > aj ? -1 : 1;
+    return key_cmp(r->keys + (size_t)i * r->W, r->keys + (size_t)j * r->W, r->W);
+}
+
+static void select_detspace(or_run *r)
+{
+    int64_t nd = r->q.ss_size < r->n ? r->q.ss_size : r->n;
+    /* order: |n| descending, then key ascending (a total order: keys are distinct) */
+    int64_t *ix = (int64_t *)malloc(sizeof(int64_t) * (size_t)(r->n ? r->n : 1));
+    for (int64_t i = 0; i < r->n; ++i) ix[i] = i;
+    g_top.r = r;
+    qsort(ix, (size_t)r->n, sizeof(int64_t), top_cmp);
+    r->nd = nd;
+    r->dkeys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nd ? nd : 1) * r->W);
+    r->kdd = (double *)malloc(sizeof(double) * (size_t)(nd ? nd * nd : 1));
+    r->last_y = (double *)calloc((size_t)(nd ? nd : 1), sizeof(double));
+    for (int64_t d = 0; d < nd; ++d) {
+        memcpy(r->dkeys + (size_t)d * r->W, r->keys + (size_t)ix[d] * r->W, sizeof(uint64_t) * r->W);
+        r->dslot[ix[d]] = (int32_t)d;
+    }
+    for (int64_t d = 0; d < nd; ++d)
+        for (int64_t e = 0; e < nd; ++e) {
+            double v;
+            if (d == e)
+                v = r->kdiag[ix[d]];
+            else
+                v = or_hij(r->s, r->dkeys + (size_t)d * r->W, r->dkeys + (size_t)e * r->W);
+            r->kdd[d * nd + e] = v;
+        }
+    /* sorted copy for membership tests */
+    g_sort.keys = r->dkeys;
+    g_sort.W = r->W;
+    int64_t *sx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd ? nd : 1));
+    for (int64_t d = 0; d < nd; ++d) sx[d] = d;
+    qsort(sx, (size_t)nd, sizeof(int64_t), idx_cmp);
+    r->dsorted = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nd ? nd : 1) * r->W);
+    r->dsorted_ix = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nd ? nd : 1));
+    for (int64_t d = 0; d < nd; ++d) {
+        memcpy(r->dsorted + (size_t)d * r->W, r->dkeys + (size_t)sx[d] * r->W, sizeof(uint64_t) * r->W);
+        r->dsorted_ix[d] = (int32_t)sx[d];
+    }
+    free(sx);
+    free(ix);
+    r->ss_active = 1;
+}
+
+static int step_once(or_run *r)
+{
+    const or_sys *s = r->s;
+    int W = r->W;
+    r->t += 1;
+    uint32_t t = (uint32_t)r->t;
+    int64_t n = r->n;
+    int64_t flips = 0;
+    /* 1. spawning from the start-of-iteration populations */
+    r->ns = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t n0 = r->pops[i];
+        if (n0 == 0) continue;
+        const uint64_t *key = r->keys + (size_t)i * W;
+        if (r->q.fixed_point_bits == 0 && (n0 >= (1 << 28) || n0 <= -(1 << 28))) return OR_EOVERFLOW;
+        uint64_t h = or_hash64(key, W);
+        int64_t nat = n_attempts(r, n0);
+        int64_t an = n0 < 0 ? -(int64_t)n0 : n0;
+        int pin_d = r->ss_active && r->dslot[i] >= 0;
+        uint8_t init = (uint8_t)(an > r->thr || is_reference(r, key) || pin_d);
+        for (int64_t k = 0; k < nat; ++k) {
+            int st = spawn_attempt(r, key, h, n0, nat, k, init, pin_d);
+            if (st) return st;
+        }
+    }
+    /* 2. death/cloning (Sec. 2.4 "death"; shift as diagonal offset, Sec. 2.1),
+     *    3. deterministic projection for D entries; both from start-of-iteration values */
+    int64_t *newpop = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    double *cvec = NULL;
+    if (r->ss_active) {
+        cvec = (double *)calloc((size_t)(r->nd ? r->nd : 1), sizeof(double));
+        for (int64_t i = 0; i < n; ++i)
+            if (r->dslot[i] >= 0) cvec[r->dslot[i]] = (double)r->pops[i];
+        for (int64_t d = 0; d < r->nd; ++d) r->last_y[d] = det_row(r->kdd + d * r->nd, cvec, r->nd);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t n0 = r->pops[i];
+        const uint64_t *key = r->keys + (size_t)i * W;
+        uint64_t h = or_hash64(key, W);
+        uint32_t rnd[4];
+        if (r->ss_active && r->dslot[i] >= 0) {
+            int64_t d = r->dslot[i];
+            double delta = (-r->q.tau) * (r->last_y[d] - r->S * (double)n0);
+            draw(r, TAG_SEMISTOCH, 0, t, h, rnd);
+            double u = u53(rnd[0], rnd[1]);
+            if (!(fabs(delta) < 0x1p40)) { free(newpop); free(cvec); return OR_EOVERFLOW; }
+            int64_t k = delta >= 0.0 ? sround(delta, u) : -sround(-delta, u);
+            newpop[i] = (int64_t)n0 + k;
+            continue;
+        }
+        if (n0 == 0) { newpop[i] = 0; continue; }
+        double an = (double)(n0 < 0 ? -(int64_t)n0 : (int64_t)n0);
+        double m = (r->q.tau * (r->kdiag[i] - r->S)) * an;
+        draw(r, TAG_DEATH, 0, t, h, rnd);
+        double u = u53(rnd[0], rnd[1]);
+        if (!(fabs(m) < 0x1p40)) { free(newpop); free(cvec); return OR_EOVERFLOW; }
+        int64_t k = m >= 0.0 ? sround(m, u) : -sround(-m, u);
+        int64_t sg = n0 > 0 ? 1 : -1;
+        int64_t v = (int64_t)n0 - sg * k;
+        if ((v > 0 && n0 < 0) || (v < 0 && n0 > 0)) ++flips;
+        newpop[i] = v;
+    }
+    free(cvec);
+    /* 4. annihilation (Sec. 2.4; appendix "Parallelization"): sort the spawned
+     *    walkers, combine those on the same determinant, merge into the main list */
+    int64_t ns = r->ns;
+    int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+    for (int64_t i = 0; i < ns; ++i) ord[i] = i;
+    g_sort.keys = r->skeys;
+    g_sort.W = W;
+    qsort(ord, (size_t)ns, sizeof(int64_t), idx_cmp);
+    int64_t nu = 0;
+    uint64_t *ukeys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(ns > 0 ? ns : 1) * W);
+    int64_t *usum = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+    uint8_t *uflag = (uint8_t *)malloc((size_t)(ns > 0 ? ns : 1));
+    for (int64_t i = 0; i < ns; ++i) {
+        const uint64_t *k = r->skeys + (size_t)ord[i] * W;
+        if (nu > 0 && key_cmp(ukeys + (size_t)(nu - 1) * W, k, W) == 0) {
+            usum[nu - 1] += r->samps[ord[i]];
+            uflag[nu - 1] |= r->sinit[ord[i]];
+        } else {
+            memcpy(ukeys + (size_t)nu * W, k, sizeof(uint64_t) * W);
+            usum[nu] = r->samps[ord[i]];
+            uflag[nu] = r->sinit[ord[i]];
+            ++nu;
+        }
+    }
+    free(ord);
+    int64_t cap2 = n + nu + 1;
+    uint64_t *nk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)cap2 * W);
+    int32_t *np = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap2);
+    double *nkd = (double *)malloc(sizeof(double) * (size_t)cap2);
+    int32_t *nds = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap2);
+    int64_t a = 0, b = 0, o = 0, rejected = 0, rejected_sum = 0, death_sum = 0, spawn_sum = 0;
+    for (int64_t i = 0; i < n; ++i) death_sum += newpop[i];
+    for (int64_t i = 0; i < ns; ++i) spawn_sum += r->samps[i];
+    int status = OR_OK;
+    while (a < n || b < nu) {
+        int c;
+        if (a >= n) c = 1;
+        else if (b >= nu) c = -1;
+        else c = key_cmp(r->keys + (size_t)a * W, ukeys + (size_t)b * W, W);
+        int64_t v;
+        if (c <= 0) {
+            v = newpop[a];
+            if (c == 0) { v += usum[b]; ++b; }
+            if (v > 2147483647 || v < -2147483647) status = OR_EOVERFLOW;
+            if (v != 0 || r->dslot[a] >= 0) {
+                memcpy(nk + (size_t)o * W, r->keys + (size_t)a * W, sizeof(uint64_t) * W);
+                np[o] = (int32_t)v;
+                nkd[o] = r->kdiag[a];
+                nds[o] = r->dslot[a];
+                ++o;
+            }
+            ++a;
+        } else {
+            /* initiator rule (Sec. 2.1): a new determinant only from an initiator parent */
+            v = usum[b];
+            int accept = (!r->q.initiator || uflag[b]) && v != 0;
+            if (accept) {
+                if (v > 2147483647 || v < -2147483647) status = OR_EOVERFLOW;
+                memcpy(nk + (size_t)o * W, ukeys + (size_t)b * W, sizeof(uint64_t) * W);
+                np[o] = (int32_t)v;
+                nkd[o] = or_diag(s, ukeys + (size_t)b * W) - s->H00;
+                nds[o] = -1;
+                ++o;
+            } else {
+                rejected += v < 0 ? -v : v;
+                rejected_sum += v;
+            }
+            ++b;
+        }
+    }
+    free(newpop); free(ukeys); free(usum); free(uflag);
+    if (status != OR_OK) { free(nk); free(np); free(nkd); free(nds); return status; }
+    free(r->keys); free(r->pops); free(r->kdiag); free(r->dslot);
+    r->keys = nk; r->pops = np; r->kdiag = nkd; r->dslot = nds;
+    r->n = o;
+    r->cap = cap2;
+    /* 5. estimators on the new list */
+    compute_estimators(r);
+    r->est.n_spawned = ns;
+    r->est.n_sign_flips = flips;
+    r->est.n_rejected_units = rejected;
+    r->est.n_spawn_events = nu;
+    r->est.death_sum = death_sum;
+    r->est.spawn_sum = spawn_sum;
+    r->est.rejected_sum = rejected_sum;
+    /* 6. shift update every A iterations (Sec. 2.1: diagonal energy offset) */
+    if (r->t % r->q.shift_period == 0) {
+        int64_t nw = r->est.n_walkers_units;
+        double target = r->q.target_population * ldexp(1.0, r->q.fixed_point_bits);
+        if (!r->vary) {
+            if ((double)nw >= target) { r->vary = 1; r->nprev = nw; }
+        } else {
+            double c = r->q.shift_damping / ((double)r->q.shift_period * r->q.tau);
+            double ratio = (double)nw / (double)r->nprev;
+            r->S = r->S - c * log(ratio);
+            r->nprev = nw;
+        }
+        r->est.shift = r->S;
+        r->est.vary_shift = r->vary;
+    }
+    /* deterministic space chosen from the most highly weighted determinants */
+    if (r->q.ss_size > 0 && !r->ss_active && r->t >= r->q.ss_start_iteration) select_detspace(r);
+    return OR_OK;
+}
+
+int or_run_step(or_run *r, int n_iter)
+{
+    for (int i = 0; i < n_iter; ++i) {
+        int st = step_once(r);
+        if (st) { r->est.status = st; return st; }
+    }
+    return OR_OK;
+}
+
+void or_run_estimators(const or_run *r, or_estimators *out) { *out = r->est; }
+int64_t or_run_size(const or_run *r) { return r->n; }
+
+void or_run_export(const or_run *r, uint64_t *keys, int32_t *pops)
+{
+    memcpy(keys, r->keys, sizeof(uint64_t) * (size_t)r->n * r->W);
+    memcpy(pops, r->pops, sizeof(int32_t) * (size_t)r->n);
+}
+
+int or_run_import(or_run *r, const uint64_t *keys, const int32_t *pops, int64_t n, double shift,
+                  int64_t iteration, int32_t vary, int64_t n_prev)
+{
+    int W = r->W;
+    int64_t *ix = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    for (int64_t i = 0; i < n; ++i) ix[i] = i;
+    g_sort.keys = keys;
+    g_sort.W = W;
+    qsort(ix, (size_t)n, sizeof(int64_t), idx_cmp);
+    for (int64_t i = 1; i < n; ++i)
+        if (key_cmp(keys + (size_t)ix[i] * W, keys + (size_t)ix[i - 1] * W, W) == 0) {
+            free(ix);
+            return OR_EINVAL;
+        }
+    free(r->keys); free(r->pops); free(r->kdiag); free(r->dslot);
+    r->keys = NULL; r->pops = NULL; r->kdiag = NULL; r->dslot = NULL; r->cap = 0;
+    list_reserve(r, n ? n : 1);
+    int64_t o = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (pops[ix[i]] == 0) continue;
+        memcpy(r->keys + (size_t)o * W, keys + (size_t)ix[i] * W, sizeof(uint64_t) * W);
+        r->pops[o] = pops[ix[i]];
+        r->kdiag[o] = or_diag(r->s, keys + (size_t)ix[i] * W) - r->s->H00;
+        r->dslot[o] = -1;
+        ++o;
+    }
+    free(ix);
+    r->n = o;
+    r->S = shift;
+    r->t = iteration;
+    r->vary = vary;
+    r->nprev = n_prev;
+    free(r->dkeys); free(r->kdd); free(r->dsorted); free(r->dsorted_ix); free(r->last_y);
+    r->dkeys = NULL; r->kdd = NULL; r->dsorted = NULL; r->dsorted_ix = NULL; r->last_y = NULL;
+    r->ss_active = 0;
+    r->nd = 0;
+    compute_estimators(r);
+    if (r->q.ss_size > 0 && r->t >= r->q.ss_start_iteration) select_detspace(r);
+    return OR_OK;
+}
+
+int64_t or_run_n_spawns(const or_run *r) { return r->ns; }
+
+void or_run_spawns(const or_run *r, uint64_t *keys, int32_t *amps, uint8_t *init)
+{
+    memcpy(keys, r->skeys, sizeof(uint64_t) * (size_t)r->ns * r->W);
+    memcpy(amps, r->samps, sizeof(int32_t) * (size_t)r->ns);
+    memcpy(init, r->sinit, (size_t)r->ns);
+}
+
+int64_t or_run_detspace(const or_run *r, uint64_t *keys)
+{
+    if (keys && r->nd) memcpy(keys, r->dkeys, sizeof(uint64_t) * (size_t)r->nd * r->W);
+    return r->nd;
+}
+
+void or_run_last_projection(const or_run *r, double *y)
+{
+    if (r->nd) memcpy(y, r->last_y, sizeof(double) * (size_t)r->nd);
+}
