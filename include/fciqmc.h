@@ -1,0 +1,213 @@
+/*
+ * fciqmc.h -- C ABI of the MI355X FCIQMC hot path (one GPU, HIP, gfx950).
+ *
+ * One projector iteration of full configuration interaction quantum Monte
+ * Carlo over a list of occupied Slater determinants held as bit strings with
+ * signed fixed-point walker populations (Spencer et al., "The HANDE-QMC
+ * project", arXiv:1811.11679):
+ *   c_i(tau + dtau) = c_i(tau) - dtau sum_j <D_i|H - S|D_j> c_j(tau)
+ * (Sec. 2.1, eq. fciqmc, with the shift S as a diagonal energy offset),
+ * sampled by spawning, death/cloning and annihilation (Sec. 2.4), with real
+ * fixed-precision weights (Sec. 2.1 and the weights bibnote), the initiator
+ * approximation (Sec. 2.1), semi-stochastic propagation in a deterministic
+ * space (Sec. 2.1; tutorial appendix, semi_stoch block), the projected-energy
+ * estimator (tutorial appendix) and the sorted main list / spawned list of the
+ * appendix "Parallelization".
+ *
+ * Conventions shared by every call:
+ *  - Every function returns fq_status: 0 on success, a negative code on error.
+ *    fq_last_error() returns a text for the last error of a context.
+ *  - Host pointers (integral arrays, walker keys and populations) belong to
+ *    the caller and are only read (or written, for export) during the call.
+ *  - The device workspace belongs to the caller, must hold at least
+ *    fq_workspace_bytes() bytes, be 256-byte aligned and outlive the context.
+ *  - The HIP stream belongs to the caller; every device operation of a context
+ *    is enqueued on it. Calls on one context must not run concurrently.
+ *  - Bit strings: spin-orbital P = 2p + sigma (sigma 0 = alpha, 1 = beta) is bit
+ *    P % 64 of 64-bit word P / 64; word 0 is least significant; a key holds W
+ *    = ceil(n_spin_orbitals / 64) words, W in {1, 2, 4, 8} (3 is padded to 4,
+ *    5..7 to 8). Keys are compared as unsigned big integers.
+ *  - Populations are int32 multiples of 2^-b walkers (b = fixed_point_bits;
+ *    b = 0 gives integer walkers).
+ *
+ * Errors: FQ_EINVAL (bad arguments; nothing is changed), FQ_ECAPACITY (a list
+ * would exceed its capacity), FQ_EOVERFLOW (a population or spawn would exceed
+ * int32), FQ_EHIP (a HIP runtime call failed), FQ_ESTATE (call out of order).
+ * After FQ_ECAPACITY or FQ_EOVERFLOW from fq_step the walker lists are those
+ * at the start of the failing iteration and the context can be exported.
+ */
+#ifndef FCIQMC_H
+#define FCIQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fq_status;
+#define FQ_OK 0
+#define FQ_EINVAL (-1)
+#define FQ_ECAPACITY (-2)
+#define FQ_EOVERFLOW (-3)
+#define FQ_EHIP (-4)
+#define FQ_ESTATE (-5)
+
+/* model systems (paper Sec. 4.2: Hubbard, uniform electron gas) and molecular
+ * integrals (Sec. 3.1 and the tutorial appendix: h_pq and (pq|rs)) */
+#define FQ_HUBBARD_REAL 1
+#define FQ_UEG 2
+#define FQ_MOLECULAR 3
+
+/* excitation generators (Sec. 2.4 "system dependent"; heat bath, Sec. 2.1) */
+#define FQ_EXGEN_HUB_UNIFORM 1
+#define FQ_EXGEN_UEG_UNIFORM 2
+#define FQ_EXGEN_HEATBATH_UNIFORM_SINGLES 3
+
+#define FQ_SS_FP64 0       /* deterministic projection in FP64, fixed order */
+#define FQ_SS_SPLIT_BF16 1 /* BF16 x3 split products, FP32 accumulation (MFMA) */
+
+/* A system. Hubbard: 1D chain of n_sites, periodic or open, hopping t,
+ * on-site U, real-space basis. UEG: plane waves n in Z^3 with |n|^2 <= ecut_n2
+ * in a cubic box of side L = rs (4 pi N / 3)^(1/3), Coulomb 4 pi / (L^3 k^2),
+ * k = 0 term excluded. Molecular: n_orb spatial orbitals, h1[p*n+q] and
+ * eri[((p*n+q)*n+r)*n+s] = (pq|rs) in chemists' notation, both real and
+ * symmetric, copied during fq_init_system. */
+typedef struct {
+    int32_t kind;
+    int32_t n_alpha, n_beta;
+    int32_t n_sites, periodic;
+    double t, U;
+    double rs;
+    int32_t ecut_n2;
+    int32_t n_orb;
+    const double *h1;
+    const double *eri;
+} fq_system;
+
+/* Run parameters, as the paper's qmc table (tutorial appendix). */
+typedef struct {
+    double tau;                 /* time step dtau */
+    uint64_t rng_seed;          /* Philox key = (seed_lo, seed_hi ^ replica_id) */
+    int32_t replica_id;
+    double init_pop;            /* walkers placed on the reference at start */
+    double target_population;   /* walkers; the shift varies once it is reached */
+    int32_t shift_period;       /* A: iterations between shift updates (mc_cycles) */
+    double shift_damping;       /* zeta */
+    double initial_shift;       /* S at start, relative to H_00 */
+    int32_t excit_gen;          /* FQ_EXGEN_* matching the system */
+    double p_single;            /* heat-bath generator: probability of a single */
+    int32_t initiator;          /* 1: initiator approximation on */
+    double initiator_threshold; /* n_add, walkers (strict >) */
+    int32_t fixed_point_bits;   /* b; 0 = integer walkers */
+    double spawn_cutoff;        /* walkers; real mode only */
+} fq_qmc;
+
+/* Semi-stochastic block (tutorial appendix, semi_stoch = {size,
+ * start_iteration, space = "high"}): the size most highly weighted
+ * determinants at the end of iteration start_iteration form D. */
+typedef struct {
+    int32_t size;
+    int32_t start_iteration;
+    int32_t precision; /* FQ_SS_FP64 or FQ_SS_SPLIT_BF16 */
+} fq_semistoch;
+
+/* Estimators of one iteration of one instance (tutorial appendix: shift,
+ * number of walkers, projected-energy numerator sum_j H_0j N_j and
+ * denominator N_0). Walker quantities are in units of 2^-b walkers except
+ * proj_numerator, which is in walkers. */
+typedef struct {
+    int64_t iteration;
+    int64_t n_walkers_units;  /* sum |n_i| */
+    int64_t n_occupied;       /* determinants in the main list */
+    int64_t n_spawned;        /* spawn events this iteration */
+    int64_t ref_pop_units;    /* n_0 */
+    int64_t n_sign_flips;     /* death steps that changed a population's sign */
+    int64_t n_rejected_units; /* sum |A| of segments refused by the initiator rule */
+    int64_t n_spawn_events;   /* distinct spawned determinants */
+    int64_t death_sum, spawn_sum, rejected_sum; /* signed unit totals */
+    int32_t vary_shift, status;
+    double shift;             /* relative to H_00 */
+    double proj_numerator;    /* walkers x Hartree */
+    double proj_energy;       /* numerator / N_0 (correlation energy); NaN if N_0 = 0 */
+    double e_ref;             /* H_00 */
+    int64_t num_limbs[4];     /* exact fixed-point numerator (2^-64 resolution), units */
+} fq_estimators_t;
+
+typedef struct fq_ctx fq_ctx;
+
+/* Bytes of device workspace needed for n_instances replicas that share one
+ * system shape (same kind and key width), with main_capacity determinants and
+ * spawn_capacity spawned walkers summed over the instances. */
+size_t fq_workspace_bytes(const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss,
+                          int32_t n_instances, int64_t main_capacity, int64_t spawn_capacity);
+
+/* Creates a context for n_instances independent replicas (arrays sys[], qmc[]
+ * and, if not NULL, ss[] of that length) that advance together. Each replica
+ * starts with round(init_pop 2^b) units on its reference determinant (Hubbard:
+ * alpha on sites 0,2,4,..., beta on 1,3,5,...; UEG and molecular: aufbau). */
+fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc,
+                         const fq_semistoch *ss, int32_t n_instances, int64_t main_capacity,
+                         int64_t spawn_capacity, void *d_workspace, size_t ws_bytes,
+                         void *hip_stream);
+
+/* Advances every replica by n_iterations projector iterations (spawning,
+ * death/cloning, semi-stochastic projection, annihilation with the initiator
+ * rule, estimators, and the shift update every shift_period iterations:
+ * S <- S - zeta / (A dtau) ln(N_w(t) / N_w(t - A)) once N_w reached target).
+ * Returns after the work is enqueued and the host-side shift logic has run;
+ * estimators of every iteration are available afterwards. */
+fq_status fq_step(fq_ctx *ctx, int32_t n_iterations);
+
+/* Estimators of the last completed iteration of one instance. */
+fq_status fq_estimators(const fq_ctx *ctx, int32_t instance, fq_estimators_t *out);
+
+/* Estimators of the last n iterations (up to the last fq_step call), oldest
+ * first; *n_out receives the number written. */
+fq_status fq_estimator_history(const fq_ctx *ctx, int32_t instance, fq_estimators_t *out,
+                               int32_t cap, int32_t *n_out);
+
+/* Copies the main list of one instance to host arrays, sorted by key:
+ * keys[i*W + w], pops[i]. cap is the capacity in determinants. */
+fq_status fq_export_walkers(const fq_ctx *ctx, int32_t instance, uint64_t *keys, int32_t *pops,
+                            int64_t cap, int64_t *n_out);
+
+/* Replaces the main list of one instance (distinct keys, any order; zero
+ * populations are dropped) and sets its shift state and iteration counter
+ * (all instances share the counter: the same value must be given for each).
+ * If the semi-stochastic block is active and iteration >= start_iteration,
+ * the deterministic space is chosen from the imported list. */
+fq_status fq_import_walkers(fq_ctx *ctx, int32_t instance, const uint64_t *keys,
+                            const int32_t *pops, int64_t n, double shift, int64_t iteration,
+                            int32_t vary_shift, int64_t n_prev);
+
+/* Spawned walkers of the last iteration of one instance (unordered):
+ * keys[i*W + w], amps[i] (units), init[i] (1 if the parent was an initiator). */
+fq_status fq_export_spawns(const fq_ctx *ctx, int32_t instance, uint64_t *keys, int32_t *amps,
+                           uint8_t *init, int64_t cap, int64_t *n_out);
+
+/* Deterministic space of one instance in D order (|n| descending, key
+ * ascending at selection) and the last projection y = K_DD n (FP64 or
+ * split precision); either pointer may be NULL. */
+fq_status fq_detspace(const fq_ctx *ctx, int32_t instance, uint64_t *keys, double *last_y,
+                      int64_t cap, int64_t *n_out);
+
+/* Key width W and (kind, n_spin_orbitals, H_00) of a context. */
+fq_status fq_info(const fq_ctx *ctx, int32_t *W, int32_t *n_spin_orbitals, double *e_ref);
+
+/* Per-stage device time of the last fq_step call, in milliseconds, summed
+ * over its iterations, measured with HIP events on the context's stream:
+ * [0] attempt scan, [1] spawning, [2] radix sort, [3] segmented reduction,
+ * [4] merge with death and estimators, [5] deterministic projection,
+ * [6] whole iterations. Timing is recorded only after fq_set_timing(ctx, 1). */
+fq_status fq_set_timing(fq_ctx *ctx, int32_t on);
+fq_status fq_stage_times(const fq_ctx *ctx, double *ms7);
+
+const char *fq_last_error(const fq_ctx *ctx);
+void fq_destroy(fq_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1081 @@
+// Host half of the FCIQMC library: the C ABI of include/fciqmc.h.
+//
+// Builds the per-system device tables (UEG plane-wave basis, kinetic and
+// Coulomb tables, momentum grid; molecular integrals and heat-bath tables),
+// carves the caller's workspace into the main lists, the spawned list and the
+// sort/merge scratch, enqueues iterations on the caller's stream and runs the
+// shift update of the paper (Sec. 2.1: diagonal energy offset; tutorial
+// appendix: mc_cycles, target_population) on the host between iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/fciqmc.h"
+#include "fq_kernels.h"
+
+using namespace fq;
+
+namespace {
+
+constexpr int HIST_LEN = 128;
+constexpr uint64_t HOST_HASH_SEED = 0x9E3779B97F4A7C15ull;
+
+// MurmurHash64A over the key words (host copy of the device definition)
+uint64_t host_hash(const uint64_t *k, int W)
+{
+    const uint64_t m = 0xc6a4a7935bd1e995ull;
+    uint64_t h = HOST_HASH_SEED ^ ((uint64_t)(8 * W) * m);
+    for (int i = 0; i < W; ++i) {
+        uint64_t x = k[i];
+        x *= m;
+        x ^= x >> 47;
+        x *= m;
+        h ^= x;
+        h *= m;
+    }
+    h ^= h >> 47;
+    h *= m;
+    h ^= h >> 47;
+    return h;
+}
+
+uint64_t host_skey(uint64_t h, uint32_t rep, int rb) { return rb ? (((uint64_t)rep << (64 - rb)) | (h >> rb)) : h; }
+
+int key_cmp_host(const uint64_t *a, const uint64_t *b, int W)
+{
+    for (int i = W - 1; i >= 0; --i) {
+        if (a[i] < b[i]) return -1;
+        if (a[i] > b[i]) return 1;
+    }
+    return 0;
+}
+
+int round_w(int n_so)
+{
+    const int w = (n_so + 63) / 64;
+    if (w <= 1) return 1;
+    if (w <= 2) return 2;
+    if (w <= 4) return 4;
+    return 8;
+}
+
+// Host description of one system and the tables it ships to the device.
+struct HostSys {
+    int kind = 0, n_spatial = 0, n_so = 0, nel = 0, na = 0, nb = 0, periodic = 0;
+    double t = 0, U = 0, L = 0, k2 = 0, vc = 0;
+    int gmax = 0, gdim = 0, vlen = 0;
+    std::vector<int8_t> nvec;
+    std::vector<double> eps, vtab;
+    std::vector<int16_t> grid;
+    std::vector<double> h1, eri;
+    std::vector<int64_t> hb_off;
+    std::vector<int32_t> hb_cnt;
+    std::vector<double> hb_S, hb_cdf;
+    std::vector<uint16_t> hb_AB;
+    uint64_t ref[MAXW] = {0};
+};
+
+void setbit_h(uint64_t *k, int P) { k[P >> 6] |= 1ull << (P & 63); }
+
+double antisym_mol(const HostSys &s, int A, int B, int P, int Q)
+{
+    const int n = s.n_spatial;
+    auto e = [&](int p, int q, int r, int t) { return s.eri[(((size_t)p * n + q) * n + r) * n + t]; };
+    const int sa = A & 1, sb = B & 1, sp = P & 1, sq = Q & 1;
+    const double x = (sa == sp && sb == sq) ? e(A >> 1, P >> 1, B >> 1, Q >> 1) : 0.0;
+    const double y = (sa == sq && sb == sp) ? e(A >> 1, Q >> 1, B >> 1, P >> 1) : 0.0;
+    return x - y;
+}
+
+std::string build_system(const fq_system &d, HostSys &s)
+{
+    s.kind = d.kind;
+    s.na = d.n_alpha;
+    s.nb = d.n_beta;
+    s.nel = d.n_alpha + d.n_beta;
+    if (d.n_alpha < 0 || d.n_beta < 0 || s.nel < 2) return "need at least two electrons";
+    if (d.kind == FQ_HUBBARD_REAL) {
+        if (d.n_sites < 3 || d.n_sites > 32) return "Hubbard chain needs 3..32 sites";
+        if (d.n_alpha > d.n_sites || d.n_beta > d.n_sites) return "too many electrons for the chain";
+        s.n_spatial = d.n_sites;
+        s.periodic = d.periodic ? 1 : 0;
+        s.t = d.t;
+        s.U = d.U;
+        int placed = 0;
+        for (int pass = 0; pass < 2 && placed < d.n_alpha; ++pass)
+            for (int p = pass; p < d.n_sites && placed < d.n_alpha; p += 2, ++placed) setbit_h(s.ref, 2 * p);
+        placed = 0;
+        for (int pass = 1; pass >= 0 && placed < d.n_beta; --pass)
+            for (int p = pass; p < d.n_sites && placed < d.n_beta; p += 2, ++placed) setbit_h(s.ref, 2 * p + 1);
+    } else if (d.kind == FQ_UEG) {
+        if (d.ecut_n2 < 1 || !(d.rs > 0)) return "UEG needs rs > 0 and ecut_n2 >= 1";
+        int c = 0;
+        while ((c + 1) * (c + 1) <= d.ecut_n2) ++c;
+        struct PW { int n2, x, y, z; };
+        std::vector<PW> pw;
+        for (int x = -c; x <= c; ++x)
+            for (int y = -c; y <= c; ++y)
+                for (int z = -c; z <= c; ++z) {
+                    const int n2 = x * x + y * y + z * z;
+                    if (n2 <= d.ecut_n2) pw.push_back({n2, x, y, z});
+                }
+        std::sort(pw.begin(), pw.end(), [](const PW &a, const PW &b) {
+            if (a.n2 != b.n2) return a.n2 < b.n2;
+            if (a.x != b.x) return a.x < b.x;
+            if (a.y != b.y) return a.y < b.y;
+            return a.z < b.z;
+        });
+        const int M = (int)pw.size();
+        if (2 * M > 64 * MAXW) return "UEG basis exceeds 512 spin-orbitals";
+        if (d.n_alpha > M || d.n_beta > M) return "too many electrons for the basis";
+        s.n_spatial = M;
+        s.nvec.resize(3 * M);
+        s.eps.resize(M);
+        for (int i = 0; i < M; ++i) {
+            s.nvec[3 * i] = (int8_t)pw[i].x;
+            s.nvec[3 * i + 1] = (int8_t)pw[i].y;
+            s.nvec[3 * i + 2] = (int8_t)pw[i].z;
+        }
+        const double N = (double)s.nel;
+        s.L = d.rs * std::cbrt((4.0 * M_PI * N) / 3.0);
+        const double g = (2.0 * M_PI) / s.L;
+        s.k2 = g * g;
+        s.vc = (4.0 * M_PI) / ((s.L * s.L) * s.L);
+        for (int i = 0; i < M; ++i) s.eps[i] = (s.k2 * (double)pw[i].n2) * 0.5;
+        s.vlen = 4 * d.ecut_n2 + 1;
+        s.vtab.assign(s.vlen, 0.0);
+        for (int q = 1; q < s.vlen; ++q) s.vtab[q] = s.vc / (s.k2 * (double)q);
+        s.gmax = 3 * c;
+        s.gdim = 2 * s.gmax + 1;
+        s.grid.assign((size_t)s.gdim * s.gdim * s.gdim, (int16_t)-1);
+        for (int i = 0; i < M; ++i)
+            s.grid[((size_t)(pw[i].x + s.gmax) * s.gdim + (pw[i].y + s.gmax)) * s.gdim + (pw[i].z + s.gmax)] =
+                (int16_t)i;
+        for (int i = 0; i < d.n_alpha; ++i) setbit_h(s.ref, 2 * i);
+        for (int i = 0; i < d.n_beta; ++i) setbit_h(s.ref, 2 * i + 1);
+    } else if (d.kind == FQ_MOLECULAR) {
+        const int n = d.n_orb;
+        if (n <= 0 || 2 * n > 128 || !d.h1 || !d.eri) return "molecular system needs 1..64 orbitals and integrals";
+        if (d.n_alpha > n || d.n_beta > n) return "too many electrons for the orbitals";
+        s.n_spatial = n;
+        s.h1.assign(d.h1, d.h1 + (size_t)n * n);
+        s.eri.assign(d.eri, d.eri + (size_t)n * n * n * n);
+        for (int i = 0; i < d.n_alpha; ++i) setbit_h(s.ref, 2 * i);
+        for (int i = 0; i < d.n_beta; ++i) setbit_h(s.ref, 2 * i + 1);
+        const int ns = 2 * n;
+        s.hb_off.assign((size_t)ns * ns, 0);
+        s.hb_cnt.assign((size_t)ns * ns, 0);
+        s.hb_S.assign((size_t)ns * ns, 0.0);
+        // heat-bath tables: allowed A < B (spin conserving, outside {P,Q}) in
+        // lexicographic order, weight |<AB|PQ> - <AB|QP>|, sequential running sums
+        int64_t tot = 0;
+        for (int P = 0; P < ns; ++P)
+            for (int Q = P + 1; Q < ns; ++Q) {
+                s.hb_off[(size_t)P * ns + Q] = tot;
+                double cum = 0.0;
+                int cnt = 0;
+                for (int A = 0; A < ns; ++A)
+                    for (int B = A + 1; B < ns; ++B) {
+                        if (A == P || A == Q || B == P || B == Q) continue;
+                        if ((A & 1) + (B & 1) != (P & 1) + (Q & 1)) continue;
+                        cum = cum + std::fabs(antisym_mol(s, A, B, P, Q));
+                        s.hb_AB.push_back((uint16_t)(A | (B << 8)));
+                        s.hb_cdf.push_back(cum);
+                        ++cnt;
+                    }
+                s.hb_cnt[(size_t)P * ns + Q] = cnt;
+                s.hb_S[(size_t)P * ns + Q] = cum;
+                tot += cnt;
+            }
+    } else {
+        return "unknown system kind";
+    }
+    s.n_so = 2 * s.n_spatial;
+    return "";
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// device image of one system's tables
+size_t table_bytes(const HostSys &s)
+{
+    return al(s.nvec.size()) + al(8 * s.eps.size()) + al(8 * s.vtab.size()) + al(2 * s.grid.size()) +
+           al(8 * s.h1.size()) + al(8 * s.eri.size()) + al(8 * s.hb_off.size()) + al(4 * s.hb_cnt.size()) +
+           al(8 * s.hb_S.size()) + al(2 * s.hb_AB.size()) + al(8 * s.hb_cdf.size());
+}
+
+struct Layout {
+    size_t total = 0;
+    size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge;
+    size_t main[2][6];
+    size_t sp[7];
+    size_t u[4];
+    size_t ds[10];
+    size_t dkeys;
+};
+
+int64_t tiles_of(int64_t n, int64_t tile) { return (n + tile - 1) / tile + 1; }
+
+// spans of 256 attempts the attempt partition can hold
+int64_t span_capacity(int64_t mcap, int64_t scap) { return tiles_of(std::max(mcap * 16, scap * 4), 256); }
+
+Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D)
+{
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t r = o;
+        o += al(b);
+        return r;
+    };
+    L.ctl = take(sizeof(Ctl));
+    L.acc = take(sizeof(EstAcc) * R);
+    L.hist = take(sizeof(EstAcc) * R * HIST_LEN);
+    L.shift = take(8 * R);
+    L.rep = take(sizeof(RepParams) * R);
+    L.sys = take(sizeof(DevSys) * R);
+    L.tables = take((size_t)tables);
+    L.att = take(8 * (size_t)(mcap + 1));
+    L.span = take(8 * (size_t)(span_capacity(mcap, scap) + 2));
+    L.mpart = take(8 * (size_t)(tiles_of(mcap + scap, 1024) + 2));
+    L.st_scan = take(8 * (size_t)tiles_of(mcap, 2048));
+    L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, 4096));
+    L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
+    L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 1024));
+    for (int b = 0; b < 2; ++b) {
+        L.main[b][0] = take(8 * (size_t)mcap);
+        L.main[b][1] = take(8 * (size_t)mcap * W);
+        L.main[b][2] = take(4 * (size_t)mcap);
+        L.main[b][3] = take(8 * (size_t)mcap);
+        L.main[b][4] = take(4 * (size_t)mcap);
+        L.main[b][5] = take(4 * (size_t)mcap);
+    }
+    L.sp[0] = take(8 * (size_t)scap);
+    L.sp[1] = take(8 * (size_t)scap * W);
+    L.sp[2] = take(4 * (size_t)scap);
+    L.sp[3] = take((size_t)scap);
+    L.sp[4] = take(8 * (size_t)scap);
+    L.sp[5] = take(4 * (size_t)scap);
+    L.sp[6] = take(4 * (size_t)scap);
+    L.u[0] = take(8 * (size_t)scap);
+    L.u[1] = take(8 * (size_t)scap * W);
+    L.u[2] = take(8 * (size_t)scap);
+    L.u[3] = take(4 * (size_t)scap);
+    const size_t nd = (size_t)D * R;
+    L.ds[0] = take(8 * nd * (size_t)D);  // K fp64
+    L.ds[1] = take(2 * nd * (size_t)D);  // K hi bf16
+    L.ds[2] = take(2 * nd * (size_t)D);  // K lo bf16
+    L.ds[3] = take(4 * nd);              // pos
+    L.ds[4] = take(8 * nd);              // h64
+    L.ds[5] = take(8 * nd);              // c
+    L.ds[6] = take(8 * nd);              // y
+    L.ds[7] = take(8 * nd);              // delta
+    L.ds[8] = take(8 * nd);              // sorted skeys
+    L.ds[9] = take(8 * nd * W);          // sorted keys
+    L.dkeys = take(8 * nd * W);          // keys in D order
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct fq_ctx {
+    int R = 0, W = 0, kind = 0, rb = 0;
+    hipStream_t stream = nullptr;
+    std::vector<HostSys> sys;
+    std::vector<fq_qmc> qmc;
+    bool has_ss = false;
+    fq_semistoch ss{};
+    int D = 0;
+    bool ss_active = false;
+    Layout L;
+    char *ws = nullptr;
+    Work w{};
+    MainList buf[2];
+    int cur = 0;
+    int64_t main_cap = 0, spawn_cap = 0;
+    Grids grids{};
+    std::vector<double> shift;
+    std::vector<int> vary;
+    std::vector<int64_t> nprev;
+    int64_t t = 0;           // completed (enqueued and synchronised) iterations
+    std::vector<fq_estimators_t> last;
+    std::vector<std::vector<fq_estimators_t>> hist;  // [R][...] of the last fq_step
+    std::vector<std::vector<uint64_t>> dkeys;        // [R][D*W] D order
+    Ctl *h_ctl = nullptr;
+    EstAcc *h_hist = nullptr;
+    double *h_shift = nullptr;
+    double h00[64] = {0};
+    std::vector<double> h00v;
+    bool timing = false;
+    double stage_ms[7] = {0};
+    std::string err;
+};
+
+namespace {
+
+fq_status fail(fq_ctx *c, fq_status s, const std::string &m)
+{
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) return fail(ctx, FQ_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+void estimators_from_acc(const fq_ctx *c, int r, const EstAcc &a, fq_estimators_t &e)
+{
+    std::memset(&e, 0, sizeof(e));
+    e.iteration = a.t;
+    e.n_walkers_units = a.nw;
+    e.n_occupied = a.nocc;
+    e.n_spawned = a.nspawn;
+    e.ref_pop_units = a.n0;
+    e.n_sign_flips = a.flips;
+    e.n_rejected_units = a.rej_units;
+    e.n_spawn_events = a.nuniq;
+    e.death_sum = a.death_sum;
+    e.spawn_sum = a.spawn_sum;
+    e.rejected_sum = a.rej_sum;
+    for (int k = 0; k < 4; ++k) e.num_limbs[k] = a.limbs[k];
+    __int128 tot = 0;
+    for (int k = 0; k < 4; ++k) tot += (__int128)a.limbs[k] * ((__int128)1 << (32 * k));
+    const double num = (double)tot * 0x1p-64;
+    e.proj_numerator = num * std::ldexp(1.0, -c->qmc[r].fixed_point_bits);
+    e.proj_energy = a.n0 != 0 ? num / (double)a.n0 : NAN;
+    e.e_ref = c->h00v[r];
+}
+
+void set_main_views(fq_ctx *c)
+{
+    for (int b = 0; b < 2; ++b) {
+        MainList &m = c->buf[b];
+        m.skey = (uint64_t *)(c->ws + c->L.main[b][0]);
+        m.key = (uint64_t *)(c->ws + c->L.main[b][1]);
+        m.pop = (int32_t *)(c->ws + c->L.main[b][2]);
+        m.kdiag = (double *)(c->ws + c->L.main[b][3]);
+        m.dslot = (int32_t *)(c->ws + c->L.main[b][4]);
+        m.natt = (int32_t *)(c->ws + c->L.main[b][5]);
+    }
+    c->w.cur = c->buf[c->cur];
+    c->w.nxt = c->buf[c->cur ^ 1];
+}
+
+struct HostEntry {
+    uint64_t skey;
+    uint64_t key[MAXW];
+    int32_t pop;
+    int32_t dslot;
+};
+
+// downloads the whole current main list
+fq_status download_main(fq_ctx *c, std::vector<HostEntry> &out, int64_t &n)
+{
+    HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    n = c->h_ctl->n_main_new;
+    const MainList &m = c->buf[c->cur];
+    std::vector<uint64_t> sk(n), kk((size_t)n * c->W);
+    std::vector<int32_t> pp(n), ds(n);
+    if (n) {
+        HIPCHK(c, hipMemcpy(sk.data(), m.skey, 8 * n, hipMemcpyDeviceToHost));
+        for (int q = 0; q < c->W; ++q)
+            HIPCHK(c, hipMemcpy(kk.data() + (size_t)q * n, m.key + (size_t)q * c->main_cap, 8 * n, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(pp.data(), m.pop, 4 * n, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(ds.data(), m.dslot, 4 * n, hipMemcpyDeviceToHost));
+    }
+    out.resize(n);
+    for (int64_t i = 0; i < n; ++i) {
+        out[i].skey = sk[i];
+        for (int q = 0; q < MAXW; ++q) out[i].key[q] = q < c->W ? kk[(size_t)q * n + i] : 0;
+        out[i].pop = pp[i];
+        out[i].dslot = ds[i];
+    }
+    return FQ_OK;
+}
+
+// uploads a list sorted by (skey, key) into the current buffer, recomputes
+// K_ii - H_00 and attempt counts on the device
+fq_status upload_main(fq_ctx *c, const std::vector<HostEntry> &e)
+{
+    const int64_t n = (int64_t)e.size();
+    if (n > c->main_cap) return fail(c, FQ_ECAPACITY, "main list capacity exceeded");
+    const MainList &m = c->buf[c->cur];
+    std::vector<uint64_t> sk(n), kk((size_t)n * c->W);
+    std::vector<int32_t> pp(n), ds(n);
+    for (int64_t i = 0; i < n; ++i) {
+        sk[i] = e[i].skey;
+        for (int q = 0; q < c->W; ++q) kk[(size_t)q * n + i] = e[i].key[q];
+        pp[i] = e[i].pop;
+        ds[i] = e[i].dslot;
+    }
+    if (n) {
+        HIPCHK(c, hipMemcpy(m.skey, sk.data(), 8 * n, hipMemcpyHostToDevice));
+        for (int q = 0; q < c->W; ++q)
+            HIPCHK(c, hipMemcpy(m.key + (size_t)q * c->main_cap, kk.data() + (size_t)q * n, 8 * n, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(m.pop, pp.data(), 4 * n, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(m.dslot, ds.data(), 4 * n, hipMemcpyHostToDevice));
+    }
+    set_main_views(c);
+    HIPCHK(c, enqueue_setup(1, c->kind, c->w, nullptr, 0, m, n, nullptr, nullptr, c->stream));
+    Ctl ctl;
+    HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    ctl.n_main = n;
+    ctl.n_main_new = n;
+    HIPCHK(c, hipMemcpy(c->w.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FQ_OK;
+}
+
+bool entry_less(const HostEntry &a, const HostEntry &b, int W)
+{
+    if (a.skey != b.skey) return a.skey < b.skey;
+    return key_cmp_host(a.key, b.key, W) < 0;
+}
+
+// initial estimators of each replica (iteration counter value, list as is)
+fq_status host_estimators(fq_ctx *c)
+{
+    std::vector<HostEntry> e;
+    int64_t n;
+    fq_status st = download_main(c, e, n);
+    if (st) return st;
+    for (int r = 0; r < c->R; ++r) {
+        EstAcc a;
+        std::memset(&a, 0, sizeof(a));
+        a.t = c->t;
+        for (const HostEntry &x : e) {
+            const uint32_t rep = c->rb ? (uint32_t)(x.skey >> (64 - c->rb)) : 0u;
+            if ((int)rep != r) continue;
+            a.nw += x.pop < 0 ? -(long long)x.pop : x.pop;
+            a.nocc += 1;
+            if (key_cmp_host(x.key, c->sys[r].ref, c->W) == 0) a.n0 = x.pop;
+        }
+        estimators_from_acc(c, r, a, c->last[r]);
+        c->last[r].shift = c->shift[r];
+        c->last[r].vary_shift = c->vary[r];
+    }
+    return FQ_OK;
+}
+
+// deterministic space: the `size` largest |n| of each replica (key ascending on ties)
+fq_status select_detspace(fq_ctx *c)
+{
+    std::vector<HostEntry> e;
+    int64_t n;
+    fq_status st = download_main(c, e, n);
+    if (st) return st;
+    const int D = c->D, R = c->R, W = c->W;
+    const size_t nd = (size_t)D * R;
+    std::vector<int32_t> pos(nd, 0);
+    std::vector<uint64_t> h64(nd, 0), dk(nd * W, 0);
+    c->dkeys.assign(R, std::vector<uint64_t>());
+    for (int r = 0; r < R; ++r) {
+        std::vector<int64_t> ix;
+        for (int64_t i = 0; i < n; ++i) {
+            const uint32_t rep = c->rb ? (uint32_t)(e[i].skey >> (64 - c->rb)) : 0u;
+            if ((int)rep == r) ix.push_back(i);
+        }
+        if ((int64_t)ix.size() < D) return fail(c, FQ_ESTATE, "fewer occupied determinants than the deterministic space size");
+        std::sort(ix.begin(), ix.end(), [&](int64_t a, int64_t b) {
+            const long long pa = std::llabs((long long)e[a].pop), pb = std::llabs((long long)e[b].pop);
+            if (pa != pb) return pa > pb;
+            return key_cmp_host(e[a].key, e[b].key, W) < 0;
+        });
+        c->dkeys[r].resize((size_t)D * W);
+        for (int d = 0; d < D; ++d) {
+            const int64_t i = ix[d];
+            e[i].dslot = d;
+            pos[(size_t)r * D + d] = (int32_t)i;
+            h64[(size_t)r * D + d] = host_hash(e[i].key, W);
+            for (int q = 0; q < W; ++q) {
+                dk[(size_t)q * nd + (size_t)r * D + d] = e[i].key[q];
+                c->dkeys[r][(size_t)d * W + q] = e[i].key[q];
+            }
+        }
+    }
+    // sorted copy for membership tests
+    std::vector<size_t> order(nd);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<uint64_t> sks(nd);
+    for (size_t x = 0; x < nd; ++x) {
+        uint64_t k[MAXW] = {0};
+        for (int q = 0; q < W; ++q) k[q] = dk[(size_t)q * nd + x];
+        sks[x] = host_skey(host_hash(k, W), (uint32_t)(x / D), c->rb);
+    }
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        if (sks[a] != sks[b]) return sks[a] < sks[b];
+        uint64_t ka[MAXW] = {0}, kb[MAXW] = {0};
+        for (int q = 0; q < W; ++q) {
+            ka[q] = dk[(size_t)q * nd + a];
+            kb[q] = dk[(size_t)q * nd + b];
+        }
+        return key_cmp_host(ka, kb, W) < 0;
+    });
+    std::vector<uint64_t> ssk(nd), skk(nd * W);
+    for (size_t x = 0; x < nd; ++x) {
+        ssk[x] = sks[order[x]];
+        for (int q = 0; q < W; ++q) skk[(size_t)q * nd + x] = dk[(size_t)q * nd + order[x]];
+    }
+    // dslot of the current list
+    std::vector<int32_t> ds(n);
+    for (int64_t i = 0; i < n; ++i) ds[i] = e[i].dslot;
+    const MainList &m = c->buf[c->cur];
+    if (n) HIPCHK(c, hipMemcpy(m.dslot, ds.data(), 4 * n, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[3], pos.data(), 4 * nd, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[4], h64.data(), 8 * nd, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[8], ssk.data(), 8 * nd, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[9], skk.data(), 8 * nd * W, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.dkeys, dk.data(), 8 * nd * W, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(c->ws + c->L.ds[6], 0, 8 * nd));
+    HIPCHK(c, enqueue_setup(2, c->kind, c->w, nullptr, 0, m, 0, (const uint64_t *)(c->ws + c->L.dkeys),
+                            (double *)(c->ws + c->L.ds[0]), c->stream));
+    Ctl ctl;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    ctl.ss_active = 1;
+    HIPCHK(c, hipMemcpy(c->w.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice));
+    c->ss_active = true;
+    return FQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fq_workspace_bytes(const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss, int32_t n_instances,
+                          int64_t main_capacity, int64_t spawn_capacity)
+{
+    (void)qmc;
+    if (!sys || n_instances <= 0 || main_capacity <= 0 || spawn_capacity <= 0) return 0;
+    int64_t tables = 0;
+    int W = 1;
+    for (int r = 0; r < n_instances; ++r) {
+        HostSys s;
+        if (!build_system(sys[r], s).empty()) return 0;
+        tables += (int64_t)table_bytes(s);
+        W = std::max(W, round_w(s.n_so));
+    }
+    const int D = ss ? std::max(0, ss[0].size) : 0;
+    return make_layout(n_instances, W, main_capacity, spawn_capacity, tables, D).total + 256;
+}
+
+fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss,
+                         int32_t n_instances, int64_t main_capacity, int64_t spawn_capacity, void *d_workspace,
+                         size_t ws_bytes, void *hip_stream)
+{
+    if (!out || !sys || !qmc || n_instances <= 0 || n_instances > 4096 || main_capacity < n_instances ||
+        spawn_capacity < 1 || !d_workspace)
+        return FQ_EINVAL;
+    if (spawn_capacity >= (1ll << 32)) return FQ_EINVAL;
+    *out = nullptr;
+    fq_ctx *c = new fq_ctx();
+    c->R = n_instances;
+    c->stream = (hipStream_t)hip_stream;
+    c->main_cap = main_capacity;
+    c->spawn_cap = spawn_capacity;
+    c->sys.resize(c->R);
+    c->qmc.assign(qmc, qmc + c->R);
+    int64_t tables = 0;
+    for (int r = 0; r < c->R; ++r) {
+        const std::string m = build_system(sys[r], c->sys[r]);
+        if (!m.empty()) { delete c; return FQ_EINVAL; }
+        const int W = round_w(c->sys[r].n_so);
+        if (r == 0) { c->W = W; c->kind = sys[r].kind; }
+        if (W != c->W || sys[r].kind != c->kind) { delete c; return FQ_EINVAL; }
+        const fq_qmc &q = qmc[r];
+        const int need = c->kind == FQ_HUBBARD_REAL ? FQ_EXGEN_HUB_UNIFORM
+                         : c->kind == FQ_UEG        ? FQ_EXGEN_UEG_UNIFORM
+                                                    : FQ_EXGEN_HEATBATH_UNIFORM_SINGLES;
+        if (!(q.tau > 0) || q.excit_gen != need || q.fixed_point_bits < 0 || q.fixed_point_bits > 20 ||
+            q.shift_period <= 0 || q.shift_period > HIST_LEN / 2 || !(q.init_pop >= 0) ||
+            (q.excit_gen == FQ_EXGEN_HEATBATH_UNIFORM_SINGLES && !(q.p_single >= 0 && q.p_single < 1))) {
+            delete c;
+            return FQ_EINVAL;
+        }
+        tables += (int64_t)table_bytes(c->sys[r]);
+    }
+    if (c->kind == FQ_HUBBARD_REAL && c->W != 1) { delete c; return FQ_EINVAL; }
+    for (int r = 1; r < c->R; ++r)
+        if (qmc[r].shift_period != qmc[0].shift_period) { delete c; return FQ_EINVAL; }
+    c->rb = 0;
+    while ((1 << c->rb) < c->R) ++c->rb;
+    if (ss && ss[0].size > 0) {
+        c->has_ss = true;
+        c->ss = ss[0];
+        c->D = ss[0].size;
+        if (ss[0].precision != FQ_SS_FP64 && ss[0].precision != FQ_SS_SPLIT_BF16) { delete c; return FQ_EINVAL; }
+        for (int r = 1; r < c->R; ++r)
+            if (ss[r].size != ss[0].size || ss[r].start_iteration != ss[0].start_iteration) { delete c; return FQ_EINVAL; }
+    }
+    c->L = make_layout(c->R, c->W, main_capacity, spawn_capacity, tables, c->D);
+    if (ws_bytes < c->L.total || ((uintptr_t)d_workspace & 255)) { delete c; return FQ_EINVAL; }
+    c->ws = (char *)d_workspace;
+    Work &w = c->w;
+    w.ctl = (Ctl *)(c->ws + c->L.ctl);
+    w.acc = (EstAcc *)(c->ws + c->L.acc);
+    w.hist = (EstAcc *)(c->ws + c->L.hist);
+    w.shift = (double *)(c->ws + c->L.shift);
+    w.rep = (const RepParams *)(c->ws + c->L.rep);
+    w.sys = (const DevSys *)(c->ws + c->L.sys);
+    w.att_off = (long long *)(c->ws + c->L.att);
+    w.span_lo = (long long *)(c->ws + c->L.span);
+    w.mpart = (long long *)(c->ws + c->L.mpart);
+    w.st_scan = (unsigned long long *)(c->ws + c->L.st_scan);
+    w.st_sort = (unsigned long long *)(c->ws + c->L.st_sort);
+    w.st_red = (unsigned long long *)(c->ws + c->L.st_red);
+    w.st_merge = (unsigned long long *)(c->ws + c->L.st_merge);
+    w.sp.skey = (uint64_t *)(c->ws + c->L.sp[0]);
+    w.sp.key = (uint64_t *)(c->ws + c->L.sp[1]);
+    w.sp.amp = (int32_t *)(c->ws + c->L.sp[2]);
+    w.sp.init = (uint8_t *)(c->ws + c->L.sp[3]);
+    w.sp.skey2 = (uint64_t *)(c->ws + c->L.sp[4]);
+    w.sp.idx = (uint32_t *)(c->ws + c->L.sp[5]);
+    w.sp.idx2 = (uint32_t *)(c->ws + c->L.sp[6]);
+    w.u.skey = (uint64_t *)(c->ws + c->L.u[0]);
+    w.u.key = (uint64_t *)(c->ws + c->L.u[1]);
+    w.u.sum = (long long *)(c->ws + c->L.u[2]);
+    w.u.flag = (uint32_t *)(c->ws + c->L.u[3]);
+    w.ds.n = c->D;
+    w.ds.precision = c->has_ss ? c->ss.precision : 0;
+    w.ds.K = (const double *)(c->ws + c->L.ds[0]);
+    w.ds.Khi = (const uint16_t *)(c->ws + c->L.ds[1]);
+    w.ds.Klo = (const uint16_t *)(c->ws + c->L.ds[2]);
+    w.ds.pos = (int32_t *)(c->ws + c->L.ds[3]);
+    w.ds.h64 = (const uint64_t *)(c->ws + c->L.ds[4]);
+    w.ds.c = (double *)(c->ws + c->L.ds[5]);
+    w.ds.y = (double *)(c->ws + c->L.ds[6]);
+    w.ds.delta = (long long *)(c->ws + c->L.ds[7]);
+    w.ds.skey_sorted = (const uint64_t *)(c->ws + c->L.ds[8]);
+    w.ds.key_sorted = (const uint64_t *)(c->ws + c->L.ds[9]);
+    w.main_cap = main_capacity;
+    w.spawn_cap = spawn_capacity;
+    w.span_cap = span_capacity(main_capacity, spawn_capacity);
+    w.R = c->R;
+    w.rb = c->rb;
+    w.W = c->W;
+    w.hist_len = HIST_LEN;
+    c->cur = 0;
+    set_main_views(c);
+
+    // tables and per-system device structs
+    std::vector<DevSys> ds(c->R);
+    std::vector<RepParams> rp(c->R);
+    size_t toff = c->L.tables;
+    auto put = [&](const void *src, size_t bytes) -> const void * {
+        if (!bytes) return nullptr;
+        char *dst = c->ws + toff;
+        (void)hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+        toff += al(bytes);
+        return dst;
+    };
+    for (int r = 0; r < c->R; ++r) {
+        const HostSys &s = c->sys[r];
+        DevSys &d = ds[r];
+        std::memset(&d, 0, sizeof(d));
+        d.kind = s.kind;
+        d.n_spatial = s.n_spatial;
+        d.n_so = s.n_so;
+        d.nel = s.nel;
+        d.na = s.na;
+        d.nb = s.nb;
+        d.periodic = s.periodic;
+        d.t = s.t;
+        d.U = s.U;
+        d.gmax = s.gmax;
+        d.gdim = s.gdim;
+        d.vlen = s.vlen;
+        d.nvec = (const int8_t *)put(s.nvec.data(), s.nvec.size());
+        d.eps = (const double *)put(s.eps.data(), 8 * s.eps.size());
+        d.vtab = (const double *)put(s.vtab.data(), 8 * s.vtab.size());
+        d.grid = (const int16_t *)put(s.grid.data(), 2 * s.grid.size());
+        d.h1 = (const double *)put(s.h1.data(), 8 * s.h1.size());
+        d.eri = (const double *)put(s.eri.data(), 8 * s.eri.size());
+        d.hb_off = (const int64_t *)put(s.hb_off.data(), 8 * s.hb_off.size());
+        d.hb_cnt = (const int32_t *)put(s.hb_cnt.data(), 4 * s.hb_cnt.size());
+        d.hb_S = (const double *)put(s.hb_S.data(), 8 * s.hb_S.size());
+        d.hb_AB = (const uint16_t *)put(s.hb_AB.data(), 2 * s.hb_AB.size());
+        d.hb_cdf = (const double *)put(s.hb_cdf.data(), 8 * s.hb_cdf.size());
+        std::memcpy(d.ref, s.ref, sizeof(d.ref));
+        const fq_qmc &q = qmc[r];
+        RepParams &p = rp[r];
+        std::memset(&p, 0, sizeof(p));
+        p.tau = q.tau;
+        p.p_single = q.p_single;
+        const double scale = std::ldexp(1.0, q.fixed_point_bits);
+        p.cu = q.fixed_point_bits ? (int64_t)std::floor(q.spawn_cutoff * scale + 0.5) : 0;
+        p.thr = (int64_t)std::floor(q.initiator_threshold * scale);
+        p.k0 = (uint32_t)q.rng_seed;
+        p.k1 = (uint32_t)(q.rng_seed >> 32) ^ (uint32_t)q.replica_id;
+        p.bits = q.fixed_point_bits;
+        p.initiator = q.initiator ? 1 : 0;
+        p.sys = r;
+    }
+    hipError_t he = hipMemcpy((void *)w.sys, ds.data(), sizeof(DevSys) * c->R, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy((void *)w.rep, rp.data(), sizeof(RepParams) * c->R, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemset(w.ctl, 0, sizeof(Ctl));
+    if (he == hipSuccess) he = hipMemset(c->ws + c->L.st_scan, 0, c->L.main[0][0] - c->L.st_scan);
+    if (he == hipSuccess) he = enqueue_setup(0, c->kind, w, (DevSys *)w.sys, c->R, c->buf[0], 0, nullptr, nullptr, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) { delete c; return FQ_EHIP; }
+    c->h00v.resize(c->R);
+    for (int r = 0; r < c->R; ++r) {
+        DevSys d;
+        hipMemcpy(&d, w.sys + r, sizeof(DevSys), hipMemcpyDeviceToHost);
+        c->h00v[r] = d.H00;
+    }
+    he = hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), 0);
+    if (he == hipSuccess) he = hipHostMalloc((void **)&c->h_hist, sizeof(EstAcc) * c->R * HIST_LEN, 0);
+    if (he == hipSuccess) he = hipHostMalloc((void **)&c->h_shift, 8 * c->R, 0);
+    if (he != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
+
+    // grids: persistent tile kernels sized to the resident capacity
+    int dev = 0, ncu = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    c->grids.scan = ncu * occupancy_blocks(3);
+    c->grids.sort = ncu * occupancy_blocks(0);
+    c->grids.merge = ncu * occupancy_blocks(1);
+    c->grids.reduce = ncu * occupancy_blocks(2);
+    c->grids.part = ncu * 4;
+    c->grids.spawn = ncu * 8;
+    c->grids.hist = ncu * 4;
+    c->grids.fixup = ncu * 2;
+    c->grids.det = ncu * 4;
+
+    c->shift.assign(c->R, 0.0);
+    c->vary.assign(c->R, 0);
+    c->nprev.assign(c->R, 0);
+    c->last.resize(c->R);
+    c->hist.assign(c->R, {});
+    // initial list: the reference of each replica
+    std::vector<HostEntry> init(c->R);
+    for (int r = 0; r < c->R; ++r) {
+        HostEntry &e = init[r];
+        std::memset(&e, 0, sizeof(e));
+        std::memcpy(e.key, c->sys[r].ref, sizeof(e.key));
+        e.skey = host_skey(host_hash(e.key, c->W), (uint32_t)r, c->rb);
+        const double scale = std::ldexp(1.0, qmc[r].fixed_point_bits);
+        const double u = std::floor(qmc[r].init_pop * scale + 0.5);
+        if (u > 2147483647.0) { fq_destroy(c); return FQ_EOVERFLOW; }
+        e.pop = (int32_t)u;
+        e.dslot = -1;
+        c->shift[r] = qmc[r].initial_shift;
+    }
+    std::vector<HostEntry> nz;
+    for (auto &e : init)
+        if (e.pop != 0) nz.push_back(e);
+    std::sort(nz.begin(), nz.end(), [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, c->W); });
+    for (int r = 0; r < c->R; ++r) c->h_shift[r] = c->shift[r];
+    if (hipMemcpy(w.shift, c->h_shift, 8 * c->R, hipMemcpyHostToDevice) != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
+    if (upload_main(c, nz) != FQ_OK || host_estimators(c) != FQ_OK) { fq_destroy(c); return FQ_EHIP; }
+    *out = c;
+    return FQ_OK;
+}
+
+fq_status fq_step(fq_ctx *c, int32_t n_iterations)
+{
+    if (!c) return FQ_EINVAL;
+    if (n_iterations < 0) return fail(c, FQ_EINVAL, "negative iteration count");
+    const int A = c->qmc[0].shift_period;
+    for (int r = 0; r < c->R; ++r) c->hist[r].clear();
+    std::fill(c->stage_ms, c->stage_ms + 7, 0.0);
+    std::vector<hipEvent_t> evs;
+    int done = 0;
+    while (done < n_iterations) {
+        // iterations until the next host decision point (shift update, D selection, end)
+        int64_t stop = c->t + (n_iterations - done);
+        const int64_t next_shift = (c->t / A + 1) * A;
+        stop = std::min(stop, next_shift);
+        if (c->has_ss && !c->ss_active && c->t < c->ss.start_iteration) stop = std::min<int64_t>(stop, c->ss.start_iteration);
+        stop = std::min<int64_t>(stop, c->t + HIST_LEN / 2);
+        const int64_t t0 = c->t;
+        const int cur0 = c->cur;
+        const int nb = (int)(stop - t0);
+        if (c->timing) {
+            evs.resize((size_t)nb * 7);
+            for (auto &e : evs) hipEventCreate(&e);
+        }
+        for (int k = 0; k < nb; ++k) {
+            hipError_t he = enqueue_iteration(c->w, c->kind, c->grids, c->stream, c->timing ? &evs[(size_t)k * 7] : nullptr);
+            if (he != hipSuccess) return fail(c, FQ_EHIP, std::string("launch: ") + hipGetErrorString(he));
+            c->cur ^= 1;
+            set_main_views(c);
+        }
+        HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->h_hist, c->w.hist, sizeof(EstAcc) * c->R * HIST_LEN, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->timing) {
+            for (int k = 0; k < nb; ++k) {
+                float ms;
+                hipEvent_t *e = &evs[(size_t)k * 7];
+                hipEventElapsedTime(&ms, e[0], e[1]); c->stage_ms[0] += ms;
+                hipEventElapsedTime(&ms, e[1], e[2]); c->stage_ms[1] += ms;
+                hipEventElapsedTime(&ms, e[2], e[3]); c->stage_ms[2] += ms;
+                hipEventElapsedTime(&ms, e[3], e[4]); c->stage_ms[3] += ms;
+                hipEventElapsedTime(&ms, e[5], e[6]); c->stage_ms[4] += ms;
+                hipEventElapsedTime(&ms, e[4], e[5]); c->stage_ms[5] += ms;
+                hipEventElapsedTime(&ms, e[0], e[6]); c->stage_ms[6] += ms;
+            }
+            for (auto &e : evs) hipEventDestroy(e);
+            evs.clear();
+        }
+        const Ctl &ctl = *c->h_ctl;
+        if (ctl.err) {
+            const int64_t tf = ctl.t;  // failing iteration
+            c->cur = cur0 ^ (int)((tf - 1 - t0) & 1);
+            set_main_views(c);
+            // restore the device counters to the start of the failing iteration
+            Ctl fix = ctl;
+            fix.err = 0;
+            fix.t = (uint32_t)(tf - 1);
+            fix.n_main_new = ctl.n_main;
+            HIPCHK(c, hipMemcpy(c->w.ctl, &fix, sizeof(Ctl), hipMemcpyHostToDevice));
+            for (int64_t it = t0 + 1; it < tf; ++it)
+                for (int r = 0; r < c->R; ++r) {
+                    fq_estimators_t e;
+                    estimators_from_acc(c, r, c->h_hist[(size_t)(it % HIST_LEN) * c->R + r], e);
+                    e.shift = c->shift[r];
+                    e.vary_shift = c->vary[r];
+                    c->hist[r].push_back(e);
+                    c->last[r] = e;
+                }
+            c->t = tf - 1;
+            if (ctl.err & (ERR_OVERFLOW | ERR_ATTEMPTS)) return fail(c, FQ_EOVERFLOW, "population or spawn exceeds the fixed-point range");
+            return fail(c, FQ_ECAPACITY, (ctl.err & ERR_SPAWN_CAP) ? "spawn capacity exceeded" : "main list capacity exceeded");
+        }
+        for (int64_t it = t0 + 1; it <= stop; ++it) {
+            for (int r = 0; r < c->R; ++r) {
+                fq_estimators_t e;
+                estimators_from_acc(c, r, c->h_hist[(size_t)(it % HIST_LEN) * c->R + r], e);
+                if (it % A == 0) {
+                    const double target = c->qmc[r].target_population * std::ldexp(1.0, c->qmc[r].fixed_point_bits);
+                    const int64_t nw = e.n_walkers_units;
+                    if (!c->vary[r]) {
+                        if ((double)nw >= target) {
+                            c->vary[r] = 1;
+                            c->nprev[r] = nw;
+                        }
+                    } else {
+                        const double cc = c->qmc[r].shift_damping / ((double)A * c->qmc[r].tau);
+                        const double ratio = (double)nw / (double)c->nprev[r];
+                        c->shift[r] = c->shift[r] - cc * std::log(ratio);
+                        c->nprev[r] = nw;
+                    }
+                }
+                e.shift = c->shift[r];
+                e.vary_shift = c->vary[r];
+                c->hist[r].push_back(e);
+                c->last[r] = e;
+            }
+        }
+        c->t = stop;
+        done += nb;
+        for (int r = 0; r < c->R; ++r) c->h_shift[r] = c->shift[r];
+        HIPCHK(c, hipMemcpyAsync(c->w.shift, c->h_shift, 8 * c->R, hipMemcpyHostToDevice, c->stream));
+        if (c->has_ss && !c->ss_active && c->t >= c->ss.start_iteration) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            fq_status st = select_detspace(c);
+            if (st) return st;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FQ_OK;
+}
+
+fq_status fq_estimators(const fq_ctx *c, int32_t instance, fq_estimators_t *out)
+{
+    if (!c || !out || instance < 0 || instance >= c->R) return FQ_EINVAL;
+    *out = c->last[instance];
+    return FQ_OK;
+}
+
+fq_status fq_estimator_history(const fq_ctx *c, int32_t instance, fq_estimators_t *out, int32_t cap, int32_t *n_out)
+{
+    if (!c || !out || !n_out || instance < 0 || instance >= c->R || cap < 0) return FQ_EINVAL;
+    const auto &h = c->hist[instance];
+    const int n = (int)std::min<size_t>(h.size(), (size_t)cap);
+    for (int i = 0; i < n; ++i) out[i] = h[h.size() - n + i];
+    *n_out = n;
+    return FQ_OK;
+}
+
+fq_status fq_export_walkers(const fq_ctx *cc, int32_t instance, uint64_t *keys, int32_t *pops, int64_t cap,
+                            int64_t *n_out)
+{
+    fq_ctx *c = const_cast<fq_ctx *>(cc);
+    if (!c || instance < 0 || instance >= c->R || !n_out) return FQ_EINVAL;
+    std::vector<HostEntry> e;
+    int64_t n;
+    fq_status st = download_main(c, e, n);
+    if (st) return st;
+    std::vector<const HostEntry *> sel;
+    for (const HostEntry &x : e) {
+        const uint32_t rep = c->rb ? (uint32_t)(x.skey >> (64 - c->rb)) : 0u;
+        if ((int)rep == instance) sel.push_back(&x);
+    }
+    std::sort(sel.begin(), sel.end(), [&](const HostEntry *a, const HostEntry *b) { return key_cmp_host(a->key, b->key, c->W) < 0; });
+    *n_out = (int64_t)sel.size();
+    if ((int64_t)sel.size() > cap) return fail(c, FQ_ECAPACITY, "export buffer too small");
+    for (size_t i = 0; i < sel.size(); ++i) {
+        if (keys)
+            for (int q = 0; q < c->W; ++q) keys[i * c->W + q] = sel[i]->key[q];
+        if (pops) pops[i] = sel[i]->pop;
+    }
+    return FQ_OK;
+}
+
+fq_status fq_import_walkers(fq_ctx *c, int32_t instance, const uint64_t *keys, const int32_t *pops, int64_t n,
+                            double shift, int64_t iteration, int32_t vary_shift, int64_t n_prev)
+{
+    if (!c || instance < 0 || instance >= c->R || n < 0 || (n > 0 && (!keys || !pops)) || iteration < 0)
+        return FQ_EINVAL;
+    std::vector<HostEntry> e;
+    int64_t m;
+    fq_status st = download_main(c, e, m);
+    if (st) return st;
+    std::vector<HostEntry> out;
+    for (const HostEntry &x : e) {
+        const uint32_t rep = c->rb ? (uint32_t)(x.skey >> (64 - c->rb)) : 0u;
+        if ((int)rep != instance) out.push_back(x);
+    }
+    std::vector<HostEntry> add;
+    for (int64_t i = 0; i < n; ++i) {
+        if (pops[i] == 0) continue;
+        HostEntry x;
+        std::memset(&x, 0, sizeof(x));
+        for (int q = 0; q < c->W; ++q) x.key[q] = keys[(size_t)i * c->W + q];
+        x.skey = host_skey(host_hash(x.key, c->W), (uint32_t)instance, c->rb);
+        x.pop = pops[i];
+        x.dslot = -1;
+        add.push_back(x);
+    }
+    std::sort(add.begin(), add.end(), [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, c->W); });
+    for (size_t i = 1; i < add.size(); ++i)
+        if (add[i].skey == add[i - 1].skey && key_cmp_host(add[i].key, add[i - 1].key, c->W) == 0)
+            return fail(c, FQ_EINVAL, "duplicate determinant in import");
+    out.insert(out.end(), add.begin(), add.end());
+    for (auto &x : out) x.dslot = -1;
+    std::sort(out.begin(), out.end(), [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, c->W); });
+    c->shift[instance] = shift;
+    c->vary[instance] = vary_shift;
+    c->nprev[instance] = n_prev;
+    c->t = iteration;
+    Ctl ctl;
+    HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    ctl.t = (uint32_t)iteration;
+    ctl.err = 0;
+    ctl.ss_active = 0;
+    HIPCHK(c, hipMemcpy(c->w.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice));
+    c->ss_active = false;
+    for (int r = 0; r < c->R; ++r) c->h_shift[r] = c->shift[r];
+    HIPCHK(c, hipMemcpy(c->w.shift, c->h_shift, 8 * c->R, hipMemcpyHostToDevice));
+    st = upload_main(c, out);
+    if (st) return st;
+    st = host_estimators(c);
+    if (st) return st;
+    if (c->has_ss && c->t >= c->ss.start_iteration) return select_detspace(c);
+    return FQ_OK;
+}
+
+fq_status fq_export_spawns(const fq_ctx *cc, int32_t instance, uint64_t *keys, int32_t *amps, uint8_t *init,
+                           int64_t cap, int64_t *n_out)
+{
+    fq_ctx *c = const_cast<fq_ctx *>(cc);
+    if (!c || instance < 0 || instance >= c->R || !n_out) return FQ_EINVAL;
+    Ctl ctl;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    const int64_t n = (int64_t)std::min<unsigned long long>(ctl.n_spawn, (unsigned long long)c->spawn_cap);
+    std::vector<uint64_t> sk(n), kk((size_t)n * c->W);
+    std::vector<uint32_t> ix(n);
+    std::vector<int32_t> am(n);
+    std::vector<uint8_t> in(n);
+    if (n) {
+        HIPCHK(c, hipMemcpy(sk.data(), c->w.sp.skey, 8 * n, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(ix.data(), c->w.sp.idx, 4 * n, hipMemcpyDeviceToHost));
+        for (int q = 0; q < c->W; ++q)
+            HIPCHK(c, hipMemcpy(kk.data() + (size_t)q * n, c->w.sp.key + (size_t)q * c->spawn_cap, 8 * n, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(am.data(), c->w.sp.amp, 4 * n, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(in.data(), c->w.sp.init, n, hipMemcpyDeviceToHost));
+    }
+    int64_t o = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        const uint32_t rep = c->rb ? (uint32_t)(sk[p] >> (64 - c->rb)) : 0u;
+        if ((int)rep != instance) continue;
+        const uint32_t j = ix[p];
+        if (o < cap) {
+            if (keys)
+                for (int q = 0; q < c->W; ++q) keys[(size_t)o * c->W + q] = kk[(size_t)q * n + j];
+            if (amps) amps[o] = am[j];
+            if (init) init[o] = in[j];
+        }
+        ++o;
+    }
+    *n_out = o;
+    return o > cap ? fail(c, FQ_ECAPACITY, "export buffer too small") : FQ_OK;
+}
+
+fq_status fq_detspace(const fq_ctx *cc, int32_t instance, uint64_t *keys, double *last_y, int64_t cap, int64_t *n_out)
+{
+    fq_ctx *c = const_cast<fq_ctx *>(cc);
+    if (!c || instance < 0 || instance >= c->R || !n_out) return FQ_EINVAL;
+    if (!c->ss_active) {
+        *n_out = 0;
+        return FQ_OK;
+    }
+    *n_out = c->D;
+    if (cap < c->D) return fail(c, FQ_ECAPACITY, "buffer too small");
+    if (keys) std::memcpy(keys, c->dkeys[instance].data(), 8 * (size_t)c->D * c->W);
+    if (last_y) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(last_y, c->w.ds.y + (size_t)instance * c->D, 8 * (size_t)c->D, hipMemcpyDeviceToHost));
+    }
+    return FQ_OK;
+}
+
+fq_status fq_info(const fq_ctx *c, int32_t *W, int32_t *n_so, double *e_ref)
+{
+    if (!c) return FQ_EINVAL;
+    if (W) *W = c->W;
+    if (n_so) *n_so = c->sys[0].n_so;
+    if (e_ref) *e_ref = c->h00v[0];
+    return FQ_OK;
+}
+
+fq_status fq_set_timing(fq_ctx *c, int32_t on)
+{
+    if (!c) return FQ_EINVAL;
+    c->timing = on != 0;
+    return FQ_OK;
+}
+
+fq_status fq_stage_times(const fq_ctx *c, double *ms7)
+{
+    if (!c || !ms7) return FQ_EINVAL;
+    std::memcpy(ms7, c->stage_ms, sizeof(c->stage_ms));
+    return FQ_OK;
+}
+
+const char *fq_last_error(const fq_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void fq_destroy(fq_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->h_ctl) hipHostFree(c->h_ctl);
+    if (c->h_hist) hipHostFree(c->h_hist);
+    if (c->h_shift) hipHostFree(c->h_shift);
+    delete c;
+}
+
+}  // extern "C"

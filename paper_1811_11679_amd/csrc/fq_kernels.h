@@ -1,0 +1,137 @@
+// Kernels of one FCIQMC projector iteration on gfx950 (declarations shared by
+// the kernel and host translation units).
+#pragma once
+
+#include "fq_device.h"
+
+namespace fq {
+
+// Per-replica run parameters (device copy).
+struct RepParams {
+    double tau;
+    double p_single;
+    int64_t cu;        // spawn cutoff in units (real mode)
+    int64_t thr;       // initiator threshold in units (strict >)
+    uint32_t k0, k1;   // Philox key
+    int32_t bits;      // fixed-point bits b
+    int32_t initiator;
+    int32_t sys;       // index of this replica's DevSys
+    int32_t pad;
+};
+
+// Error bits raised on the device; once any bit is set every later kernel
+// returns immediately, so the lists of the failing iteration's input survive.
+enum : uint32_t {
+    ERR_SPAWN_CAP = 1u,
+    ERR_MAIN_CAP = 2u,
+    ERR_OVERFLOW = 4u,
+    ERR_ATTEMPTS = 8u,
+    ERR_UNIQ_CAP = 16u,
+};
+
+enum : int {
+    TK_SCAN = 0,
+    TK_SORT = 1,   // 8 passes: 1..8
+    TK_RED1 = 9,
+    TK_RED2 = 10,
+    TK_MERGE = 11,
+    TK_COUNT = 16,
+};
+
+struct Ctl {
+    long long n_main;      // determinants in the current main list (all replicas)
+    long long n_main_new;  // written by the merge
+    long long n_att;       // total spawning attempts this iteration
+    unsigned long long n_spawn;  // spawned walkers written
+    long long n_uniq;      // distinct spawned determinants
+    uint32_t t;            // iteration counter (1 = first iteration)
+    uint32_t err;
+    uint32_t collision;    // equal sort keys with different determinants seen
+    uint32_t ss_active;
+    uint32_t tickets[TK_COUNT];
+    uint32_t hist[8][256];  // radix-sort digit histogram of the spawned keys
+};
+
+// Per-replica estimator accumulators (exact integers).
+struct EstAcc {
+    long long nw, nocc, n0, nspawn, nuniq, flips, rej_units, death_sum, spawn_sum, rej_sum;
+    long long limbs[4];
+    long long t;
+    long long pad;
+};
+constexpr int EST_FIELDS = 14;
+
+struct MainList {
+    uint64_t *skey;
+    uint64_t *key;   // word-major: key[w * cap + i]
+    int32_t *pop;
+    double *kdiag;   // H_ii - H_00
+    int32_t *dslot;  // index in the deterministic space, -1 if not in it
+    int32_t *natt;   // spawning attempts for the next iteration
+};
+
+struct SpawnList {
+    uint64_t *skey;   // sort key (replica | hash)
+    uint64_t *key;    // word-major
+    int32_t *amp;
+    uint8_t *init;
+    uint64_t *skey2;  // radix ping-pong
+    uint32_t *idx;
+    uint32_t *idx2;
+};
+
+struct UniqList {
+    uint64_t *skey;
+    uint64_t *key;  // word-major
+    long long *sum;
+    uint32_t *flag;
+};
+
+struct DetSpace {
+    int32_t n;            // D (per replica equal; total = n * R)
+    int32_t precision;
+    const double *K;      // [R][n][n] FP64 K_DD (replica-major)
+    const uint16_t *Khi;  // bf16 planes [R][n][n]
+    const uint16_t *Klo;
+    int32_t *pos;         // [R*n] position in the current main list
+    const uint64_t *h64;  // [R*n] determinant hashes (for the rounding stream)
+    double *c;            // [R*n] start-of-iteration populations
+    double *y;            // [R*n] last projection
+    long long *delta;     // [R*n] rounded projection increments
+    const uint64_t *skey_sorted;  // [R*n] sorted (skey) for membership tests
+    const uint64_t *key_sorted;   // [W][R*n]
+};
+
+struct Work {
+    Ctl *ctl;
+    EstAcc *acc;        // [R]
+    EstAcc *hist;       // [HIST][R]
+    double *shift;      // [R]
+    const RepParams *rep;  // [R]
+    const DevSys *sys;     // [n_sys]
+    long long *att_off;    // [main_cap + 1]
+    long long *span_lo;    // [spans + 1]
+    long long *mpart;      // merge partition [tiles + 1]
+    unsigned long long *st_scan, *st_sort, *st_red, *st_merge;  // look-back status
+    MainList cur, nxt;
+    SpawnList sp;
+    UniqList u;
+    DetSpace ds;
+    long long main_cap, spawn_cap, span_cap;
+    int32_t R, rb, W, hist_len;
+};
+
+// launch geometry of the persistent kernels
+struct Grids {
+    int scan, part, spawn, hist, sort, reduce, fixup, merge, det;
+};
+
+// enqueue one whole iteration on a stream (ev: 7 events or nullptr)
+hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_t s, hipEvent_t *ev);
+// set-up work: 0 = H_00 of every system, 1 = K_ii - H_00 and attempts of a
+// list of n entries, 2 = K_DD of the deterministic space
+hipError_t enqueue_setup(int what, int kind, const Work &w, DevSys *sys, int n_sys, MainList L, long long n,
+                         const uint64_t *dk, double *K, hipStream_t s);
+int occupancy_blocks(int which);
+
+}  // namespace fq

@@ -1,0 +1,1273 @@
+// Kernels of one FCIQMC projector iteration (paper Sec. 2.1 eq. fciqmc,
+// Sec. 2.4 spawning / death / annihilation, appendix "Parallelization":
+// sorted main list, spawned list sorted and merged into it), written for
+// gfx950: 64-wide wavefronts, LDS-staged tiles, persistent grids that read
+// their problem sizes from device memory, decoupled look-back for every
+// prefix that crosses tiles (Merrill & Garland 2016) and a onesweep LSD
+// radix sort (Adinets & Merrill 2022).
+#include "fq_kernels.h"
+
+#include <algorithm>
+
+namespace fq {
+
+// ---------------------------------------------------------------------------
+// decoupled look-back status words: [epoch:24 | flag:2 | value:38]
+// ---------------------------------------------------------------------------
+constexpr unsigned long long ST_AGG = 1ull, ST_INC = 2ull;
+constexpr int ST_VBITS = 38;
+constexpr unsigned long long ST_VMASK = (1ull << ST_VBITS) - 1;
+
+__device__ __forceinline__ uint32_t epoch_of(uint32_t t, uint32_t use) { return ((t << 4) | use) & 0xFFFFFFu; }
+
+__device__ __forceinline__ unsigned long long st_pack(uint32_t epoch, unsigned long long flag, long long v)
+{
+    return ((unsigned long long)epoch << 40) | (flag << ST_VBITS) | ((unsigned long long)v & ST_VMASK);
+}
+
+__device__ __forceinline__ void st_store(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long st_load(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One thread: publishes this tile's aggregate, walks back to the nearest
+// inclusive prefix, publishes its own inclusive prefix, returns the exclusive one.
+// Waits only on tiles with smaller tickets, which are resident and never wait
+// on this tile, so every wait ends.
+__device__ long long lookback(unsigned long long *st, long long tile, uint32_t epoch, long long agg)
+{
+    if (tile == 0) {
+        st_store(st, st_pack(epoch, ST_INC, agg));
+        return 0;
+    }
+    st_store(st + tile, st_pack(epoch, ST_AGG, agg));
+    long long excl = 0;
+    long long j = tile - 1;
+    for (;;) {
+        const unsigned long long s = st_load(st + j);
+        const uint32_t e = (uint32_t)(s >> 40);
+        const unsigned long long f = (s >> ST_VBITS) & 3ull;
+        if (e != epoch || f == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += (long long)(s & ST_VMASK);
+        if (f == ST_INC) break;
+        --j;
+    }
+    st_store(st + tile, st_pack(epoch, ST_INC, excl + agg));
+    return excl;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// exclusive block scan of one value per thread (blockDim = 256)
+template <typename T>
+__device__ T block_excl_scan(T v, T &total, T *lds /* 8 entries */)
+{
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    T base = 0, tot = 0;
+    const int nw = blockDim.x >> 6;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wid) base += lds[w];
+        tot += lds[w];
+    }
+    total = tot;
+    __syncthreads();
+    return base + x - v;
+}
+
+// ---------------------------------------------------------------------------
+// estimator accumulation: per-thread values, reduced over the wave when all
+// active lanes belong to one replica, else added lane by lane
+// ---------------------------------------------------------------------------
+struct LocalAcc {
+    long long v[EST_FIELDS];
+    int rep;
+    __device__ void clear()
+    {
+#pragma unroll
+        for (int i = 0; i < EST_FIELDS; ++i) v[i] = 0;
+    }
+};
+
+__device__ void flush_acc(LocalAcc &a, EstAcc *acc, bool active)
+{
+    const uint64_t act = __ballot(active);
+    if (!act) return;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const int rep0 = __shfl(a.rep, leader, 64);
+    const bool uniform = __ballot(active && a.rep != rep0) == 0;
+    long long *dst;
+    if (uniform) {
+#pragma unroll
+        for (int i = 0; i < EST_FIELDS; ++i) {
+            const long long s = wave_sum<long long>(active ? a.v[i] : 0);
+            if (lane_id() == leader && s != 0) {
+                dst = &acc[rep0].nw + i;
+                atomicAdd((unsigned long long *)dst, (unsigned long long)s);
+            }
+        }
+    } else if (active) {
+#pragma unroll
+        for (int i = 0; i < EST_FIELDS; ++i)
+            if (a.v[i] != 0) {
+                dst = &acc[a.rep].nw + i;
+                atomicAdd((unsigned long long *)dst, (unsigned long long)a.v[i]);
+            }
+    }
+    a.clear();
+}
+
+enum { F_NW = 0, F_NOCC, F_N0, F_NSPAWN, F_NUNIQ, F_FLIPS, F_REJU, F_DEATH, F_SPAWN, F_REJ, F_L0, F_L1, F_L2, F_L3 };
+
+// ---------------------------------------------------------------------------
+// iteration prologue / epilogue
+// ---------------------------------------------------------------------------
+__global__ void k_begin(Work w)
+{
+    Ctl *c = w.ctl;
+    if (c->err) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        c->t += 1;
+        c->n_main = c->n_main_new;
+        c->n_spawn = 0;
+        c->n_uniq = 0;
+        c->n_att = 0;
+        c->collision = 0;
+    }
+    for (int i = threadIdx.x; i < TK_COUNT; i += blockDim.x) c->tickets[i] = 0;
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&c->hist[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < w.R * (int)(sizeof(EstAcc) / 8); i += blockDim.x) ((long long *)w.acc)[i] = 0;
+}
+
+__global__ void k_end(Work w)
+{
+    const Ctl *c = w.ctl;
+    if (c->err) return;
+    const int slot = (int)(c->t % (uint32_t)w.hist_len);
+    for (int r = threadIdx.x; r < w.R; r += blockDim.x) {
+        EstAcc a = w.acc[r];
+        a.t = c->t;
+        w.hist[(size_t)slot * w.R + r] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// attempt scan: att_off = exclusive prefix of natt over the main list
+// ---------------------------------------------------------------------------
+constexpr int SCAN_T = 256, SCAN_I = 8, SCAN_TILE = SCAN_T * SCAN_I;
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_attempts(Work w)
+{
+    Ctl *c = w.ctl;
+    if (c->err) return;
+    const long long n = c->n_main;
+    const long long ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    const uint32_t epoch = epoch_of(c->t, 8);
+    __shared__ long long s_tile, s_base;
+    __shared__ long long s_red[8];
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[TK_SCAN], 1u);
+        __syncthreads();
+        const long long tile = s_tile;
+        if (tile >= ntiles) break;
+        const long long base = tile * SCAN_TILE + (long long)threadIdx.x * SCAN_I;
+        long long v[SCAN_I];
+        long long sum = 0;
+#pragma unroll
+        for (int i = 0; i < SCAN_I; ++i) {
+            v[i] = (base + i < n) ? (long long)w.cur.natt[base + i] : 0;
+            sum += v[i];
+        }
+        long long tot;
+        const long long ex = block_excl_scan<long long>(sum, tot, s_red);
+        if (threadIdx.x == 0) s_base = lookback(w.st_scan, tile, epoch, tot);
+        __syncthreads();
+        long long run = s_base + ex;
+#pragma unroll
+        for (int i = 0; i < SCAN_I; ++i) {
+            if (base + i < n) w.att_off[base + i] = run;
+            run += v[i];
+        }
+        if (tile == ntiles - 1 && threadIdx.x == 0) {
+            w.att_off[n] = s_base + tot;
+            c->n_att = s_base + tot;
+        }
+        __syncthreads();
+    }
+    if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        w.att_off[0] = 0;
+        c->n_att = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// spawning (Sec. 2.4): one thread per attempt, parents found through the
+// attempt prefix (load balanced: a heavily populated determinant spreads its
+// attempts over many threads and blocks)
+// ---------------------------------------------------------------------------
+constexpr int SPAN = 256;
+
+__device__ __forceinline__ long long upper_bound_ll(const long long *a, long long lo, long long hi, long long x)
+{
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_spawn_partition(Work w)
+{
+    const Ctl *c = w.ctl;
+    if (c->err) return;
+    const long long total = c->n_att, n = c->n_main;
+    const long long nspans = (total + SPAN - 1) / SPAN;
+    if (nspans + 1 > w.span_cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&((Ctl *)c)->err, ERR_SPAWN_CAP);
+        return;
+    }
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s <= nspans;
+         s += (long long)gridDim.x * blockDim.x) {
+        if (s == nspans) {
+            w.span_lo[s] = n > 0 ? n - 1 : 0;
+        } else {
+            w.span_lo[s] = upper_bound_ll(w.att_off, 0, n + 1, s * SPAN) - 1;
+        }
+    }
+}
+
+template <int KIND, int W>
+__global__ __launch_bounds__(SPAN) void k_spawn(Work w)
+{
+    Ctl *c = w.ctl;
+    if (c->err) return;
+    constexpr int LCAP = 2 * SPAN + 2;
+    __shared__ long long s_off[LCAP];
+    const long long total = c->n_att;
+    const long long nspans = (total + SPAN - 1) / SPAN;
+    if (nspans + 1 > w.span_cap) return;
+    const uint32_t t = c->t;
+    const bool ss = c->ss_active != 0;
+    for (long long span = blockIdx.x; span < nspans; span += gridDim.x) {
+        const long long lo = w.span_lo[span];
+        const long long hi = w.span_lo[span + 1];  // parent of the next span's first attempt
+        const long long len = hi - lo + 2;
+        const bool staged = len <= LCAP;
+        __syncthreads();
+        if (staged)
+            for (long long i = threadIdx.x; i < len; i += SPAN) s_off[i] = w.att_off[lo + i];
+        __syncthreads();
+        const long long a = span * SPAN + threadIdx.x;
+        bool has = false;
+        uint64_t child[W];
+        long long parent = 0;
+        int32_t amp = 0;
+        uint8_t init = 0;
+        uint32_t rep = 0;
+        if (a < total) {
+            long long i;
+            if (staged) {
+                int l = 0, h = (int)len;
+                while (l < h) {
+                    const int m = (l + h) >> 1;
+                    if (s_off[m] <= a) l = m + 1; else h = m;
+                }
+                i = lo + l - 1;
+            } else {
+                i = upper_bound_ll(w.att_off, lo, hi + 2, a) - 1;
+            }
+            parent = i;
+            const long long a0 = w.att_off[i];
+            const long long nat = w.att_off[i + 1] - a0;
+            const long long k = a - a0;
+            uint64_t key[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) key[q] = w.cur.key[(size_t)q * w.main_cap + i];
+            const int32_t n0 = w.cur.pop[i];
+            const int32_t dsl = w.cur.dslot[i];
+            rep = skey_rep(w.cur.skey[i], w.rb);
+            const RepParams rp = w.rep[rep];
+            const DevSys &sy = w.sys[rp.sys];
+            const uint64_t h = hash64<W>(key);
+            const long long an = n0 < 0 ? -(long long)n0 : (long long)n0;
+            const bool pin_d = ss && dsl >= 0;
+            init = (uint8_t)(an > rp.thr || key_eq<W>(key, *(const uint64_t(*)[W])sy.ref) || pin_d);
+            const U4 r0 = draw(TAG_SELECT, (uint32_t)k, t, h, rp.k0, rp.k1);
+            double pgen = 0.0, hv = 0.0;
+            bool ok;
+            if constexpr (KIND == K_HUBBARD)
+                ok = gen_hubbard<W>(sy, key, r0.x, child, pgen, hv);
+            else if constexpr (KIND == K_UEG)
+                ok = gen_ueg<W>(sy, key, r0.x, r0.y, child, pgen, hv);
+            else
+                ok = gen_heatbath<W>(sy, rp.p_single, key, r0, (uint32_t)k, t, h, rp.k0, rp.k1, child, pgen, hv);
+            if (ok && hv != 0.0) {
+                bool skip = false;
+                if (pin_d) {
+                    // discard spawns that stay inside the deterministic space
+                    const uint64_t cs = make_skey(hash64<W>(child), rep, w.rb);
+                    const int nd = w.ds.n * w.R;
+                    int l = 0, hh = nd;
+                    while (l < hh) {
+                        const int m = (l + hh) >> 1;
+                        const uint64_t sk = w.ds.skey_sorted[m];
+                        bool less = sk < cs;
+                        if (sk == cs) {
+                            uint64_t dk[W];
+#pragma unroll
+                            for (int q = 0; q < W; ++q) dk[q] = w.ds.key_sorted[(size_t)q * nd + m];
+                            less = key_cmp<W>(dk, child) < 0;
+                        }
+                        if (less) l = m + 1; else hh = m;
+                    }
+                    if (l < nd && w.ds.skey_sorted[l] == cs) {
+                        uint64_t dk[W];
+#pragma unroll
+                        for (int q = 0; q < W; ++q) dk[q] = w.ds.key_sorted[(size_t)q * nd + l];
+                        skip = key_eq<W>(dk, child);
+                    }
+                }
+                if (!skip) {
+                    const double ah = fabs(hv);
+                    double m;
+                    if (rp.bits == 0)
+                        m = (rp.tau * ah) / pgen;
+                    else
+                        m = (((rp.tau * ah) / pgen) * (double)an) / (double)nat;
+                    const U4 rr = draw(TAG_SPAWN_ROUND, (uint32_t)k, t, h, rp.k0, rp.k1);
+                    const double u = u53(rr.x, rr.y);
+                    long long kk = 0;
+                    if (!(m < 0x1p31)) {
+                        atomicOr(&c->err, ERR_OVERFLOW);
+                    } else {
+                        if (rp.bits != 0 && m < (double)rp.cu)
+                            kk = (u * (double)rp.cu < m) ? rp.cu : 0;
+                        else
+                            kk = sround(m, u);
+                        if (kk > 2147483647ll) {
+                            atomicOr(&c->err, ERR_OVERFLOW);
+                            kk = 0;
+                        }
+                    }
+                    if (kk != 0) {
+                        const int sh = hv > 0.0 ? 1 : -1;
+                        const int sn = n0 > 0 ? 1 : -1;
+                        amp = (int32_t)(-(long long)(sh * sn) * kk);
+                        has = true;
+                    }
+                }
+            }
+        }
+        // wave-aggregated slot reservation
+        const uint64_t msk = __ballot(has);
+        if (msk) {
+            const int leader = __ffsll((unsigned long long)msk) - 1;
+            unsigned long long base = 0;
+            if (lane_id() == leader) base = atomicAdd(&c->n_spawn, (unsigned long long)__popcll(msk));
+            base = __shfl(base, leader, 64);
+            if (has) {
+                const unsigned long long slot = base + __popcll(msk & lanemask_lt());
+                if (slot < (unsigned long long)w.spawn_cap) {
+                    const uint64_t h2 = hash64<W>(child);
+                    w.sp.skey[slot] = make_skey(h2, rep, w.rb);
+#pragma unroll
+                    for (int q = 0; q < W; ++q) w.sp.key[(size_t)q * w.spawn_cap + slot] = child[q];
+                    w.sp.amp[slot] = amp;
+                    w.sp.init[slot] = init;
+                    w.u.sum[slot] = 0;
+                    w.u.flag[slot] = 0;
+                } else {
+                    atomicOr(&c->err, ERR_SPAWN_CAP);
+                }
+            }
+        }
+        (void)parent;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// onesweep LSD radix sort of (sort key, index) pairs, 8 passes of 8 bits
+// ---------------------------------------------------------------------------
+constexpr int OS_T = 256, OS_I = 16, OS_TILE = OS_T * OS_I, OS_WAVES = OS_T / 64;
+
+__global__ __launch_bounds__(256) void k_sort_hist(Work w)
+{
+    Ctl *c = w.ctl;
+    if (c->err) return;
+    __shared__ uint32_t h[8][256];
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const long long n = (long long)min(c->n_spawn, (unsigned long long)w.spawn_cap);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const uint64_t k = w.sp.skey[i];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) {
+        const uint32_t v = (&h[0][0])[i];
+        if (v) atomicAdd(&(&c->hist[0][0])[i], v);
+    }
+}
+
+__global__ __launch_bounds__(OS_T) void k_sort_pass(Work w, int pass, const uint64_t *kin, const uint32_t *iin,
+                                                    uint64_t *kout, uint32_t *iout)
+{
+    Ctl *c = w.ctl;
+    if (c->err) return;
+    __shared__ uint64_t lk[OS_TILE];
+    __shared__ uint32_t li[OS_TILE];
+    __shared__ uint32_t wh[OS_WAVES][256];
+    __shared__ uint32_t gofs[256];     // global digit start (from the histogram)
+    __shared__ uint32_t lofs[256];     // digit start inside the tile
+    __shared__ long long gbase[256];   // tile's first output per digit
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_red[8];
+    const long long n = (long long)min(c->n_spawn, (unsigned long long)w.spawn_cap);
+    const long long ntiles = (n + OS_TILE - 1) / OS_TILE;
+    const uint32_t epoch = epoch_of(c->t, (uint32_t)pass);
+    const int shift = 8 * pass;
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    {
+        // global exclusive digit offsets of this pass
+        const uint32_t v = c->hist[pass][threadIdx.x];
+        uint32_t tot;
+        gofs[threadIdx.x] = block_excl_scan<uint32_t>(v, tot, s_red);
+    }
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[TK_SORT + pass], 1u);
+        __syncthreads();
+        const long long tile = s_tile;
+        if (tile >= ntiles) break;
+        const long long tbase = tile * OS_TILE;
+        const int tcount = (int)min((long long)OS_TILE, n - tbase);
+        for (int i = threadIdx.x; i < OS_WAVES * 256; i += OS_T) (&wh[0][0])[i] = 0;
+        __syncthreads();
+        uint64_t kk[OS_I];
+        uint32_t ix[OS_I];
+        uint32_t rk[OS_I];
+        // warp-striped sub-tile: element e = tbase + wid*64*OS_I + i*64 + lane
+#pragma unroll
+        for (int i = 0; i < OS_I; ++i) {
+            const int le = wid * 64 * OS_I + i * 64 + lane;
+            const long long e = tbase + le;
+            const bool valid = le < tcount;
+            kk[i] = valid ? kin[e] : 0;
+            ix[i] = valid ? (iin ? iin[e] : (uint32_t)e) : 0;
+            const uint32_t d = (uint32_t)(kk[i] >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const uint64_t m = __ballot((d >> b) & 1u);
+                peers &= ((d >> b) & 1u) ? m : ~m;
+            }
+            uint32_t r = 0;
+            if (valid) r = wh[wid][d] + (uint32_t)__popcll(peers & lanemask_lt());
+            __builtin_amdgcn_wave_barrier();
+            if (valid && lane == __ffsll((unsigned long long)peers) - 1) wh[wid][d] += (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+            rk[i] = r;
+        }
+        __syncthreads();
+        {
+            const int d = threadIdx.x;
+            uint32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < OS_WAVES; ++q) {
+                const uint32_t x = wh[q][d];
+                wh[q][d] = run;
+                run += x;
+            }
+            uint32_t tot;
+            const uint32_t lo = block_excl_scan<uint32_t>(run, tot, s_red);
+            lofs[d] = lo;
+            gbase[d] = run;  // temporarily the tile count
+        }
+        __syncthreads();
+        {
+            const int d = threadIdx.x;
+            const long long cnt = gbase[d];
+            unsigned long long *st = w.st_sort + (size_t)tile * 256 + d;
+            long long excl = 0;
+            if (tile == 0) {
+                st_store(st, st_pack(epoch, ST_INC, cnt));
+            } else {
+                st_store(st, st_pack(epoch, ST_AGG, cnt));
+                long long j = tile - 1;
+                for (;;) {
+                    const unsigned long long s = st_load(w.st_sort + (size_t)j * 256 + d);
+                    const uint32_t e = (uint32_t)(s >> 40);
+                    const unsigned long long f = (s >> ST_VBITS) & 3ull;
+                    if (e != epoch || f == 0) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    excl += (long long)(s & ST_VMASK);
+                    if (f == ST_INC) break;
+                    --j;
+                }
+                st_store(st, st_pack(epoch, ST_INC, excl + cnt));
+            }
+            gbase[d] = (long long)gofs[d] + excl;
+        }
+        __syncthreads();
+        // scatter into LDS in digit order (stable)
+#pragma unroll
+        for (int i = 0; i < OS_I; ++i) {
+            const int le = wid * 64 * OS_I + i * 64 + lane;
+            if (le < tcount) {
+                const uint32_t d = (uint32_t)(kk[i] >> shift) & 255u;
+                const uint32_t pos = lofs[d] + wh[wid][d] + rk[i];
+                lk[pos] = kk[i];
+                li[pos] = ix[i];
+            }
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < tcount; p += OS_T) {
+            const uint64_t k = lk[p];
+            const uint32_t d = (uint32_t)(k >> shift) & 255u;
+            const long long o = gbase[d] + (p - (long long)lofs[d]);
+            kout[o] = k;
+            iout[o] = li[p];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// segmented reduction of the sorted spawned list (Sec. 2.4 annihilation:
+// combine walkers on the same determinant): one entry per distinct
+// determinant with the int64 sum of amplitudes and the OR of initiator flags
+// ---------------------------------------------------------------------------
+constexpr int RD_T = 256, RD_I = 4, RD_TILE = RD_T * RD_I;
+
+template <int W>
+__global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
+{
+    Ctl *c = w.ctl;
+    if (c->err) return;
+    if (second && !c->collision) return;
+    __shared__ uint64_t s_lastk[RD_T][W];
+    __shared__ uint64_t s_lasts[RD_T];
+    __shared__ long long s_tile, s_base;
+    __shared__ long long s_red[8];
+    const long long n = (long long)min(c->n_spawn, (unsigned long long)w.spawn_cap);
+    const long long ntiles = (n + RD_TILE - 1) / RD_TILE;
+    const uint32_t epoch = epoch_of(c->t, second ? 10 : 9);
+    const uint64_t *skey = w.sp.skey;
+    const uint32_t *idx = w.sp.idx;
+    LocalAcc acc;
+    acc.clear();
+    acc.rep = -1;
+    bool any = false;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[second ? TK_RED2 : TK_RED1], 1u);
+        __syncthreads();
+        const long long tile = s_tile;
+        if (tile >= ntiles) break;
+        const long long base = tile * RD_TILE + (long long)threadIdx.x * RD_I;
+        uint64_t sk[RD_I], kk[RD_I][W];
+        int32_t am[RD_I];
+        uint32_t fl[RD_I];
+        bool valid[RD_I];
+#pragma unroll
+        for (int i = 0; i < RD_I; ++i) {
+            const long long e = base + i;
+            valid[i] = e < n;
+            sk[i] = 0;
+            am[i] = 0;
+            fl[i] = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) kk[i][q] = 0;
+            if (valid[i]) {
+                sk[i] = skey[e];
+                const uint32_t j = idx[e];
+#pragma unroll
+                for (int q = 0; q < W; ++q) kk[i][q] = w.sp.key[(size_t)q * w.spawn_cap + j];
+                am[i] = w.sp.amp[j];
+                fl[i] = w.sp.init[j];
+            }
+        }
+        s_lasts[threadIdx.x] = sk[RD_I - 1];
+#pragma unroll
+        for (int q = 0; q < W; ++q) s_lastk[threadIdx.x][q] = kk[RD_I - 1][q];
+        __syncthreads();
+        uint64_t psk;
+        uint64_t pk[W];
+        bool have_prev = base > 0;
+        if (threadIdx.x > 0) {
+            psk = s_lasts[threadIdx.x - 1];
+#pragma unroll
+            for (int q = 0; q < W; ++q) pk[q] = s_lastk[threadIdx.x - 1][q];
+        } else if (base > 0) {
+            psk = skey[base - 1];
+            const uint32_t j = idx[base - 1];
+#pragma unroll
+            for (int q = 0; q < W; ++q) pk[q] = w.sp.key[(size_t)q * w.spawn_cap + j];
+        } else {
+            psk = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) pk[q] = 0;
+        }
+        bool head[RD_I];
+        int nh = 0;
+#pragma unroll
+        for (int i = 0; i < RD_I; ++i) {
+            head[i] = false;
+            if (valid[i]) {
+                const bool same_s = have_prev && psk == sk[i];
+                const bool same_k = same_s && key_eq<W>(pk, kk[i]);
+                if (same_s && !same_k) atomicOr(&c->collision, 1u);
+                head[i] = !same_k;
+                nh += head[i];
+            }
+            psk = sk[i];
+#pragma unroll
+            for (int q = 0; q < W; ++q) pk[q] = kk[i][q];
+            have_prev = true;
+        }
+        long long tot;
+        const long long ex = block_excl_scan<long long>((long long)nh, tot, s_red);
+        if (threadIdx.x == 0) s_base = lookback(w.st_red, tile, epoch, tot);
+        __syncthreads();
+        long long seg = s_base + ex - 1;  // segment of the element before this thread's first
+        long long run_sum = 0;
+        uint32_t run_flag = 0;
+        long long run_seg = -1;
+#pragma unroll
+        for (int i = 0; i < RD_I; ++i) {
+            if (!valid[i]) continue;
+            if (head[i]) {
+                ++seg;
+                w.u.skey[seg] = sk[i];
+#pragma unroll
+                for (int q = 0; q < W; ++q) w.u.key[(size_t)q * w.spawn_cap + seg] = kk[i][q];
+            }
+            if (seg != run_seg) {
+                if (run_seg >= 0) {
+                    atomicAdd((unsigned long long *)&w.u.sum[run_seg], (unsigned long long)run_sum);
+                    if (run_flag) atomicOr(&w.u.flag[run_seg], run_flag);
+                }
+                run_seg = seg;
+                run_sum = 0;
+                run_flag = 0;
+            }
+            run_sum += am[i];
+            run_flag |= fl[i];
+            const int rep = (int)skey_rep(sk[i], w.rb);
+            if (rep != acc.rep) {
+                if (acc.rep >= 0) {
+#pragma unroll
+                    for (int f = 0; f < EST_FIELDS; ++f)
+                        if (acc.v[f]) atomicAdd((unsigned long long *)(&w.acc[acc.rep].nw + f), (unsigned long long)acc.v[f]);
+                    acc.clear();
+                }
+                acc.rep = rep;
+            }
+            acc.v[F_NSPAWN] += 1;
+            acc.v[F_SPAWN] += am[i];
+            acc.v[F_NUNIQ] += head[i] ? 1 : 0;
+            any = true;
+        }
+        if (run_seg >= 0) {
+            atomicAdd((unsigned long long *)&w.u.sum[run_seg], (unsigned long long)run_sum);
+            if (run_flag) atomicOr(&w.u.flag[run_seg], run_flag);
+        }
+        if (tile == ntiles - 1 && threadIdx.x == 0) c->n_uniq = s_base + tot;
+        __syncthreads();
+    }
+    flush_acc(acc, w.acc, any && acc.rep >= 0);
+}
+
+// Rare path: equal sort keys holding different determinants are put in key
+// order (insertion sort of the run), and the reduction is redone.
+template <int W>
+__global__ void k_fixup(Work w)
+{
+    Ctl *c = w.ctl;
+    if (c->err || !c->collision) return;
+    const long long n = (long long)min(c->n_spawn, (unsigned long long)w.spawn_cap);
+    uint64_t *skey = w.sp.skey;
+    uint32_t *idx = w.sp.idx;
+    const long long gs = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) {
+        w.u.sum[i] = 0;
+        w.u.flag[i] = 0;
+    }
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < w.R * (int)(sizeof(EstAcc) / 8); i += blockDim.x) {
+            const int r = i / (int)(sizeof(EstAcc) / 8), f = i % (int)(sizeof(EstAcc) / 8);
+            if (f == F_NSPAWN || f == F_NUNIQ || f == F_SPAWN) ((long long *)&w.acc[r])[f] = 0;
+        }
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) {
+        if (i > 0 && skey[i - 1] == skey[i]) continue;
+        long long e = i + 1;
+        while (e < n && skey[e] == skey[i]) ++e;
+        if (e - i < 2) continue;
+        for (long long a = i + 1; a < e; ++a) {
+            const uint32_t ja = idx[a];
+            uint64_t ka[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) ka[q] = w.sp.key[(size_t)q * w.spawn_cap + ja];
+            long long b = a - 1;
+            while (b >= i) {
+                uint64_t kb[W];
+                const uint32_t jb = idx[b];
+#pragma unroll
+                for (int q = 0; q < W; ++q) kb[q] = w.sp.key[(size_t)q * w.spawn_cap + jb];
+                if (key_cmp<W>(kb, ka) <= 0) break;
+                idx[b + 1] = jb;
+                --b;
+            }
+            idx[b + 1] = ja;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// annihilation merge (Sec. 2.4; appendix "Parallelization"): merge-path merge
+// of the distinct spawned determinants into the sorted main list, fused with
+// death/cloning of existing entries, the deterministic-space update, the
+// initiator rule for new determinants (Sec. 2.1), removal of empty entries,
+// the estimators of the new list (tutorial appendix) and the attempt counts of
+// the next iteration. Ties in the merge order put the main entry first.
+// ---------------------------------------------------------------------------
+constexpr int MG_T = 256, MG_I = 4, MG_TILE = MG_T * MG_I;
+
+template <int W>
+__device__ __forceinline__ void load_key(const uint64_t *base, long long cap, long long i, uint64_t (&k)[W])
+{
+#pragma unroll
+    for (int q = 0; q < W; ++q) k[q] = base[(size_t)q * cap + i];
+}
+
+// main[i] <= uniq[j] in (sort key, key) order
+template <int W>
+__device__ __forceinline__ bool le_ab(const Work &w, long long i, uint64_t si, long long j, uint64_t sj)
+{
+    if (si != sj) return si < sj;
+    uint64_t a[W], b[W];
+    load_key<W>(w.cur.key, w.main_cap, i, a);
+    load_key<W>(w.u.key, w.spawn_cap, j, b);
+    return key_cmp<W>(a, b) <= 0;
+}
+
+template <int W>
+__global__ void k_merge_partition(Work w)
+{
+    const Ctl *c = w.ctl;
+    if (c->err) return;
+    const long long na = c->n_main, nb = c->n_uniq;
+    const long long ntiles = (na + nb + MG_TILE - 1) / MG_TILE;
+    for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile <= ntiles;
+         tile += (long long)gridDim.x * blockDim.x) {
+        const long long d = min(tile * MG_TILE, na + nb);
+        long long lo = max(0ll, d - nb), hi = min(d, na);
+        while (lo < hi) {
+            const long long mid = (lo + hi) >> 1;
+            const long long j = d - 1 - mid;
+            if (le_ab<W>(w, mid, w.cur.skey[mid], j, w.u.skey[j])) lo = mid + 1; else hi = mid;
+        }
+        w.mpart[tile] = lo;
+    }
+}
+
+__device__ __forceinline__ void add_limbs(long long (&v)[EST_FIELDS], double x)
+{
+    if (x == 0.0) return;
+    const bool neg = x < 0.0;
+    const uint64_t bits = (uint64_t)__double_as_longlong(fabs(x));
+    const int ex = (int)((bits >> 52) & 0x7FF);
+    const uint64_t mant = (bits & ((1ull << 52) - 1)) | (ex ? (1ull << 52) : 0ull);
+    const int sh = (ex ? ex : 1) - 1075 + 64;  // |x| * 2^64 = mant * 2^sh
+    uint64_t lo = 0, hi = 0;
+    if (sh >= 64) {
+        hi = mant << (sh - 64);
+    } else if (sh > 0) {
+        lo = mant << sh;
+        hi = mant >> (64 - sh);
+    } else if (sh == 0) {
+        lo = mant;
+    } else if (sh > -64) {
+        lo = mant >> (-sh);
+    }
+    const long long l0 = (long long)(lo & 0xFFFFFFFFull), l1 = (long long)(lo >> 32);
+    const long long l2 = (long long)(hi & 0xFFFFFFFFull), l3 = (long long)(hi >> 32);
+    v[F_L0] += neg ? -l0 : l0;
+    v[F_L1] += neg ? -l1 : l1;
+    v[F_L2] += neg ? -l2 : l2;
+    v[F_L3] += neg ? -l3 : l3;
+}
+
+template <int KIND, int W>
+__global__ __launch_bounds__(MG_T) void k_merge(Work w)
+{
+    Ctl *c = w.ctl;
+    if (c->err) return;
+    __shared__ uint64_t sa[MG_TILE + 1];
+    __shared__ uint64_t sb[MG_TILE + 1];
+    __shared__ long long s_tile, s_base;
+    __shared__ long long s_red[8];
+    const long long na = c->n_main, nb = c->n_uniq;
+    const long long ntiles = (na + nb + MG_TILE - 1) / MG_TILE;
+    const uint32_t t = c->t;
+    const uint32_t epoch = epoch_of(t, 11);
+    const bool ss = c->ss_active != 0;
+    LocalAcc acc;
+    acc.clear();
+    acc.rep = -1;
+    bool any = false;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[TK_MERGE], 1u);
+        __syncthreads();
+        const long long tile = s_tile;
+        if (tile >= ntiles) break;
+        const long long d0 = tile * MG_TILE, d1 = min(d0 + MG_TILE, na + nb);
+        const long long i0 = w.mpart[tile], i1 = w.mpart[tile + 1];
+        const long long j0 = d0 - i0, j1 = d1 - i1;
+        const int la = (int)(i1 - i0), lb = (int)(j1 - j0);
+        for (int q = threadIdx.x; q < la; q += MG_T) sa[q] = w.cur.skey[i0 + q];
+        for (int q = threadIdx.x; q < lb; q += MG_T) sb[q] = w.u.skey[j0 + q];
+        __syncthreads();
+        // this thread's diagonal range inside the tile
+        const int dl = min((int)threadIdx.x * MG_I, la + lb);
+        int lo = max(0, dl - lb), hi = min(dl, la);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            const int j = dl - 1 - mid;
+            if (le_ab<W>(w, i0 + mid, sa[mid], j0 + j, sb[j])) lo = mid + 1; else hi = mid;
+        }
+        int ia = lo, jb = dl - lo;
+        // outputs of this thread
+        uint64_t osk[MG_I], okey[MG_I][W];
+        int32_t opop[MG_I], ods[MG_I];
+        double okd[MG_I];
+        int nout = 0;
+        const int steps = min(MG_I, la + lb - dl);
+        for (int s = 0; s < steps; ++s) {
+            bool takeA;
+            if (ia >= la) takeA = false;
+            else if (jb >= lb) takeA = true;
+            else takeA = le_ab<W>(w, i0 + ia, sa[ia], j0 + jb, sb[jb]);
+            if (takeA) {
+                const long long gi = i0 + ia;
+                uint64_t key[W];
+                load_key<W>(w.cur.key, w.main_cap, gi, key);
+                const uint64_t sk = sa[ia];
+                const int32_t n0 = w.cur.pop[gi];
+                const int32_t dsl = w.cur.dslot[gi];
+                const double kd = w.cur.kdiag[gi];
+                const int rep = (int)skey_rep(sk, w.rb);
+                const RepParams rp = w.rep[rep];
+                const DevSys &sy = w.sys[rp.sys];
+                if (rep != acc.rep) {
+                    if (acc.rep >= 0) {
+#pragma unroll
+                        for (int f = 0; f < EST_FIELDS; ++f)
+                            if (acc.v[f]) atomicAdd((unsigned long long *)(&w.acc[acc.rep].nw + f), (unsigned long long)acc.v[f]);
+                        acc.clear();
+                    }
+                    acc.rep = rep;
+                }
+                any = true;
+                // matching spawned determinant: the next unconsumed one
+                const long long gj = j0 + jb;
+                long long add = 0;
+                if (gj < nb && w.u.skey[gj] == sk) {
+                    uint64_t bk[W];
+                    load_key<W>(w.u.key, w.spawn_cap, gj, bk);
+                    if (key_eq<W>(bk, key)) add = w.u.sum[gj];
+                }
+                long long v;
+                if (ss && dsl >= 0) {
+                    v = (long long)n0 + w.ds.delta[(size_t)rep * w.ds.n + dsl];
+                } else if (n0 != 0) {
+                    const double an = (double)(n0 < 0 ? -(long long)n0 : (long long)n0);
+                    const double m = (rp.tau * (kd - w.shift[rep])) * an;
+                    const uint64_t h = hash64<W>(key);
+                    const U4 r = draw(TAG_DEATH, 0, t, h, rp.k0, rp.k1);
+                    const double u = u53(r.x, r.y);
+                    if (!(fabs(m) < 0x1p40)) atomicOr(&c->err, ERR_OVERFLOW);
+                    const long long k = m >= 0.0 ? sround(m, u) : -sround(-m, u);
+                    const long long sg = n0 > 0 ? 1 : -1;
+                    v = (long long)n0 - sg * k;
+                    if ((v > 0 && n0 < 0) || (v < 0 && n0 > 0)) acc.v[F_FLIPS] += 1;
+                } else {
+                    v = 0;
+                }
+                acc.v[F_DEATH] += v;
+                v += add;
+                if (v > 2147483647ll || v < -2147483647ll) atomicOr(&c->err, ERR_OVERFLOW);
+                if (v != 0 || dsl >= 0) {
+                    osk[nout] = sk;
+#pragma unroll
+                    for (int q = 0; q < W; ++q) okey[nout][q] = key[q];
+                    opop[nout] = (int32_t)v;
+                    okd[nout] = kd;
+                    ods[nout] = dsl;
+                    ++nout;
+                }
+                ++ia;
+            } else {
+                const long long gj = j0 + jb;
+                const uint64_t sk = sb[jb];
+                uint64_t key[W];
+                load_key<W>(w.u.key, w.spawn_cap, gj, key);
+                // matched with the previous main entry: handled there
+                const long long gi = i0 + ia - 1;
+                bool matched = false;
+                if (gi >= 0 && w.cur.skey[gi] == sk) {
+                    uint64_t ak[W];
+                    load_key<W>(w.cur.key, w.main_cap, gi, ak);
+                    matched = key_eq<W>(ak, key);
+                }
+                if (!matched) {
+                    const long long sum = w.u.sum[gj];
+                    const uint32_t fl = w.u.flag[gj];
+                    const int rep = (int)skey_rep(sk, w.rb);
+                    const RepParams rp = w.rep[rep];
+                    const DevSys &sy = w.sys[rp.sys];
+                    if (rep != acc.rep) {
+                        if (acc.rep >= 0) {
+#pragma unroll
+                            for (int f = 0; f < EST_FIELDS; ++f)
+                                if (acc.v[f]) atomicAdd((unsigned long long *)(&w.acc[acc.rep].nw + f), (unsigned long long)acc.v[f]);
+                            acc.clear();
+                        }
+                        acc.rep = rep;
+                    }
+                    any = true;
+                    const bool accept = (!rp.initiator || fl) && sum != 0;
+                    if (accept) {
+                        if (sum > 2147483647ll || sum < -2147483647ll) atomicOr(&c->err, ERR_OVERFLOW);
+                        osk[nout] = sk;
+#pragma unroll
+                        for (int q = 0; q < W; ++q) okey[nout][q] = key[q];
+                        opop[nout] = (int32_t)sum;
+                        okd[nout] = diag_element<KIND, W>(sy, key) - sy.H00;
+                        ods[nout] = -1;
+                        ++nout;
+                    } else {
+                        acc.v[F_REJU] += sum < 0 ? -sum : sum;
+                        acc.v[F_REJ] += sum;
+                    }
+                }
+                ++jb;
+            }
+        }
+        long long tot;
+        const long long ex = block_excl_scan<long long>((long long)nout, tot, s_red);
+        if (threadIdx.x == 0) s_base = lookback(w.st_merge, tile, epoch, tot);
+        __syncthreads();
+        const long long obase = s_base + ex;
+        for (int q = 0; q < nout; ++q) {
+            const long long o = obase + q;
+            if (o >= w.main_cap) {
+                atomicOr(&c->err, ERR_MAIN_CAP);
+                break;
+            }
+            const int rep = (int)skey_rep(osk[q], w.rb);
+            const RepParams rp = w.rep[rep];
+            const DevSys &sy = w.sys[rp.sys];
+            w.nxt.skey[o] = osk[q];
+#pragma unroll
+            for (int x = 0; x < W; ++x) w.nxt.key[(size_t)x * w.main_cap + o] = okey[q][x];
+            const int32_t p = opop[q];
+            w.nxt.pop[o] = p;
+            w.nxt.kdiag[o] = okd[q];
+            w.nxt.dslot[o] = ods[q];
+            if (ods[q] >= 0) w.ds.pos[(size_t)rep * w.ds.n + ods[q]] = (int32_t)o;
+            const long long ap = p < 0 ? -(long long)p : (long long)p;
+            long long nat;
+            if (rp.bits == 0) {
+                nat = ap;
+                if (ap >= (1ll << 28)) atomicOr(&c->err, ERR_ATTEMPTS);
+            } else {
+                nat = (ap + (1ll << rp.bits) - 1) >> rp.bits;
+            }
+            w.nxt.natt[o] = (int32_t)nat;
+            if (rep != acc.rep) {
+                if (acc.rep >= 0) {
+#pragma unroll
+                    for (int f = 0; f < EST_FIELDS; ++f)
+                        if (acc.v[f]) atomicAdd((unsigned long long *)(&w.acc[acc.rep].nw + f), (unsigned long long)acc.v[f]);
+                    acc.clear();
+                }
+                acc.rep = rep;
+            }
+            any = true;
+            acc.v[F_NW] += ap;
+            acc.v[F_NOCC] += 1;
+            const uint64_t(&ref)[W] = *(const uint64_t(*)[W])sy.ref;
+            int nd = 0;
+#pragma unroll
+            for (int x = 0; x < W; ++x) nd += __popcll(okey[q][x] ^ ref[x]);
+            if (nd == 0) {
+                acc.v[F_N0] += p;
+            } else if (nd == 2 || nd == 4) {
+                const double hv = hij<KIND, W>(sy, ref, okey[q]);
+                add_limbs(acc.v, hv * (double)p);
+            }
+        }
+        if (tile == ntiles - 1 && threadIdx.x == 0) c->n_main_new = s_base + tot;
+        __syncthreads();
+    }
+    flush_acc(acc, w.acc, any && acc.rep >= 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ntiles == 0) c->n_main_new = 0;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic projection (Sec. 2.1 semi-stochastic): y = K_DD n_D with 64
+// interleaved partial sums (j = lane mod 64) taken in increasing j, combined
+// by a fixed halving tree; then n_D += SR(-dtau (y - S n_D))
+// ---------------------------------------------------------------------------
+__global__ void k_det_gather(Work w)
+{
+    const Ctl *c = w.ctl;
+    if (c->err || !c->ss_active) return;
+    const int nd = w.ds.n * w.R;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x)
+        w.ds.c[i] = (double)w.cur.pop[w.ds.pos[i]];
+}
+
+__global__ __launch_bounds__(256) void k_det_project_fp64(Work w)
+{
+    const Ctl *c = w.ctl;
+    if (c->err || !c->ss_active) return;
+    const int n = w.ds.n;
+    const int lane = lane_id();
+    const long long rows = (long long)n * w.R;
+    for (long long row = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < rows;
+         row += (long long)gridDim.x * (blockDim.x >> 6)) {
+        const int rep = (int)(row / n), d = (int)(row % n);
+        const double *K = w.ds.K + ((size_t)rep * n + d) * n;
+        const double *cv = w.ds.c + (size_t)rep * n;
+        double part = 0.0;
+        for (int j = lane; j < n; j += 64) part = part + K[j] * cv[j];
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const double o = __shfl_down(part, step, 64);
+            if (lane < step) part = part + o;
+        }
+        if (lane == 0) {
+            const RepParams rp = w.rep[rep];
+            const double nv = cv[d];
+            const double delta = (-rp.tau) * (part - w.shift[rep] * nv);
+            const U4 r = draw(TAG_SEMISTOCH, 0, c->t, w.ds.h64[row], rp.k0, rp.k1);
+            const double u = u53(r.x, r.y);
+            if (!(fabs(delta) < 0x1p40)) atomicOr(&((Ctl *)c)->err, ERR_OVERFLOW);
+            const long long k = delta >= 0.0 ? sround(delta, u) : -sround(-delta, u);
+            w.ds.y[row] = part;
+            w.ds.delta[row] = k;
+        }
+    }
+}
+
+// explicit instantiations
+#define FQ_INST(KIND, W)                                   \
+    template __global__ void k_spawn<KIND, W>(Work);       \
+    template __global__ void k_merge<KIND, W>(Work);
+FQ_INST(K_HUBBARD, 1)
+FQ_INST(K_UEG, 1)
+FQ_INST(K_UEG, 2)
+FQ_INST(K_UEG, 4)
+FQ_INST(K_UEG, 8)
+FQ_INST(K_MOLECULAR, 1)
+FQ_INST(K_MOLECULAR, 2)
+#define FQ_INSTW(W)                                        \
+    template __global__ void k_reduce<W>(Work, int);       \
+    template __global__ void k_fixup<W>(Work);             \
+    template __global__ void k_merge_partition<W>(Work);
+FQ_INSTW(1)
+FQ_INSTW(2)
+FQ_INSTW(4)
+FQ_INSTW(8)
+
+}  // namespace fq
+
+// ---------------------------------------------------------------------------
+// set-up kernels: H_00 per system, K_ii - H_00 and attempt counts of a list,
+// K_DD of a deterministic space
+// ---------------------------------------------------------------------------
+namespace fq {
+
+template <int KIND, int W>
+__global__ void k_h00(DevSys *sys, int n_sys)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_sys) return;
+    uint64_t ref[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) ref[q] = sys[i].ref[q];
+    sys[i].H00 = diag_element<KIND, W>(sys[i], ref);
+}
+
+template <int KIND, int W>
+__global__ void k_kdiag(Work w, MainList L, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        uint64_t key[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) key[q] = L.key[(size_t)q * w.main_cap + i];
+        const int rep = (int)skey_rep(L.skey[i], w.rb);
+        const RepParams rp = w.rep[rep];
+        const DevSys &sy = w.sys[rp.sys];
+        L.kdiag[i] = diag_element<KIND, W>(sy, key) - sy.H00;
+        const int32_t p = L.pop[i];
+        const long long ap = p < 0 ? -(long long)p : (long long)p;
+        L.natt[i] = (int32_t)(rp.bits == 0 ? ap : ((ap + (1ll << rp.bits) - 1) >> rp.bits));
+    }
+}
+
+// K[rep][d][e] = <D_d|H|D_e> - H_00 delta_de for D keys given in D order
+template <int KIND, int W>
+__global__ void k_build_kdd(Work w, const uint64_t *dkeys /* [W][R*n] */, double *K)
+{
+    const int n = w.ds.n;
+    const int nd = n * w.R;
+    const long long tot = (long long)w.R * n * n;
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < tot; x += (long long)gridDim.x * blockDim.x) {
+        const int rep = (int)(x / ((long long)n * n));
+        const int d = (int)((x / n) % n), e = (int)(x % n);
+        uint64_t a[W], b[W];
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            a[q] = dkeys[(size_t)q * nd + (size_t)rep * n + d];
+            b[q] = dkeys[(size_t)q * nd + (size_t)rep * n + e];
+        }
+        const DevSys &sy = w.sys[w.rep[rep].sys];
+        double v;
+        if (d == e)
+            v = diag_element<KIND, W>(sy, a) - sy.H00;
+        else
+            v = hij<KIND, W>(sy, a, b);
+        K[x] = v;
+    }
+}
+
+#define FQ_INST2(KIND, W)                                                     \
+    template __global__ void k_h00<KIND, W>(DevSys *, int);                 \
+    template __global__ void k_kdiag<KIND, W>(Work, MainList, long long);   \
+    template __global__ void k_build_kdd<KIND, W>(Work, const uint64_t *, double *);
+FQ_INST2(K_HUBBARD, 1)
+FQ_INST2(K_UEG, 1)
+FQ_INST2(K_UEG, 2)
+FQ_INST2(K_UEG, 4)
+FQ_INST2(K_UEG, 8)
+FQ_INST2(K_MOLECULAR, 1)
+FQ_INST2(K_MOLECULAR, 2)
+
+// ---------------------------------------------------------------------------
+// launchers used by the host library
+// ---------------------------------------------------------------------------
+template <int KIND, int W>
+static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t *ev)
+{
+    auto rec = [&](int i) {
+        if (ev) hipEventRecord(ev[i], s);
+    };
+    rec(0);
+    k_begin<<<1, 256, 0, s>>>(w);
+    k_scan_attempts<<<g.scan, SCAN_T, 0, s>>>(w);
+    k_spawn_partition<<<g.part, 256, 0, s>>>(w);
+    rec(1);
+    k_spawn<KIND, W><<<g.spawn, SPAN, 0, s>>>(w);
+    rec(2);
+    k_sort_hist<<<g.hist, 256, 0, s>>>(w);
+    uint64_t *K[2] = {w.sp.skey, w.sp.skey2};
+    uint32_t *I[2] = {w.sp.idx, w.sp.idx2};
+    for (int p = 0; p < 8; ++p)
+        k_sort_pass<<<g.sort, OS_T, 0, s>>>(w, p, K[p & 1], p == 0 ? nullptr : I[p & 1], K[(p + 1) & 1],
+                                             I[(p + 1) & 1]);
+    rec(3);
+    k_reduce<W><<<g.reduce, RD_T, 0, s>>>(w, 0);
+    k_fixup<W><<<g.fixup, 256, 0, s>>>(w);
+    k_reduce<W><<<g.reduce, RD_T, 0, s>>>(w, 1);
+    rec(4);
+    k_det_gather<<<g.det, 256, 0, s>>>(w);
+    k_det_project_fp64<<<g.det, 256, 0, s>>>(w);
+    rec(5);
+    k_merge_partition<W><<<g.part, 256, 0, s>>>(w);
+    k_merge<KIND, W><<<g.merge, MG_T, 0, s>>>(w);
+    k_end<<<1, 64, 0, s>>>(w);
+    rec(6);
+}
+
+hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_t s, hipEvent_t *ev)
+{
+    switch (kind * 16 + w.W) {
+    case K_HUBBARD * 16 + 1: launch_kind<K_HUBBARD, 1>(w, g, s, ev); break;
+    case K_UEG * 16 + 1: launch_kind<K_UEG, 1>(w, g, s, ev); break;
+    case K_UEG * 16 + 2: launch_kind<K_UEG, 2>(w, g, s, ev); break;
+    case K_UEG * 16 + 4: launch_kind<K_UEG, 4>(w, g, s, ev); break;
+    case K_UEG * 16 + 8: launch_kind<K_UEG, 8>(w, g, s, ev); break;
+    case K_MOLECULAR * 16 + 1: launch_kind<K_MOLECULAR, 1>(w, g, s, ev); break;
+    case K_MOLECULAR * 16 + 2: launch_kind<K_MOLECULAR, 2>(w, g, s, ev); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int KIND, int W>
+static void setup_kind(int what, const Work &w, DevSys *sys, int n_sys, MainList L, long long n, const uint64_t *dk,
+                       double *K, hipStream_t s)
+{
+    if (what == 0) k_h00<KIND, W><<<(n_sys + 63) / 64, 64, 0, s>>>(sys, n_sys);
+    if (what == 1 && n > 0) k_kdiag<KIND, W><<<(int)std::min<long long>((n + 255) / 256, 4096), 256, 0, s>>>(w, L, n);
+    if (what == 2) k_build_kdd<KIND, W><<<2048, 256, 0, s>>>(w, dk, K);
+}
+
+hipError_t enqueue_setup(int what, int kind, const Work &w, DevSys *sys, int n_sys, MainList L, long long n,
+                         const uint64_t *dk, double *K, hipStream_t s)
+{
+    switch (kind * 16 + w.W) {
+    case K_HUBBARD * 16 + 1: setup_kind<K_HUBBARD, 1>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case K_UEG * 16 + 1: setup_kind<K_UEG, 1>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case K_UEG * 16 + 2: setup_kind<K_UEG, 2>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case K_UEG * 16 + 4: setup_kind<K_UEG, 4>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case K_UEG * 16 + 8: setup_kind<K_UEG, 8>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case K_MOLECULAR * 16 + 1: setup_kind<K_MOLECULAR, 1>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case K_MOLECULAR * 16 + 2: setup_kind<K_MOLECULAR, 2>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int occupancy_blocks(int which)
+{
+    int nb = 1;
+    switch (which) {
+    case 0: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass, OS_T, 0); break;
+    case 1: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2>, MG_T, 0); break;
+    case 2: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce<2>, RD_T, 0); break;
+    case 3: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan_attempts, SCAN_T, 0); break;
+    default: break;
+    }
+    return nb < 1 ? 1 : nb;
+}
+
+}  // namespace fq

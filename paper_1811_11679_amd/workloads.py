@@ -1,0 +1,43 @@
+"""Run parameters of the synthetic workloads (plain values, no arithmetic).
+
+Each entry gives the system description and the qmc parameters in the units of
+the paper's input tables (tutorial appendix): walkers, Hartree, iterations.
+"""
+
+# 1D Hubbard ring, 8 sites, U/t = 4, half filling: 4900 determinants
+HUBBARD8 = dict(
+    system=dict(kind="hubbard", n_sites=8, periodic=1, t=1.0, U=4.0, n_alpha=4, n_beta=4),
+    qmc=dict(tau=0.01, rng_seed=7, init_pop=500.0, target_population=1e4, shift_period=10,
+             shift_damping=0.05, initial_shift=-4.0, initiator=0, fixed_point_bits=0, spawn_cutoff=0.0),
+    iterations=2000,
+)
+
+# 3D uniform electron gas: 14 electrons, rs = 1, 57 plane waves (114 spin-orbitals)
+UEG14 = dict(
+    system=dict(kind="ueg", rs=1.0, ecut_n2=5, n_alpha=7, n_beta=7),
+    qmc=dict(tau=0.002, rng_seed=7, init_pop=5e5, target_population=1e7, shift_period=10,
+             shift_damping=0.05, initial_shift=0.0, initiator=1, initiator_threshold=3.0,
+             fixed_point_bits=8, spawn_cutoff=0.1),
+    iterations=5000,
+)
+
+# molecular-like Hamiltonian: 30 orbitals, 8 + 8 electrons, heat-bath generator
+MOL30 = dict(
+    system=dict(kind="molecular", n_orb=30, n_alpha=8, n_beta=8),
+    qmc=dict(tau=0.001, rng_seed=7, init_pop=5e5, target_population=1e7, shift_period=10,
+             shift_damping=0.05, initial_shift=0.0, p_single=0.1, initiator=1, initiator_threshold=3.0,
+             fixed_point_bits=8, spawn_cutoff=0.1),
+    semistoch=dict(size=2000, start_iteration=1000),
+    iterations=2000,
+)
+
+# large UEG: 54 electrons, 251 plane waves (502 spin-orbitals)
+UEG54 = dict(
+    system=dict(kind="ueg", rs=1.0, ecut_n2=14, n_alpha=27, n_beta=27),
+    qmc=dict(tau=0.0005, rng_seed=7, init_pop=1e6, target_population=2e8, shift_period=10,
+             shift_damping=0.05, initial_shift=0.0, initiator=1, initiator_threshold=3.0,
+             fixed_point_bits=8, spawn_cutoff=0.1),
+    iterations=500,
+)
+
+UEG_ECUT_FOR_BASIS = {19: 2, 27: 3, 57: 5, 123: 9}

@@ -1,0 +1,48 @@
+"""The C-ABI library loads on any host and exports every function its header declares."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fciqmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fq_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_api():
+    from paper_1811_11679_amd import fciqmc as F
+    assert _declared() == sorted(F.C_API)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1811_11679_amd import fciqmc as F
+    if not os.path.exists(F.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(F.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_size_and_argument_checks():
+    from paper_1811_11679_amd import fciqmc as F
+    if not os.path.exists(F.LIB_PATH):
+        pytest.skip("library not built")
+    L = F.load_library()
+    s, _ = F.make_system(F.UEG, rs=1.0, ecut_n2=5, n_alpha=7, n_beta=7)
+    q = F.make_qmc(excit_gen=2, fixed_point_bits=8)
+    arr = (F.System * 1)(s)
+    qa = (F.Qmc * 1)(q)
+    b1 = L.fq_workspace_bytes(arr, qa, None, 1, 1 << 20, 1 << 20)
+    b2 = L.fq_workspace_bytes(arr, qa, None, 1, 1 << 21, 1 << 21)
+    assert b1 > 0 and b2 > 1.9 * b1 - (1 << 20)
+    bad, _ = F.make_system(F.UEG, rs=1.0, ecut_n2=0, n_alpha=7, n_beta=7)
+    assert L.fq_workspace_bytes((F.System * 1)(bad), qa, None, 1, 1 << 20, 1 << 20) == 0
+    ctx = ctypes.c_void_p()
+    # invalid arguments are rejected before any device call
+    assert L.fq_init_system(ctypes.byref(ctx), arr, qa, None, 1, 0, 100, None, 0, None) == F.FQ_EINVAL
+    assert L.fq_step(None, 1) == F.FQ_EINVAL
