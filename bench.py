@@ -1,0 +1,174 @@
+#!/usr/bin/env python
+"""FCIQMC iteration throughput on one MI355X.
+
+Workload: initiator FCIQMC on the 3D uniform electron gas, 14 electrons
+(7 + 7), rs = 1, 57 plane waves (114 spin-orbitals, two-word keys), Coulomb
+4 pi / (L^3 k^2), real weights in 1/256 units, spawn cutoff 0.1, initiator
+threshold 3, dtau = 0.002, target 1e7 walkers, shift varied every 10
+iterations with damping 0.05; synthetic (the system is defined by its
+parameters). One step = one whole projector iteration: attempt scan,
+spawning, radix sort, segmented reduction, merge with death/initiator,
+estimators and the host shift update.
+
+Prints one JSON line: walker updates/s = sum over the timed iterations of the
+walker population at the start of each iteration, divided by the wall time.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "walker updates/s per FCIQMC iteration, plain vs batched; annihilation HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(hist_prev, hist, W):
+    """Bytes each kernel must move per iteration (reads + writes of the data it owns)."""
+    out = {}
+    nm, nm2 = hist_prev["n_occupied"], hist["n_occupied"]
+    ns, nu = hist["n_spawned"], hist["n_spawn_events"]
+    kb = 8 * W
+    out["scan_attempts"] = nm * (4 + 8)
+    out["spawn"] = nm * (kb + 8 + 4 + 4 + 8) + ns * (8 + kb + 4 + 1 + 8 + 4)
+    out["sort_pass0"] = ns * (8 + 8 + 4)
+    for p in range(1, 8):
+        out[f"sort_pass{p}"] = ns * (8 + 4) * 2
+    out["sort_hist"] = ns * 8
+    out["reduce"] = ns * (8 + 4 + kb + 4 + 1) + nu * (8 + kb + 8 + 4)
+    out["merge"] = nm * (8 + kb + 4 + 8 + 4) + nu * (8 + kb + 8 + 4) + nm2 * (8 + kb + 4 + 8 + 4 + 4)
+    return out
+
+
+def cpu_baseline(budget_s=15.0, max_iter=400):
+    """The oracle on the same workload from its initial state, single thread."""
+    from oracle import oracle as O
+    from paper_1811_11679_amd import workloads
+    w = workloads.UEG14
+    s, q = w["system"], w["qmc"]
+    sysd = O.System.ueg(s["rs"], s["ecut_n2"], s["n_alpha"], s["n_beta"])
+    run = O.Run(sysd, O.make_qmc(tau=q["tau"], seed=q["rng_seed"], init_pop=q["init_pop"],
+                                 target_population=q["target_population"], shift_period=q["shift_period"],
+                                 shift_damping=q["shift_damping"], excit_gen=O.EXGEN_UEG, initiator=1,
+                                 initiator_threshold=q["initiator_threshold"], fixed_point_bits=8,
+                                 spawn_cutoff=q["spawn_cutoff"]))
+    nw_prev = run.estimators()["n_walkers_units"]
+    upd, it = 0.0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and it < max_iter:
+        run.step(1)
+        upd += nw_prev / 256.0
+        nw_prev = run.estimators()["n_walkers_units"]
+        it += 1
+    dt = time.perf_counter() - t0
+    return {"value": upd / dt, "unit": "walker updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {it} iterations of the same workload from its initial state "
+                      f"({run.estimators()['n_occupied']} determinants at the end), single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=4000)
+    ap.add_argument("--main-capacity", type=int, default=1 << 28)
+    ap.add_argument("--spawn-capacity", type=int, default=1 << 27)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded path is a design, "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1811_11679_amd import fciqmc as F
+    from paper_1811_11679_amd import workloads
+
+    w = workloads.UEG14
+    s, q = w["system"], dict(w["qmc"])
+    sysd = F.make_system(F.UEG, rs=s["rs"], ecut_n2=s["ecut_n2"], n_alpha=s["n_alpha"], n_beta=s["n_beta"])
+    ctx = F.Context([sysd], [F.make_qmc(excit_gen=2, **q)], main_capacity=args.main_capacity,
+                    spawn_capacity=args.spawn_capacity)
+    t_w0 = time.perf_counter()
+    done = 0
+    while done < args.warmup:
+        k = min(250, args.warmup - done)
+        ctx.step(k)
+        done += k
+        e = ctx.estimators()
+        print(f"# warmup {done}: N_w {e['n_walkers_units'] / 256:.4g} walkers, "
+              f"{e['n_occupied']} determinants, shift {e['shift']:.5f}, "
+              f"{time.perf_counter() - t_w0:.1f} s", file=sys.stderr, flush=True)
+    warm_s = time.perf_counter() - t_w0
+    e_start = ctx.estimators()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    hist = ctx.history()[-args.steps:]
+    prev = [e_start] + hist[:-1]
+    upd = sum(h["n_walkers_units"] for h in prev) / 256.0
+    dt = t1 - t0
+    ktimes, niter = ctx.kernel_times()
+    stages = ctx.stage_times()
+    # algorithmic bytes per kernel summed over the timed iterations
+    tot_bytes = {}
+    for a, b in zip(prev, hist):
+        for k, v in algorithmic_bytes(a, b, ctx.W).items():
+            tot_bytes[k] = tot_bytes.get(k, 0) + v
+    groups = {"sort_pass": [f"sort_pass{p}" for p in range(8)]}
+    cand = {"spawn": ["spawn"], "merge": ["merge"], "reduce": ["reduce"], "scan_attempts": ["scan_attempts"],
+            **groups}
+    best = max(cand, key=lambda g: sum(ktimes[k] for k in cand[g]))
+    launches = niter * len(cand[best])
+    avg_ms = sum(ktimes[k] for k in cand[best]) / max(launches, 1)
+    bytes_per_launch = sum(tot_bytes[k] for k in cand[best]) / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    ann_ms = stages["sort"] + stages["reduce"] + stages["merge"]
+    ann_bytes = sum(tot_bytes[k] for k in tot_bytes if k.startswith("sort") or k in ("reduce", "merge"))
+    out = {
+        "metric": METRIC,
+        "value": upd / dt,
+        "unit": "walker updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ueg14_rs1_57pw_initiator_target1e7", "electrons": 14, "rs": 1.0,
+                   "plane_waves": 57, "key_words": ctx.W, "tau": q["tau"], "fixed_point": "1/256",
+                   "initiator_threshold": 3.0, "target_walkers": q["target_population"],
+                   "timed_iterations": f"{e_start['iteration'] + 1}..{hist[-1]['iteration']}",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": best, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch},
+        "annihilation_gbps_algorithmic": ann_bytes / (ann_ms * 1e-3) / 1e9 if ann_ms > 0 else None,
+        "stage_ms_per_iteration": {k: v / max(niter, 1) for k, v in stages.items()},
+        "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in ktimes.items()},
+        "walkers_start": e_start["n_walkers_units"] / 256.0,
+        "walkers_end": hist[-1]["n_walkers_units"] / 256.0,
+        "determinants_end": hist[-1]["n_occupied"],
+        "spawned_per_iteration": sum(h["n_spawned"] for h in hist) / len(hist),
+        "shift_end": hist[-1]["shift"],
+        "proj_energy_end": hist[-1]["proj_energy"],
+        "warmup_s": warm_s,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

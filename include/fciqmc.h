@@ -204,6 +204,15 @@ fq_status fq_info(const fq_ctx *ctx, int32_t *W, int32_t *n_spin_orbitals, doubl
 fq_status fq_set_timing(fq_ctx *ctx, int32_t on);
 fq_status fq_stage_times(const fq_ctx *ctx, double *ms7);
 
+/* Per-kernel device time of the last fq_step call (timing on), summed over its
+ * iterations, one slot per launch of an iteration in launch order: begin,
+ * attempt scan, attempt partition, spawn, sort histogram, sort passes 0..7,
+ * reduce, collision fix-up, reduce (repeat), projection gather, projection,
+ * merge partition, merge, end. *n_slots receives the slot count (21) and
+ * *n_iterations the number of timed iterations. */
+fq_status fq_kernel_times(const fq_ctx *ctx, double *ms, int32_t cap, int32_t *n_slots,
+                          int64_t *n_iterations);
+
 const char *fq_last_error(const fq_ctx *ctx);
 void fq_destroy(fq_ctx *ctx);
 

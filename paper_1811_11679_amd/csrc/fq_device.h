@@ -221,9 +221,10 @@ struct DevSys {
     int32_t periodic;
     double t, U;
     int32_t gmax, gdim, vlen, pad0;
-    const int8_t *nvec;   // [M][3] plane-wave integer vectors
+    const int32_t *npk;   // [M] plane-wave vectors, 10 bits per component biased by 256
     const double *eps;    // kinetic energy per plane wave
     const double *vtab;   // v(|dn|^2)
+    const double *vx;     // [M][M] v(|n_p - n_q|^2) (0 on the diagonal)
     const int16_t *grid;  // momentum grid -> plane-wave index, -1 outside
     const double *h1;     // [n][n]
     const double *eri;    // [n][n][n][n] chemists' notation
@@ -244,13 +245,9 @@ __device__ __forceinline__ double eri_at(const DevSys &s, int p, int q, int r, i
     return s.eri[(((size_t)p * n + q) * n + r) * n + t];
 }
 
-__device__ __forceinline__ int dn2(const DevSys &s, int p, int q)
-{
-    const int dx = (int)s.nvec[3 * p] - (int)s.nvec[3 * q];
-    const int dy = (int)s.nvec[3 * p + 1] - (int)s.nvec[3 * q + 1];
-    const int dz = (int)s.nvec[3 * p + 2] - (int)s.nvec[3 * q + 2];
-    return dx * dx + dy * dy + dz * dz;
-}
+// packed plane-wave vectors: component c in bits [10c, 10c + 10), biased by 256;
+// sums and differences of a few vectors stay inside each 10-bit field
+__device__ __forceinline__ int pk_comp(int32_t v, int c) { return ((v >> (10 * c)) & 1023) - 256; }
 
 // calls f(P) for every set bit P of a key, in ascending order
 template <int W, typename F>
@@ -291,9 +288,10 @@ __device__ double diag_element(const DevSys &s, const uint64_t (&key)[W])
             if (((k >> (2 * p)) & 1) && ((k >> (2 * p + 1)) & 1)) e = e + s.U;
         return e;
     } else if constexpr (KIND == K_UEG) {
+        const int M = s.n_spatial;
         for_bits<W>(key, [&](int P) { e = e + s.eps[P >> 1]; });
         for_pairs<W>(key, [&](int P, int Q) {
-            if ((P & 1) == (Q & 1)) e = e - s.vtab[dn2(s, P >> 1, Q >> 1)];
+            if ((P & 1) == (Q & 1)) e = e - s.vx[(P >> 1) * M + (Q >> 1)];
         });
         return e;
     } else {
@@ -318,11 +316,10 @@ __device__ __forceinline__ double antisym(const DevSys &s, int A, int B, int P, 
     if constexpr (KIND == K_HUBBARD) {
         return 0.0;
     } else if constexpr (KIND == K_UEG) {
-        for (int c = 0; c < 3; ++c)
-            if ((int)s.nvec[3 * a + c] + (int)s.nvec[3 * b + c] != (int)s.nvec[3 * p + c] + (int)s.nvec[3 * q + c])
-                return 0.0;
-        const double x = (sa == sp && sb == sq) ? s.vtab[dn2(s, p, a)] : 0.0;
-        const double y = (sa == sq && sb == sp) ? s.vtab[dn2(s, q, a)] : 0.0;
+        if (s.npk[a] + s.npk[b] != s.npk[p] + s.npk[q]) return 0.0;  // momentum conservation
+        const int M = s.n_spatial;
+        const double x = (sa == sp && sb == sq) ? s.vx[p * M + a] : 0.0;
+        const double y = (sa == sq && sb == sp) ? s.vx[q * M + a] : 0.0;
         return x - y;
     } else {
         const double x = (sa == sp && sb == sq) ? eri_at(s, a, p, b, q) : 0.0;
@@ -485,9 +482,8 @@ __device__ bool gen_ueg(const DevSys &s, const uint64_t (&D)[W], uint32_t w0, ui
     }
     const int sA = A & 1, sB = sP + sQ - sA;
     const int p = P >> 1, q = Q >> 1, a = A >> 1;
-    const int bx = (int)s.nvec[3 * p] + (int)s.nvec[3 * q] - (int)s.nvec[3 * a];
-    const int by = (int)s.nvec[3 * p + 1] + (int)s.nvec[3 * q + 1] - (int)s.nvec[3 * a + 1];
-    const int bz = (int)s.nvec[3 * p + 2] + (int)s.nvec[3 * q + 2] - (int)s.nvec[3 * a + 2];
+    const int32_t bp = s.npk[p] + s.npk[q] - s.npk[a];
+    const int bx = pk_comp(bp, 0), by = pk_comp(bp, 1), bz = pk_comp(bp, 2);
     const int g = s.gmax;
     if (bx < -g || bx > g || by < -g || by > g || bz < -g || bz > g) return false;
     const int b = s.grid[((bx + g) * s.gdim + (by + g)) * s.gdim + (bz + g)];

@@ -70,8 +70,8 @@ struct HostSys {
     int kind = 0, n_spatial = 0, n_so = 0, nel = 0, na = 0, nb = 0, periodic = 0;
     double t = 0, U = 0, L = 0, k2 = 0, vc = 0;
     int gmax = 0, gdim = 0, vlen = 0;
-    std::vector<int8_t> nvec;
-    std::vector<double> eps, vtab;
+    std::vector<int32_t> npk;
+    std::vector<double> eps, vtab, vx;
     std::vector<int16_t> grid;
     std::vector<double> h1, eri;
     std::vector<int64_t> hb_off;
@@ -135,13 +135,10 @@ std::string build_system(const fq_system &d, HostSys &s)
         if (2 * M > 64 * MAXW) return "UEG basis exceeds 512 spin-orbitals";
         if (d.n_alpha > M || d.n_beta > M) return "too many electrons for the basis";
         s.n_spatial = M;
-        s.nvec.resize(3 * M);
+        s.npk.resize(M);
         s.eps.resize(M);
-        for (int i = 0; i < M; ++i) {
-            s.nvec[3 * i] = (int8_t)pw[i].x;
-            s.nvec[3 * i + 1] = (int8_t)pw[i].y;
-            s.nvec[3 * i + 2] = (int8_t)pw[i].z;
-        }
+        for (int i = 0; i < M; ++i)
+            s.npk[i] = (pw[i].x + 256) | ((pw[i].y + 256) << 10) | ((pw[i].z + 256) << 20);
         const double N = (double)s.nel;
         s.L = d.rs * std::cbrt((4.0 * M_PI * N) / 3.0);
         const double g = (2.0 * M_PI) / s.L;
@@ -151,6 +148,12 @@ std::string build_system(const fq_system &d, HostSys &s)
         s.vlen = 4 * d.ecut_n2 + 1;
         s.vtab.assign(s.vlen, 0.0);
         for (int q = 1; q < s.vlen; ++q) s.vtab[q] = s.vc / (s.k2 * (double)q);
+        s.vx.assign((size_t)M * M, 0.0);
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < M; ++j) {
+                const int dx = pw[i].x - pw[j].x, dy = pw[i].y - pw[j].y, dz = pw[i].z - pw[j].z;
+                s.vx[(size_t)i * M + j] = s.vtab[dx * dx + dy * dy + dz * dz];
+            }
         s.gmax = 3 * c;
         s.gdim = 2 * s.gmax + 1;
         s.grid.assign((size_t)s.gdim * s.gdim * s.gdim, (int16_t)-1);
@@ -205,14 +208,14 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 // device image of one system's tables
 size_t table_bytes(const HostSys &s)
 {
-    return al(s.nvec.size()) + al(8 * s.eps.size()) + al(8 * s.vtab.size()) + al(2 * s.grid.size()) +
+    return al(4 * s.npk.size()) + al(8 * s.eps.size()) + al(8 * s.vtab.size()) + al(8 * s.vx.size()) + al(2 * s.grid.size()) +
            al(8 * s.h1.size()) + al(8 * s.eri.size()) + al(8 * s.hb_off.size()) + al(4 * s.hb_cnt.size()) +
            al(8 * s.hb_S.size()) + al(2 * s.hb_AB.size()) + al(8 * s.hb_cdf.size());
 }
 
 struct Layout {
     size_t total = 0;
-    size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge;
+    size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge, st_spawn;
     size_t main[2][6];
     size_t sp[7];
     size_t u[4];
@@ -223,7 +226,7 @@ struct Layout {
 int64_t tiles_of(int64_t n, int64_t tile) { return (n + tile - 1) / tile + 1; }
 
 // spans of 256 attempts the attempt partition can hold
-int64_t span_capacity(int64_t mcap, int64_t scap) { return tiles_of(std::max(mcap * 16, scap * 4), 256); }
+int64_t span_capacity(int64_t mcap, int64_t scap) { return tiles_of(std::max(mcap * 16, scap * 4), 1024); }
 
 Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D)
 {
@@ -243,11 +246,12 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.tables = take((size_t)tables);
     L.att = take(8 * (size_t)(mcap + 1));
     L.span = take(8 * (size_t)(span_capacity(mcap, scap) + 2));
-    L.mpart = take(8 * (size_t)(tiles_of(mcap + scap, 1024) + 2));
+    L.mpart = take(8 * (size_t)(tiles_of(mcap + scap, 512) + 2));
     L.st_scan = take(8 * (size_t)tiles_of(mcap, 2048));
     L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, 4096));
     L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
-    L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 1024));
+    L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 512));
+    L.st_spawn = take(8 * (size_t)(span_capacity(mcap, scap) + 2));
     for (int b = 0; b < 2; ++b) {
         L.main[b][0] = take(8 * (size_t)mcap);
         L.main[b][1] = take(8 * (size_t)mcap * W);
@@ -315,6 +319,8 @@ struct fq_ctx {
     std::vector<double> h00v;
     bool timing = false;
     double stage_ms[7] = {0};
+    double kernel_ms[N_KERNEL_SLOTS] = {0};
+    int64_t timed_iterations = 0;
     std::string err;
 };
 
@@ -634,6 +640,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.st_sort = (unsigned long long *)(c->ws + c->L.st_sort);
     w.st_red = (unsigned long long *)(c->ws + c->L.st_red);
     w.st_merge = (unsigned long long *)(c->ws + c->L.st_merge);
+    w.st_spawn = (unsigned long long *)(c->ws + c->L.st_spawn);
     w.sp.skey = (uint64_t *)(c->ws + c->L.sp[0]);
     w.sp.key = (uint64_t *)(c->ws + c->L.sp[1]);
     w.sp.amp = (int32_t *)(c->ws + c->L.sp[2]);
@@ -694,7 +701,8 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         d.gmax = s.gmax;
         d.gdim = s.gdim;
         d.vlen = s.vlen;
-        d.nvec = (const int8_t *)put(s.nvec.data(), s.nvec.size());
+        d.npk = (const int32_t *)put(s.npk.data(), 4 * s.npk.size());
+        d.vx = (const double *)put(s.vx.data(), 8 * s.vx.size());
         d.eps = (const double *)put(s.eps.data(), 8 * s.eps.size());
         d.vtab = (const double *)put(s.vtab.data(), 8 * s.vtab.size());
         d.grid = (const int16_t *)put(s.grid.data(), 2 * s.grid.size());
@@ -747,7 +755,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     c->grids.merge = ncu * occupancy_blocks(1);
     c->grids.reduce = ncu * occupancy_blocks(2);
     c->grids.part = ncu * 4;
-    c->grids.spawn = ncu * 8;
+    c->grids.spawn = ncu * occupancy_blocks(4);
     c->grids.hist = ncu * 4;
     c->grids.fixup = ncu * 2;
     c->grids.det = ncu * 4;
@@ -789,6 +797,9 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
     const int A = c->qmc[0].shift_period;
     for (int r = 0; r < c->R; ++r) c->hist[r].clear();
     std::fill(c->stage_ms, c->stage_ms + 7, 0.0);
+    std::fill(c->kernel_ms, c->kernel_ms + N_KERNEL_SLOTS, 0.0);
+    c->timed_iterations = 0;
+    constexpr int NE = N_KERNEL_SLOTS + 1;
     std::vector<hipEvent_t> evs;
     int done = 0;
     while (done < n_iterations) {
@@ -802,11 +813,11 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         const int cur0 = c->cur;
         const int nb = (int)(stop - t0);
         if (c->timing) {
-            evs.resize((size_t)nb * 7);
-            for (auto &e : evs) hipEventCreate(&e);
+            evs.resize((size_t)nb * NE);
+            for (auto &e : evs) (void)hipEventCreate(&e);
         }
         for (int k = 0; k < nb; ++k) {
-            hipError_t he = enqueue_iteration(c->w, c->kind, c->grids, c->stream, c->timing ? &evs[(size_t)k * 7] : nullptr);
+            hipError_t he = enqueue_iteration(c->w, c->kind, c->grids, c->stream, c->timing ? &evs[(size_t)k * NE] : nullptr);
             if (he != hipSuccess) return fail(c, FQ_EHIP, std::string("launch: ") + hipGetErrorString(he));
             c->cur ^= 1;
             set_main_views(c);
@@ -815,18 +826,22 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         HIPCHK(c, hipMemcpyAsync(c->h_hist, c->w.hist, sizeof(EstAcc) * c->R * HIST_LEN, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         if (c->timing) {
+            // stage boundaries in the launch order: scan+partition, spawn, sort
+            // (histogram + 8 passes), reduce (2 passes + fix-up), projection, merge
+            static const int stage_of[N_KERNEL_SLOTS] = {0, 0, 0, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 5, 5, 4, 4, 4};
             for (int k = 0; k < nb; ++k) {
-                float ms;
-                hipEvent_t *e = &evs[(size_t)k * 7];
-                hipEventElapsedTime(&ms, e[0], e[1]); c->stage_ms[0] += ms;
-                hipEventElapsedTime(&ms, e[1], e[2]); c->stage_ms[1] += ms;
-                hipEventElapsedTime(&ms, e[2], e[3]); c->stage_ms[2] += ms;
-                hipEventElapsedTime(&ms, e[3], e[4]); c->stage_ms[3] += ms;
-                hipEventElapsedTime(&ms, e[5], e[6]); c->stage_ms[4] += ms;
-                hipEventElapsedTime(&ms, e[4], e[5]); c->stage_ms[5] += ms;
-                hipEventElapsedTime(&ms, e[0], e[6]); c->stage_ms[6] += ms;
+                hipEvent_t *e = &evs[(size_t)k * NE];
+                float ms = 0.f;
+                for (int q = 0; q < N_KERNEL_SLOTS; ++q) {
+                    (void)hipEventElapsedTime(&ms, e[q], e[q + 1]);
+                    c->kernel_ms[q] += ms;
+                    c->stage_ms[stage_of[q]] += ms;
+                }
+                (void)hipEventElapsedTime(&ms, e[0], e[N_KERNEL_SLOTS]);
+                c->stage_ms[6] += ms;
             }
-            for (auto &e : evs) hipEventDestroy(e);
+            c->timed_iterations += nb;
+            for (auto &e : evs) (void)hipEventDestroy(e);
             evs.clear();
         }
         const Ctl &ctl = *c->h_ctl;
@@ -1063,6 +1078,15 @@ fq_status fq_stage_times(const fq_ctx *c, double *ms7)
 {
     if (!c || !ms7) return FQ_EINVAL;
     std::memcpy(ms7, c->stage_ms, sizeof(c->stage_ms));
+    return FQ_OK;
+}
+
+fq_status fq_kernel_times(const fq_ctx *c, double *ms, int32_t cap, int32_t *n_slots, int64_t *n_iterations)
+{
+    if (!c || (!ms && cap > 0)) return FQ_EINVAL;
+    for (int q = 0; q < cap && q < N_KERNEL_SLOTS; ++q) ms[q] = c->kernel_ms[q];
+    if (n_slots) *n_slots = N_KERNEL_SLOTS;
+    if (n_iterations) *n_iterations = c->timed_iterations;
     return FQ_OK;
 }
 

@@ -35,6 +35,7 @@ enum : int {
     TK_RED1 = 9,
     TK_RED2 = 10,
     TK_MERGE = 11,
+    TK_SPAWN = 12,
     TK_COUNT = 16,
 };
 
@@ -112,7 +113,7 @@ struct Work {
     long long *att_off;    // [main_cap + 1]
     long long *span_lo;    // [spans + 1]
     long long *mpart;      // merge partition [tiles + 1]
-    unsigned long long *st_scan, *st_sort, *st_red, *st_merge;  // look-back status
+    unsigned long long *st_scan, *st_sort, *st_red, *st_merge, *st_spawn;  // look-back status
     MainList cur, nxt;
     SpawnList sp;
     UniqList u;
@@ -126,7 +127,9 @@ struct Grids {
     int scan, part, spawn, hist, sort, reduce, fixup, merge, det;
 };
 
-// enqueue one whole iteration on a stream (ev: 7 events or nullptr)
+// kernels of one iteration, in launch order (per-kernel timing slots)
+constexpr int N_KERNEL_SLOTS = 21;
+// enqueue one whole iteration on a stream (ev: N_KERNEL_SLOTS + 1 events or nullptr)
 hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_t s, hipEvent_t *ev);
 // set-up work: 0 = H_00 of every system, 1 = K_ii - H_00 and attempts of a
 // list of n entries, 2 = K_DD of the deterministic space

@@ -34,35 +34,6 @@ __device__ __forceinline__ unsigned long long st_load(unsigned long long *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One thread: publishes this tile's aggregate, walks back to the nearest
-// inclusive prefix, publishes its own inclusive prefix, returns the exclusive one.
-// Waits only on tiles with smaller tickets, which are resident and never wait
-// on this tile, so every wait ends.
-__device__ long long lookback(unsigned long long *st, long long tile, uint32_t epoch, long long agg)
-{
-    if (tile == 0) {
-        st_store(st, st_pack(epoch, ST_INC, agg));
-        return 0;
-    }
-    st_store(st + tile, st_pack(epoch, ST_AGG, agg));
-    long long excl = 0;
-    long long j = tile - 1;
-    for (;;) {
-        const unsigned long long s = st_load(st + j);
-        const uint32_t e = (uint32_t)(s >> 40);
-        const unsigned long long f = (s >> ST_VBITS) & 3ull;
-        if (e != epoch || f == 0) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-        }
-        excl += (long long)(s & ST_VMASK);
-        if (f == ST_INC) break;
-        --j;
-    }
-    st_store(st + tile, st_pack(epoch, ST_INC, excl + agg));
-    return excl;
-}
-
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
@@ -72,6 +43,45 @@ __device__ __forceinline__ T wave_sum(T v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+// Decoupled look-back, run by one whole wavefront: publishes this tile's
+// aggregate, then inspects the 64 preceding tiles at a time until it meets an
+// inclusive prefix, publishes its own inclusive prefix and returns the
+// exclusive one (to every lane). It waits only on tiles with smaller tickets,
+// which are resident and never wait on this tile, so every wait ends.
+__device__ long long lookback(unsigned long long *st, long long tile, uint32_t epoch, long long agg)
+{
+    const int lane = lane_id();
+    if (tile == 0) {
+        if (lane == 0) st_store(st, st_pack(epoch, ST_INC, agg));
+        return 0;
+    }
+    if (lane == 0) st_store(st + tile, st_pack(epoch, ST_AGG, agg));
+    long long excl = 0;
+    long long j = tile - 1;
+    for (;;) {
+        const long long idx = j - lane;
+        unsigned long long sw = 0;
+        if (idx >= 0) sw = st_load(st + idx);
+        const uint32_t e = (uint32_t)(sw >> 40);
+        const unsigned long long f = (sw >> ST_VBITS) & 3ull;
+        const bool valid = idx >= 0 && e == epoch && f != 0;
+        const uint64_t inc = __ballot(valid && f == ST_INC);
+        const uint64_t bad = __ballot(idx >= 0 && !valid);
+        // lanes that count: up to and including the nearest inclusive prefix
+        const uint64_t need = inc ? ((inc & (~inc + 1)) << 1) - 1 : ~0ull;
+        if (bad & need) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        const long long v = (((need >> lane) & 1ull) && valid) ? (long long)(sw & ST_VMASK) : 0;
+        excl += wave_sum<long long>(v);
+        if (inc) break;
+        j -= 64;
+    }
+    if (lane == 0) st_store(st + tile, st_pack(epoch, ST_INC, excl + agg));
+    return excl;
 }
 
 // exclusive block scan of one value per thread (blockDim = 256)
@@ -204,7 +214,10 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_attempts(Work w)
         }
         long long tot;
         const long long ex = block_excl_scan<long long>(sum, tot, s_red);
-        if (threadIdx.x == 0) s_base = lookback(w.st_scan, tile, epoch, tot);
+        if (threadIdx.x < 64) {
+            const long long lb_ = lookback(w.st_scan, tile, epoch, tot);
+            if (threadIdx.x == 0) s_base = lb_;
+        }
         __syncthreads();
         long long run = s_base + ex;
 #pragma unroll
@@ -227,9 +240,11 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_attempts(Work w)
 // ---------------------------------------------------------------------------
 // spawning (Sec. 2.4): one thread per attempt, parents found through the
 // attempt prefix (load balanced: a heavily populated determinant spreads its
-// attempts over many threads and blocks)
+// attempts over many threads and tiles). A tile of 1024 consecutive attempts
+// finds its spawn count, takes its output offset by decoupled look-back (no
+// contended counter) and writes its records contiguously.
 // ---------------------------------------------------------------------------
-constexpr int SPAN = 256;
+constexpr int SP_T = 256, SP_I = 4, SPAN = SP_T * SP_I;
 
 __device__ __forceinline__ long long upper_bound_ll(const long long *a, long long lo, long long hi, long long x)
 {
@@ -260,152 +275,195 @@ __global__ void k_spawn_partition(Work w)
     }
 }
 
-template <int KIND, int W>
-__global__ __launch_bounds__(SPAN) void k_spawn(Work w)
+// MULTI = false: a single replica (rb = 0), so the replica index is 0, its
+// parameters are uniform over the grid and a determinant's hash is its sort key.
+template <int KIND, int W, bool MULTI>
+__global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 {
     Ctl *c = w.ctl;
     if (c->err) return;
     constexpr int LCAP = 2 * SPAN + 2;
     __shared__ long long s_off[LCAP];
+    __shared__ uint32_t s_cnt[SP_I][SP_T / 64];
+    __shared__ long long s_tile, s_base;
+    __shared__ uint64_t s_rk[SPAN];
+    __shared__ uint64_t s_rkey[W][SPAN];
+    __shared__ int32_t s_ramp[SPAN];
+    __shared__ uint8_t s_rinit[SPAN];
     const long long total = c->n_att;
     const long long nspans = (total + SPAN - 1) / SPAN;
     if (nspans + 1 > w.span_cap) return;
     const uint32_t t = c->t;
     const bool ss = c->ss_active != 0;
-    for (long long span = blockIdx.x; span < nspans; span += gridDim.x) {
+    const uint32_t epoch = epoch_of(t, 12);
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[TK_SPAWN], 1u);
+        __syncthreads();
+        const long long span = s_tile;
+        if (span >= nspans) break;
         const long long lo = w.span_lo[span];
-        const long long hi = w.span_lo[span + 1];  // parent of the next span's first attempt
+        const long long hi = w.span_lo[span + 1];  // parent of the next tile's first attempt
         const long long len = hi - lo + 2;
         const bool staged = len <= LCAP;
-        __syncthreads();
         if (staged)
-            for (long long i = threadIdx.x; i < len; i += SPAN) s_off[i] = w.att_off[lo + i];
+            for (long long i = threadIdx.x; i < len; i += SP_T) s_off[i] = w.att_off[lo + i];
         __syncthreads();
-        const long long a = span * SPAN + threadIdx.x;
-        bool has = false;
-        uint64_t child[W];
-        long long parent = 0;
-        int32_t amp = 0;
-        uint8_t init = 0;
-        uint32_t rep = 0;
-        if (a < total) {
-            long long i;
-            if (staged) {
-                int l = 0, h = (int)len;
-                while (l < h) {
-                    const int m = (l + h) >> 1;
-                    if (s_off[m] <= a) l = m + 1; else h = m;
-                }
-                i = lo + l - 1;
-            } else {
-                i = upper_bound_ll(w.att_off, lo, hi + 2, a) - 1;
-            }
-            parent = i;
-            const long long a0 = w.att_off[i];
-            const long long nat = w.att_off[i + 1] - a0;
-            const long long k = a - a0;
-            uint64_t key[W];
+        bool has[SP_I];
+        uint64_t child[SP_I][W];
+        int32_t amp[SP_I];
+        uint8_t init[SP_I];
+        uint32_t rep[SP_I];
 #pragma unroll
-            for (int q = 0; q < W; ++q) key[q] = w.cur.key[(size_t)q * w.main_cap + i];
-            const int32_t n0 = w.cur.pop[i];
-            const int32_t dsl = w.cur.dslot[i];
-            rep = skey_rep(w.cur.skey[i], w.rb);
-            const RepParams rp = w.rep[rep];
-            const DevSys &sy = w.sys[rp.sys];
-            const uint64_t h = hash64<W>(key);
-            const long long an = n0 < 0 ? -(long long)n0 : (long long)n0;
-            const bool pin_d = ss && dsl >= 0;
-            init = (uint8_t)(an > rp.thr || key_eq<W>(key, *(const uint64_t(*)[W])sy.ref) || pin_d);
-            const U4 r0 = draw(TAG_SELECT, (uint32_t)k, t, h, rp.k0, rp.k1);
-            double pgen = 0.0, hv = 0.0;
-            bool ok;
-            if constexpr (KIND == K_HUBBARD)
-                ok = gen_hubbard<W>(sy, key, r0.x, child, pgen, hv);
-            else if constexpr (KIND == K_UEG)
-                ok = gen_ueg<W>(sy, key, r0.x, r0.y, child, pgen, hv);
-            else
-                ok = gen_heatbath<W>(sy, rp.p_single, key, r0, (uint32_t)k, t, h, rp.k0, rp.k1, child, pgen, hv);
-            if (ok && hv != 0.0) {
-                bool skip = false;
-                if (pin_d) {
-                    // discard spawns that stay inside the deterministic space
-                    const uint64_t cs = make_skey(hash64<W>(child), rep, w.rb);
-                    const int nd = w.ds.n * w.R;
-                    int l = 0, hh = nd;
-                    while (l < hh) {
-                        const int m = (l + hh) >> 1;
-                        const uint64_t sk = w.ds.skey_sorted[m];
-                        bool less = sk < cs;
-                        if (sk == cs) {
+        for (int it = 0; it < SP_I; ++it) {
+            has[it] = false;
+            amp[it] = 0;
+            init[it] = 0;
+            rep[it] = 0;
+#pragma unroll
+            for (int q = 0; q < W; ++q) child[it][q] = 0;
+            const long long a = span * SPAN + it * SP_T + threadIdx.x;
+            if (a < total) {
+                long long i;
+                if (staged) {
+                    int l = 0, h = (int)len;
+                    while (l < h) {
+                        const int m = (l + h) >> 1;
+                        if (s_off[m] <= a) l = m + 1; else h = m;
+                    }
+                    i = lo + l - 1;
+                } else {
+                    i = upper_bound_ll(w.att_off, lo, hi + 2, a) - 1;
+                }
+                const long long a0 = staged ? s_off[i - lo] : w.att_off[i];
+                const long long nat = (staged ? s_off[i - lo + 1] : w.att_off[i + 1]) - a0;
+                const long long k = a - a0;
+                uint64_t key[W];
+#pragma unroll
+                for (int q = 0; q < W; ++q) key[q] = w.cur.key[(size_t)q * w.main_cap + i];
+                const int32_t n0 = w.cur.pop[i];
+                const int32_t dsl = w.cur.dslot[i];
+                const uint64_t psk = w.cur.skey[i];
+                rep[it] = MULTI ? skey_rep(psk, w.rb) : 0u;
+                const RepParams &rp = w.rep[MULTI ? rep[it] : 0u];
+                const DevSys &sy = w.sys[rp.sys];
+                const uint64_t h = MULTI ? hash64<W>(key) : psk;
+                const long long an = n0 < 0 ? -(long long)n0 : (long long)n0;
+                const bool pin_d = ss && dsl >= 0;
+                init[it] = (uint8_t)(an > rp.thr || key_eq<W>(key, *(const uint64_t(*)[W])sy.ref) || pin_d);
+                const U4 r0 = draw(TAG_SELECT, (uint32_t)k, t, h, rp.k0, rp.k1);
+                double pgen = 0.0, hv = 0.0;
+                bool ok;
+                if constexpr (KIND == K_HUBBARD)
+                    ok = gen_hubbard<W>(sy, key, r0.x, child[it], pgen, hv);
+                else if constexpr (KIND == K_UEG)
+                    ok = gen_ueg<W>(sy, key, r0.x, r0.y, child[it], pgen, hv);
+                else
+                    ok = gen_heatbath<W>(sy, rp.p_single, key, r0, (uint32_t)k, t, h, rp.k0, rp.k1, child[it], pgen, hv);
+                if (ok && hv != 0.0) {
+                    bool skip = false;
+                    if (pin_d) {
+                        // discard spawns that stay inside the deterministic space
+                        const uint64_t cs = make_skey(hash64<W>(child[it]), rep[it], w.rb);
+                        const int nd = w.ds.n * w.R;
+                        int l = 0, hh = nd;
+                        while (l < hh) {
+                            const int m = (l + hh) >> 1;
+                            const uint64_t sk = w.ds.skey_sorted[m];
+                            bool less = sk < cs;
+                            if (sk == cs) {
+                                uint64_t dk[W];
+#pragma unroll
+                                for (int q = 0; q < W; ++q) dk[q] = w.ds.key_sorted[(size_t)q * nd + m];
+                                less = key_cmp<W>(dk, child[it]) < 0;
+                            }
+                            if (less) l = m + 1; else hh = m;
+                        }
+                        if (l < nd && w.ds.skey_sorted[l] == cs) {
                             uint64_t dk[W];
 #pragma unroll
-                            for (int q = 0; q < W; ++q) dk[q] = w.ds.key_sorted[(size_t)q * nd + m];
-                            less = key_cmp<W>(dk, child) < 0;
+                            for (int q = 0; q < W; ++q) dk[q] = w.ds.key_sorted[(size_t)q * nd + l];
+                            skip = key_eq<W>(dk, child[it]);
                         }
-                        if (less) l = m + 1; else hh = m;
                     }
-                    if (l < nd && w.ds.skey_sorted[l] == cs) {
-                        uint64_t dk[W];
-#pragma unroll
-                        for (int q = 0; q < W; ++q) dk[q] = w.ds.key_sorted[(size_t)q * nd + l];
-                        skip = key_eq<W>(dk, child);
-                    }
-                }
-                if (!skip) {
-                    const double ah = fabs(hv);
-                    double m;
-                    if (rp.bits == 0)
-                        m = (rp.tau * ah) / pgen;
-                    else
-                        m = (((rp.tau * ah) / pgen) * (double)an) / (double)nat;
-                    const U4 rr = draw(TAG_SPAWN_ROUND, (uint32_t)k, t, h, rp.k0, rp.k1);
-                    const double u = u53(rr.x, rr.y);
-                    long long kk = 0;
-                    if (!(m < 0x1p31)) {
-                        atomicOr(&c->err, ERR_OVERFLOW);
-                    } else {
-                        if (rp.bits != 0 && m < (double)rp.cu)
-                            kk = (u * (double)rp.cu < m) ? rp.cu : 0;
+                    if (!skip) {
+                        const double ah = fabs(hv);
+                        double m;
+                        if (rp.bits == 0)
+                            m = (rp.tau * ah) / pgen;
                         else
-                            kk = sround(m, u);
-                        if (kk > 2147483647ll) {
+                            m = (((rp.tau * ah) / pgen) * (double)an) / (double)nat;
+                        const U4 rr = draw(TAG_SPAWN_ROUND, (uint32_t)k, t, h, rp.k0, rp.k1);
+                        const double u = u53(rr.x, rr.y);
+                        long long kk = 0;
+                        if (!(m < 0x1p31)) {
                             atomicOr(&c->err, ERR_OVERFLOW);
-                            kk = 0;
+                        } else {
+                            if (rp.bits != 0 && m < (double)rp.cu)
+                                kk = (u * (double)rp.cu < m) ? rp.cu : 0;
+                            else
+                                kk = sround(m, u);
+                            if (kk > 2147483647ll) {
+                                atomicOr(&c->err, ERR_OVERFLOW);
+                                kk = 0;
+                            }
+                        }
+                        if (kk != 0) {
+                            const int sh = hv > 0.0 ? 1 : -1;
+                            const int sn = n0 > 0 ? 1 : -1;
+                            amp[it] = (int32_t)(-(long long)(sh * sn) * kk);
+                            has[it] = true;
                         }
                     }
-                    if (kk != 0) {
-                        const int sh = hv > 0.0 ? 1 : -1;
-                        const int sn = n0 > 0 ? 1 : -1;
-                        amp = (int32_t)(-(long long)(sh * sn) * kk);
-                        has = true;
-                    }
                 }
             }
+            const uint64_t m = __ballot(has[it]);
+            if (lane == 0) s_cnt[it][wid] = (uint32_t)__popcll(m);
         }
-        // wave-aggregated slot reservation
-        const uint64_t msk = __ballot(has);
-        if (msk) {
-            const int leader = __ffsll((unsigned long long)msk) - 1;
-            unsigned long long base = 0;
-            if (lane_id() == leader) base = atomicAdd(&c->n_spawn, (unsigned long long)__popcll(msk));
-            base = __shfl(base, leader, 64);
-            if (has) {
-                const unsigned long long slot = base + __popcll(msk & lanemask_lt());
-                if (slot < (unsigned long long)w.spawn_cap) {
-                    const uint64_t h2 = hash64<W>(child);
-                    w.sp.skey[slot] = make_skey(h2, rep, w.rb);
+        __syncthreads();
+        // offsets in attempt order: slab it, wave wid, lane
+        uint32_t tot = 0, before[SP_I];
 #pragma unroll
-                    for (int q = 0; q < W; ++q) w.sp.key[(size_t)q * w.spawn_cap + slot] = child[q];
-                    w.sp.amp[slot] = amp;
-                    w.sp.init[slot] = init;
-                    w.u.sum[slot] = 0;
-                    w.u.flag[slot] = 0;
-                } else {
-                    atomicOr(&c->err, ERR_SPAWN_CAP);
-                }
+        for (int it = 0; it < SP_I; ++it)
+#pragma unroll
+            for (int q = 0; q < SP_T / 64; ++q) {
+                if (q == wid) before[it] = tot;
+                tot += s_cnt[it][q];
+            }
+        if (threadIdx.x < 64) {
+            const long long lb_ = lookback(w.st_spawn, span, epoch, (long long)tot);
+            if (threadIdx.x == 0) s_base = lb_;
+        }
+#pragma unroll
+        for (int it = 0; it < SP_I; ++it) {
+            const uint64_t m = __ballot(has[it]);
+            if (has[it]) {
+                const uint32_t r = before[it] + (uint32_t)__popcll(m & lanemask_lt());
+                s_rk[r] = make_skey(hash64<W>(child[it]), rep[it], w.rb);
+#pragma unroll
+                for (int q = 0; q < W; ++q) s_rkey[q][r] = child[it][q];
+                s_ramp[r] = amp[it];
+                s_rinit[r] = init[it];
             }
         }
-        (void)parent;
+        __syncthreads();
+        const long long base = s_base;
+        if (base + tot > w.spawn_cap) {
+            if (threadIdx.x == 0) atomicOr(&c->err, ERR_SPAWN_CAP);
+        } else {
+            for (uint32_t p = threadIdx.x; p < tot; p += SP_T) {
+                const long long o = base + p;
+                w.sp.skey[o] = s_rk[p];
+#pragma unroll
+                for (int q = 0; q < W; ++q) w.sp.key[(size_t)q * w.spawn_cap + o] = s_rkey[q][p];
+                w.sp.amp[o] = s_ramp[p];
+                w.sp.init[o] = s_rinit[p];
+                w.u.sum[o] = 0;
+                w.u.flag[o] = 0;
+            }
+        }
+        if (span == nspans - 1 && threadIdx.x == 0) c->n_spawn = (unsigned long long)(base + tot);
+        __syncthreads();
     }
 }
 
@@ -652,7 +710,10 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
         }
         long long tot;
         const long long ex = block_excl_scan<long long>((long long)nh, tot, s_red);
-        if (threadIdx.x == 0) s_base = lookback(w.st_red, tile, epoch, tot);
+        if (threadIdx.x < 64) {
+            const long long lb_ = lookback(w.st_red, tile, epoch, tot);
+            if (threadIdx.x == 0) s_base = lb_;
+        }
         __syncthreads();
         long long seg = s_base + ex - 1;  // segment of the element before this thread's first
         long long run_sum = 0;
@@ -755,8 +816,18 @@ __global__ void k_fixup(Work w)
 // initiator rule for new determinants (Sec. 2.1), removal of empty entries,
 // the estimators of the new list (tutorial appendix) and the attempt counts of
 // the next iteration. Ties in the merge order put the main entry first.
+//
+// A tile's slices of both lists are staged in LDS with coalesced loads (main
+// entries in slots [0, la), spawned ones in [la, la + lb)); every thread
+// merges its run of positions from LDS, writes each result into the source
+// slot, and the kept entries leave in merge order with coalesced stores.
 // ---------------------------------------------------------------------------
-constexpr int MG_T = 256, MG_I = 4, MG_TILE = MG_T * MG_I;
+constexpr int MG_T = 256;
+template <int W>
+struct MergeCfg {
+    static constexpr int I = W <= 2 ? 4 : 2;
+    static constexpr int TILE = MG_T * I;
+};
 
 template <int W>
 __device__ __forceinline__ void load_key(const uint64_t *base, long long cap, long long i, uint64_t (&k)[W])
@@ -765,7 +836,7 @@ __device__ __forceinline__ void load_key(const uint64_t *base, long long cap, lo
     for (int q = 0; q < W; ++q) k[q] = base[(size_t)q * cap + i];
 }
 
-// main[i] <= uniq[j] in (sort key, key) order
+// main[i] <= uniq[j] in (sort key, key) order (global memory)
 template <int W>
 __device__ __forceinline__ bool le_ab(const Work &w, long long i, uint64_t si, long long j, uint64_t sj)
 {
@@ -781,11 +852,12 @@ __global__ void k_merge_partition(Work w)
 {
     const Ctl *c = w.ctl;
     if (c->err) return;
+    constexpr int TILE = MergeCfg<W>::TILE;
     const long long na = c->n_main, nb = c->n_uniq;
-    const long long ntiles = (na + nb + MG_TILE - 1) / MG_TILE;
+    const long long ntiles = (na + nb + TILE - 1) / TILE;
     for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile <= ntiles;
          tile += (long long)gridDim.x * blockDim.x) {
-        const long long d = min(tile * MG_TILE, na + nb);
+        const long long d = min(tile * TILE, na + nb);
         long long lo = max(0ll, d - nb), hi = min(d, na);
         while (lo < hi) {
             const long long mid = (lo + hi) >> 1;
@@ -823,17 +895,42 @@ __device__ __forceinline__ void add_limbs(long long (&v)[EST_FIELDS], double x)
     v[F_L3] += neg ? -l3 : l3;
 }
 
-template <int KIND, int W>
+__device__ __forceinline__ void acc_switch(LocalAcc &acc, int rep, EstAcc *g)
+{
+    if (rep == acc.rep) return;
+    if (acc.rep >= 0) {
+#pragma unroll
+        for (int f = 0; f < EST_FIELDS; ++f)
+            if (acc.v[f]) atomicAdd((unsigned long long *)(&g[acc.rep].nw + f), (unsigned long long)acc.v[f]);
+        acc.clear();
+    }
+    acc.rep = rep;
+}
+
+template <int KIND, int W, bool MULTI>
 __global__ __launch_bounds__(MG_T) void k_merge(Work w)
 {
     Ctl *c = w.ctl;
     if (c->err) return;
-    __shared__ uint64_t sa[MG_TILE + 1];
-    __shared__ uint64_t sb[MG_TILE + 1];
+    constexpr int MI = MergeCfg<W>::I, TILE = MergeCfg<W>::TILE;
+    __shared__ uint64_t s_sk[TILE];
+    __shared__ uint64_t s_key[W][TILE];
+    __shared__ long long s_val[TILE];   // main: population, then the new one; spawned: sum
+    __shared__ double s_kd[TILE];       // K_ii - H_00
+    __shared__ int32_t s_meta[TILE];    // main: dslot; spawned: initiator flag, then dslot (-1)
+    __shared__ uint16_t s_src[TILE];    // merge position -> slot
+    __shared__ uint16_t s_dst[TILE];    // merge position -> rank among kept
+    __shared__ uint8_t s_keep[TILE];
+    __shared__ uint64_t s_pa_sk, s_pa_key[W];  // main entry before the tile
+    __shared__ uint64_t s_nb_sk, s_nb_key[W];  // spawned entry after the tile
+    __shared__ long long s_nb_sum;
+    __shared__ int s_pa_ok, s_nb_ok;
+    __shared__ uint16_t s_newq[TILE];  // accepted new determinants (slots) awaiting K_jj
+    __shared__ int s_nnew;
     __shared__ long long s_tile, s_base;
     __shared__ long long s_red[8];
     const long long na = c->n_main, nb = c->n_uniq;
-    const long long ntiles = (na + nb + MG_TILE - 1) / MG_TILE;
+    const long long ntiles = (na + nb + TILE - 1) / TILE;
     const uint32_t t = c->t;
     const uint32_t epoch = epoch_of(t, 11);
     const bool ss = c->ss_active != 0;
@@ -846,73 +943,109 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
         __syncthreads();
         const long long tile = s_tile;
         if (tile >= ntiles) break;
-        const long long d0 = tile * MG_TILE, d1 = min(d0 + MG_TILE, na + nb);
+        const long long d0 = tile * TILE, d1 = min(d0 + TILE, na + nb);
         const long long i0 = w.mpart[tile], i1 = w.mpart[tile + 1];
         const long long j0 = d0 - i0, j1 = d1 - i1;
         const int la = (int)(i1 - i0), lb = (int)(j1 - j0);
-        for (int q = threadIdx.x; q < la; q += MG_T) sa[q] = w.cur.skey[i0 + q];
-        for (int q = threadIdx.x; q < lb; q += MG_T) sb[q] = w.u.skey[j0 + q];
+        for (int q = threadIdx.x; q < la; q += MG_T) {
+            const long long g = i0 + q;
+            s_sk[q] = w.cur.skey[g];
+#pragma unroll
+            for (int x = 0; x < W; ++x) s_key[x][q] = w.cur.key[(size_t)x * w.main_cap + g];
+            s_val[q] = w.cur.pop[g];
+            s_kd[q] = w.cur.kdiag[g];
+            s_meta[q] = w.cur.dslot[g];
+        }
+        for (int q = threadIdx.x; q < lb; q += MG_T) {
+            const long long g = j0 + q;
+            s_sk[la + q] = w.u.skey[g];
+#pragma unroll
+            for (int x = 0; x < W; ++x) s_key[x][la + q] = w.u.key[(size_t)x * w.spawn_cap + g];
+            s_val[la + q] = w.u.sum[g];
+            s_meta[la + q] = (int32_t)w.u.flag[g];
+        }
+        if (threadIdx.x == 0) {
+            s_nnew = 0;
+            s_pa_ok = i0 > 0;
+            if (i0 > 0) {
+                s_pa_sk = w.cur.skey[i0 - 1];
+#pragma unroll
+                for (int x = 0; x < W; ++x) s_pa_key[x] = w.cur.key[(size_t)x * w.main_cap + i0 - 1];
+            }
+            s_nb_ok = j1 < nb;
+            if (j1 < nb) {
+                s_nb_sk = w.u.skey[j1];
+#pragma unroll
+                for (int x = 0; x < W; ++x) s_nb_key[x] = w.u.key[(size_t)x * w.spawn_cap + j1];
+                s_nb_sum = w.u.sum[j1];
+            }
+        }
         __syncthreads();
-        // this thread's diagonal range inside the tile
-        const int dl = min((int)threadIdx.x * MG_I, la + lb);
+        auto le = [&](int a, int b) -> bool {  // A slot a <= B slot la + b
+            const uint64_t sa = s_sk[a], sb = s_sk[la + b];
+            if (sa != sb) return sa < sb;
+            int r = 0;
+#pragma unroll
+            for (int x = W - 1; x >= 0; --x)
+                if (r == 0) r = s_key[x][a] < s_key[x][la + b] ? -1 : (s_key[x][a] > s_key[x][la + b] ? 1 : 0);
+            return r <= 0;
+        };
+        auto eq_slots = [&](int p, int q) -> bool {
+            bool e = s_sk[p] == s_sk[q];
+#pragma unroll
+            for (int x = 0; x < W; ++x) e = e && s_key[x][p] == s_key[x][q];
+            return e;
+        };
+        const int dl = min((int)threadIdx.x * MI, la + lb);
         int lo = max(0, dl - lb), hi = min(dl, la);
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            const int j = dl - 1 - mid;
-            if (le_ab<W>(w, i0 + mid, sa[mid], j0 + j, sb[j])) lo = mid + 1; else hi = mid;
+            if (le(mid, dl - 1 - mid)) lo = mid + 1; else hi = mid;
         }
         int ia = lo, jb = dl - lo;
-        // outputs of this thread
-        uint64_t osk[MG_I], okey[MG_I][W];
-        int32_t opop[MG_I], ods[MG_I];
-        double okd[MG_I];
-        int nout = 0;
-        const int steps = min(MG_I, la + lb - dl);
-        for (int s = 0; s < steps; ++s) {
+        const int steps = min(MI, la + lb - dl);
+        for (int st = 0; st < steps; ++st) {
+            const int m = dl + st;
             bool takeA;
             if (ia >= la) takeA = false;
             else if (jb >= lb) takeA = true;
-            else takeA = le_ab<W>(w, i0 + ia, sa[ia], j0 + jb, sb[jb]);
+            else takeA = le(ia, jb);
             if (takeA) {
-                const long long gi = i0 + ia;
-                uint64_t key[W];
-                load_key<W>(w.cur.key, w.main_cap, gi, key);
-                const uint64_t sk = sa[ia];
-                const int32_t n0 = w.cur.pop[gi];
-                const int32_t dsl = w.cur.dslot[gi];
-                const double kd = w.cur.kdiag[gi];
-                const int rep = (int)skey_rep(sk, w.rb);
-                const RepParams rp = w.rep[rep];
-                const DevSys &sy = w.sys[rp.sys];
-                if (rep != acc.rep) {
-                    if (acc.rep >= 0) {
-#pragma unroll
-                        for (int f = 0; f < EST_FIELDS; ++f)
-                            if (acc.v[f]) atomicAdd((unsigned long long *)(&w.acc[acc.rep].nw + f), (unsigned long long)acc.v[f]);
-                        acc.clear();
-                    }
-                    acc.rep = rep;
-                }
+                const int a = ia++;
+                const uint64_t sk = s_sk[a];
+                const int32_t n0 = (int32_t)s_val[a];
+                const int32_t dsl = s_meta[a];
+                const int rep = MULTI ? (int)skey_rep(sk, w.rb) : 0;
+                acc_switch(acc, rep, w.acc);
                 any = true;
                 // matching spawned determinant: the next unconsumed one
-                const long long gj = j0 + jb;
                 long long add = 0;
-                if (gj < nb && w.u.skey[gj] == sk) {
-                    uint64_t bk[W];
-                    load_key<W>(w.u.key, w.spawn_cap, gj, bk);
-                    if (key_eq<W>(bk, key)) add = w.u.sum[gj];
+                if (jb < lb) {
+                    if (eq_slots(a, la + jb)) add = s_val[la + jb];
+                } else if (s_nb_ok && s_nb_sk == sk) {
+                    bool e = true;
+#pragma unroll
+                    for (int x = 0; x < W; ++x) e = e && s_nb_key[x] == s_key[x][a];
+                    if (e) add = s_nb_sum;
                 }
                 long long v;
                 if (ss && dsl >= 0) {
                     v = (long long)n0 + w.ds.delta[(size_t)rep * w.ds.n + dsl];
                 } else if (n0 != 0) {
+                    const RepParams &rp = w.rep[rep];
                     const double an = (double)(n0 < 0 ? -(long long)n0 : (long long)n0);
-                    const double m = (rp.tau * (kd - w.shift[rep])) * an;
-                    const uint64_t h = hash64<W>(key);
+                    const double mm = (rp.tau * (s_kd[a] - w.shift[rep])) * an;
+                    uint64_t h = sk;
+                    if constexpr (MULTI) {
+                        uint64_t key[W];
+#pragma unroll
+                        for (int x = 0; x < W; ++x) key[x] = s_key[x][a];
+                        h = hash64<W>(key);
+                    }
                     const U4 r = draw(TAG_DEATH, 0, t, h, rp.k0, rp.k1);
                     const double u = u53(r.x, r.y);
-                    if (!(fabs(m) < 0x1p40)) atomicOr(&c->err, ERR_OVERFLOW);
-                    const long long k = m >= 0.0 ? sround(m, u) : -sround(-m, u);
+                    if (!(fabs(mm) < 0x1p40)) atomicOr(&c->err, ERR_OVERFLOW);
+                    const long long k = mm >= 0.0 ? sround(mm, u) : -sround(-mm, u);
                     const long long sg = n0 > 0 ? 1 : -1;
                     v = (long long)n0 - sg * k;
                     if ((v > 0 && n0 < 0) || (v < 0 && n0 > 0)) acc.v[F_FLIPS] += 1;
@@ -922,118 +1055,120 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                 acc.v[F_DEATH] += v;
                 v += add;
                 if (v > 2147483647ll || v < -2147483647ll) atomicOr(&c->err, ERR_OVERFLOW);
-                if (v != 0 || dsl >= 0) {
-                    osk[nout] = sk;
-#pragma unroll
-                    for (int q = 0; q < W; ++q) okey[nout][q] = key[q];
-                    opop[nout] = (int32_t)v;
-                    okd[nout] = kd;
-                    ods[nout] = dsl;
-                    ++nout;
-                }
-                ++ia;
+                s_val[a] = v;
+                s_src[m] = (uint16_t)a;
+                s_keep[m] = (v != 0 || dsl >= 0) ? 1 : 0;
             } else {
-                const long long gj = j0 + jb;
-                const uint64_t sk = sb[jb];
-                uint64_t key[W];
-                load_key<W>(w.u.key, w.spawn_cap, gj, key);
-                // matched with the previous main entry: handled there
-                const long long gi = i0 + ia - 1;
-                bool matched = false;
-                if (gi >= 0 && w.cur.skey[gi] == sk) {
-                    uint64_t ak[W];
-                    load_key<W>(w.cur.key, w.main_cap, gi, ak);
-                    matched = key_eq<W>(ak, key);
-                }
-                if (!matched) {
-                    const long long sum = w.u.sum[gj];
-                    const uint32_t fl = w.u.flag[gj];
-                    const int rep = (int)skey_rep(sk, w.rb);
-                    const RepParams rp = w.rep[rep];
-                    const DevSys &sy = w.sys[rp.sys];
-                    if (rep != acc.rep) {
-                        if (acc.rep >= 0) {
+                const int b = jb++;
+                const int slot = la + b;
+                // matched with the preceding main entry: that entry's thread added it
+                bool matched;
+                if (ia > 0) {
+                    matched = eq_slots(ia - 1, slot);
+                } else {
+                    matched = s_pa_ok && s_pa_sk == s_sk[slot];
 #pragma unroll
-                            for (int f = 0; f < EST_FIELDS; ++f)
-                                if (acc.v[f]) atomicAdd((unsigned long long *)(&w.acc[acc.rep].nw + f), (unsigned long long)acc.v[f]);
-                            acc.clear();
-                        }
-                        acc.rep = rep;
-                    }
+                    for (int x = 0; x < W; ++x) matched = matched && s_pa_key[x] == s_key[x][slot];
+                }
+                s_src[m] = (uint16_t)slot;
+                s_keep[m] = 0;
+                if (!matched) {
+                    const long long sum = s_val[slot];
+                    const int32_t fl = s_meta[slot];
+                    const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
+                    const RepParams &rp = w.rep[rep];
+                    acc_switch(acc, rep, w.acc);
                     any = true;
                     const bool accept = (!rp.initiator || fl) && sum != 0;
                     if (accept) {
                         if (sum > 2147483647ll || sum < -2147483647ll) atomicOr(&c->err, ERR_OVERFLOW);
-                        osk[nout] = sk;
-#pragma unroll
-                        for (int q = 0; q < W; ++q) okey[nout][q] = key[q];
-                        opop[nout] = (int32_t)sum;
-                        okd[nout] = diag_element<KIND, W>(sy, key) - sy.H00;
-                        ods[nout] = -1;
-                        ++nout;
+                        s_newq[atomicAdd(&s_nnew, 1)] = (uint16_t)slot;
+                        s_meta[slot] = -1;
+                        s_keep[m] = 1;
                     } else {
                         acc.v[F_REJU] += sum < 0 ? -sum : sum;
                         acc.v[F_REJ] += sum;
                     }
                 }
-                ++jb;
             }
         }
-        long long tot;
-        const long long ex = block_excl_scan<long long>((long long)nout, tot, s_red);
-        if (threadIdx.x == 0) s_base = lookback(w.st_merge, tile, epoch, tot);
         __syncthreads();
-        const long long obase = s_base + ex;
-        for (int q = 0; q < nout; ++q) {
-            const long long o = obase + q;
-            if (o >= w.main_cap) {
-                atomicOr(&c->err, ERR_MAIN_CAP);
-                break;
-            }
-            const int rep = (int)skey_rep(osk[q], w.rb);
-            const RepParams rp = w.rep[rep];
-            const DevSys &sy = w.sys[rp.sys];
-            w.nxt.skey[o] = osk[q];
+        // K_jj - H_00 of the accepted new determinants, one per thread
+        for (int q = threadIdx.x; q < s_nnew; q += MG_T) {
+            const int slot = s_newq[q];
+            uint64_t key[W];
 #pragma unroll
-            for (int x = 0; x < W; ++x) w.nxt.key[(size_t)x * w.main_cap + o] = okey[q][x];
-            const int32_t p = opop[q];
-            w.nxt.pop[o] = p;
-            w.nxt.kdiag[o] = okd[q];
-            w.nxt.dslot[o] = ods[q];
-            if (ods[q] >= 0) w.ds.pos[(size_t)rep * w.ds.n + ods[q]] = (int32_t)o;
-            const long long ap = p < 0 ? -(long long)p : (long long)p;
-            long long nat;
-            if (rp.bits == 0) {
-                nat = ap;
-                if (ap >= (1ll << 28)) atomicOr(&c->err, ERR_ATTEMPTS);
-            } else {
-                nat = (ap + (1ll << rp.bits) - 1) >> rp.bits;
-            }
-            w.nxt.natt[o] = (int32_t)nat;
-            if (rep != acc.rep) {
-                if (acc.rep >= 0) {
+            for (int x = 0; x < W; ++x) key[x] = s_key[x][slot];
+            const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
+            const DevSys &sy = w.sys[w.rep[rep].sys];
+            s_kd[slot] = diag_element<KIND, W>(sy, key) - sy.H00;
+        }
+        // ranks of the kept entries in merge order
+        int cnt = 0;
+        for (int st = 0; st < steps; ++st) cnt += s_keep[dl + st];
+        long long tot;
+        const long long ex = block_excl_scan<long long>((long long)cnt, tot, s_red);
+        if (threadIdx.x < 64) {
+            const long long lb_ = lookback(w.st_merge, tile, epoch, tot);
+            if (threadIdx.x == 0) s_base = lb_;
+        }
+        {
+            int r = (int)ex;
+            for (int st = 0; st < steps; ++st)
+                if (s_keep[dl + st]) s_dst[dl + st] = (uint16_t)r++;
+        }
+        __syncthreads();
+        const long long obase = s_base;
+        if (obase + tot > w.main_cap) {
+            if (threadIdx.x == 0) atomicOr(&c->err, ERR_MAIN_CAP);
+        } else {
+            for (int m = threadIdx.x; m < la + lb; m += MG_T) {
+                if (!s_keep[m]) continue;
+                const long long o = obase + s_dst[m];
+                const int slot = s_src[m];
+                const uint64_t sk = s_sk[slot];
+                const int rep = MULTI ? (int)skey_rep(sk, w.rb) : 0;
+                const RepParams &rp = w.rep[rep];
+                const DevSys &sy = w.sys[rp.sys];
+                const int32_t p = (int32_t)s_val[slot];
+                const int32_t ds = s_meta[slot];
+                w.nxt.skey[o] = sk;
+                uint64_t key[W];
 #pragma unroll
-                    for (int f = 0; f < EST_FIELDS; ++f)
-                        if (acc.v[f]) atomicAdd((unsigned long long *)(&w.acc[acc.rep].nw + f), (unsigned long long)acc.v[f]);
-                    acc.clear();
+                for (int x = 0; x < W; ++x) {
+                    key[x] = s_key[x][slot];
+                    w.nxt.key[(size_t)x * w.main_cap + o] = key[x];
                 }
-                acc.rep = rep;
-            }
-            any = true;
-            acc.v[F_NW] += ap;
-            acc.v[F_NOCC] += 1;
-            const uint64_t(&ref)[W] = *(const uint64_t(*)[W])sy.ref;
-            int nd = 0;
+                w.nxt.pop[o] = p;
+                w.nxt.kdiag[o] = s_kd[slot];
+                w.nxt.dslot[o] = ds;
+                if (ds >= 0) w.ds.pos[(size_t)rep * w.ds.n + ds] = (int32_t)o;
+                const long long ap = p < 0 ? -(long long)p : (long long)p;
+                long long nat;
+                if (rp.bits == 0) {
+                    nat = ap;
+                    if (ap >= (1ll << 28)) atomicOr(&c->err, ERR_ATTEMPTS);
+                } else {
+                    nat = (ap + (1ll << rp.bits) - 1) >> rp.bits;
+                }
+                w.nxt.natt[o] = (int32_t)nat;
+                acc_switch(acc, rep, w.acc);
+                any = true;
+                acc.v[F_NW] += ap;
+                acc.v[F_NOCC] += 1;
+                const uint64_t(&ref)[W] = *(const uint64_t(*)[W])sy.ref;
+                int nd = 0;
 #pragma unroll
-            for (int x = 0; x < W; ++x) nd += __popcll(okey[q][x] ^ ref[x]);
-            if (nd == 0) {
-                acc.v[F_N0] += p;
-            } else if (nd == 2 || nd == 4) {
-                const double hv = hij<KIND, W>(sy, ref, okey[q]);
-                add_limbs(acc.v, hv * (double)p);
+                for (int x = 0; x < W; ++x) nd += __popcll(key[x] ^ ref[x]);
+                if (nd == 0) {
+                    acc.v[F_N0] += p;
+                } else if (nd == 2 || nd == 4) {
+                    const double hv = hij<KIND, W>(sy, ref, key);
+                    add_limbs(acc.v, hv * (double)p);
+                }
             }
         }
-        if (tile == ntiles - 1 && threadIdx.x == 0) c->n_main_new = s_base + tot;
+        if (tile == ntiles - 1 && threadIdx.x == 0) c->n_main_new = obase + tot;
         __syncthreads();
     }
     flush_acc(acc, w.acc, any && acc.rep >= 0);
@@ -1089,8 +1224,10 @@ __global__ __launch_bounds__(256) void k_det_project_fp64(Work w)
 
 // explicit instantiations
 #define FQ_INST(KIND, W)                                   \
-    template __global__ void k_spawn<KIND, W>(Work);       \
-    template __global__ void k_merge<KIND, W>(Work);
+    template __global__ void k_spawn<KIND, W, false>(Work); \
+    template __global__ void k_spawn<KIND, W, true>(Work);  \
+    template __global__ void k_merge<KIND, W, false>(Work); \
+    template __global__ void k_merge<KIND, W, true>(Work);
 FQ_INST(K_HUBBARD, 1)
 FQ_INST(K_UEG, 1)
 FQ_INST(K_UEG, 2)
@@ -1187,34 +1324,52 @@ FQ_INST2(K_MOLECULAR, 2)
 template <int KIND, int W>
 static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t *ev)
 {
-    auto rec = [&](int i) {
-        if (ev) hipEventRecord(ev[i], s);
+    // ev (optional): N_KERNEL_SLOTS + 1 events, one before the first launch and
+    // one after every launch of the iteration
+    int e = 0;
+    auto rec = [&]() {
+        if (ev) hipEventRecord(ev[e++], s);
     };
-    rec(0);
+    rec();
     k_begin<<<1, 256, 0, s>>>(w);
+    rec();
     k_scan_attempts<<<g.scan, SCAN_T, 0, s>>>(w);
+    rec();
     k_spawn_partition<<<g.part, 256, 0, s>>>(w);
-    rec(1);
-    k_spawn<KIND, W><<<g.spawn, SPAN, 0, s>>>(w);
-    rec(2);
+    rec();
+    if (w.R > 1)
+        k_spawn<KIND, W, true><<<g.spawn, SP_T, 0, s>>>(w);
+    else
+        k_spawn<KIND, W, false><<<g.spawn, SP_T, 0, s>>>(w);
+    rec();
     k_sort_hist<<<g.hist, 256, 0, s>>>(w);
+    rec();
     uint64_t *K[2] = {w.sp.skey, w.sp.skey2};
     uint32_t *I[2] = {w.sp.idx, w.sp.idx2};
-    for (int p = 0; p < 8; ++p)
+    for (int p = 0; p < 8; ++p) {
         k_sort_pass<<<g.sort, OS_T, 0, s>>>(w, p, K[p & 1], p == 0 ? nullptr : I[p & 1], K[(p + 1) & 1],
                                              I[(p + 1) & 1]);
-    rec(3);
+        rec();
+    }
     k_reduce<W><<<g.reduce, RD_T, 0, s>>>(w, 0);
+    rec();
     k_fixup<W><<<g.fixup, 256, 0, s>>>(w);
+    rec();
     k_reduce<W><<<g.reduce, RD_T, 0, s>>>(w, 1);
-    rec(4);
+    rec();
     k_det_gather<<<g.det, 256, 0, s>>>(w);
+    rec();
     k_det_project_fp64<<<g.det, 256, 0, s>>>(w);
-    rec(5);
+    rec();
     k_merge_partition<W><<<g.part, 256, 0, s>>>(w);
-    k_merge<KIND, W><<<g.merge, MG_T, 0, s>>>(w);
+    rec();
+    if (w.R > 1)
+        k_merge<KIND, W, true><<<g.merge, MG_T, 0, s>>>(w);
+    else
+        k_merge<KIND, W, false><<<g.merge, MG_T, 0, s>>>(w);
+    rec();
     k_end<<<1, 64, 0, s>>>(w);
-    rec(6);
+    rec();
 }
 
 hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_t s, hipEvent_t *ev)
@@ -1262,9 +1417,10 @@ int occupancy_blocks(int which)
     int nb = 1;
     switch (which) {
     case 0: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass, OS_T, 0); break;
-    case 1: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2>, MG_T, 0); break;
+    case 1: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false>, MG_T, 0); break;
     case 2: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce<2>, RD_T, 0); break;
     case 3: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan_attempts, SCAN_T, 0); break;
+    case 4: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false>, SP_T, 0); break;
     default: break;
     }
     return nb < 1 ? 1 : nb;

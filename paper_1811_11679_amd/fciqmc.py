@@ -23,7 +23,11 @@ SS_FP64, SS_SPLIT_BF16 = 0, 1
 # every function the header declares
 C_API = ["fq_workspace_bytes", "fq_init_system", "fq_step", "fq_estimators", "fq_estimator_history",
          "fq_export_walkers", "fq_import_walkers", "fq_export_spawns", "fq_detspace", "fq_info",
-         "fq_set_timing", "fq_stage_times", "fq_last_error", "fq_destroy"]
+         "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_last_error", "fq_destroy"]
+
+KERNEL_SLOTS = ["begin", "scan_attempts", "spawn_partition", "spawn", "sort_hist"] + \
+    [f"sort_pass{p}" for p in range(8)] + ["reduce", "fixup", "reduce2", "det_gather", "det_project",
+                                            "merge_partition", "merge", "end"]
 
 
 class FqError(RuntimeError):
@@ -106,6 +110,9 @@ def load_library():
     L.fq_set_timing.restype = C.c_int32
     L.fq_stage_times.argtypes = [P, C.POINTER(C.c_double)]
     L.fq_stage_times.restype = C.c_int32
+    L.fq_kernel_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int64)]
+    L.fq_kernel_times.restype = C.c_int32
     L.fq_last_error.argtypes = [P]
     L.fq_last_error.restype = C.c_char_p
     L.fq_destroy.argtypes = [P]
@@ -260,3 +267,10 @@ class Context:
         self._check(self.lib.fq_stage_times(self.ctx, arr))
         names = ["scan", "spawn", "sort", "reduce", "merge", "detproj", "iteration"]
         return dict(zip(names, list(arr)))
+
+    def kernel_times(self):
+        """{slot name: summed ms}, and the number of timed iterations"""
+        arr = (C.c_double * len(KERNEL_SLOTS))()
+        ns, ni = C.c_int32(), C.c_int64()
+        self._check(self.lib.fq_kernel_times(self.ctx, arr, len(KERNEL_SLOTS), C.byref(ns), C.byref(ni)))
+        return dict(zip(KERNEL_SLOTS, list(arr))), ni.value
