@@ -32,14 +32,15 @@ def algorithmic_bytes(hist_prev, hist, W):
     nm, nm2 = hist_prev["n_occupied"], hist["n_occupied"]
     ns, nu = hist["n_spawned"], hist["n_spawn_events"]
     kb = 8 * W
-    out["scan_attempts"] = nm * (4 + 8)
-    out["spawn"] = nm * (kb + 8 + 4 + 4 + 8) + ns * (8 + kb + 4 + 1 + 8 + 4)
+    nn = hist["n_spawn_events"]  # upper bound of new determinants
+    out["spawn"] = nm * (kb + 8 + 4 + 4 + 8) + ns * (8 + kb + 8 + 8 + 4)
     out["sort_pass0"] = ns * (8 + 8 + 4)
     for p in range(1, 8):
         out[f"sort_pass{p}"] = ns * (8 + 4) * 2
     out["sort_hist"] = ns * 8
-    out["reduce"] = ns * (8 + 4 + kb + 4 + 1) + nu * (8 + kb + 8 + 4)
-    out["merge"] = nm * (8 + kb + 4 + 8 + 4) + nu * (8 + kb + 8 + 4) + nm2 * (8 + kb + 4 + 8 + 4 + 4)
+    out["reduce"] = ns * (8 + 4 + kb + 8) + nu * (8 + kb + 8 + 4)
+    out["merge"] = nm * (8 + kb + 4 + 8 + 4) + nu * (8 + kb + 8 + 4) + nm2 * (8 + kb + 4 + 8 + 4 + 8)
+    out["new_diag"] = nm2 * 8
     return out
 
 
@@ -123,8 +124,7 @@ def main():
         for k, v in algorithmic_bytes(a, b, ctx.W).items():
             tot_bytes[k] = tot_bytes.get(k, 0) + v
     groups = {"sort_pass": [f"sort_pass{p}" for p in range(8)]}
-    cand = {"spawn": ["spawn"], "merge": ["merge"], "reduce": ["reduce"], "scan_attempts": ["scan_attempts"],
-            **groups}
+    cand = {"spawn": ["spawn"], "merge": ["merge"], "reduce": ["reduce"], "new_diag": ["new_diag"], **groups}
     best = max(cand, key=lambda g: sum(ktimes[k] for k in cand[g]))
     launches = niter * len(cand[best])
     avg_ms = sum(ktimes[k] for k in cand[best]) / max(launches, 1)

@@ -198,7 +198,7 @@ fq_status fq_info(const fq_ctx *ctx, int32_t *W, int32_t *n_spin_orbitals, doubl
 
 /* Per-stage device time of the last fq_step call, in milliseconds, summed
  * over its iterations, measured with HIP events on the context's stream:
- * [0] attempt scan, [1] spawning, [2] radix sort, [3] segmented reduction,
+ * [0] attempt partition, [1] spawning, [2] radix sort, [3] segmented reduction,
  * [4] merge with death and estimators, [5] deterministic projection,
  * [6] whole iterations. Timing is recorded only after fq_set_timing(ctx, 1). */
 fq_status fq_set_timing(fq_ctx *ctx, int32_t on);
@@ -206,9 +206,10 @@ fq_status fq_stage_times(const fq_ctx *ctx, double *ms7);
 
 /* Per-kernel device time of the last fq_step call (timing on), summed over its
  * iterations, one slot per launch of an iteration in launch order: begin,
- * attempt scan, attempt partition, spawn, sort histogram, sort passes 0..7,
+ * attempt partition, spawn, sort histogram, sort passes 0..7,
  * reduce, collision fix-up, reduce (repeat), projection gather, projection,
- * merge partition, merge, end. *n_slots receives the slot count (21) and
+ * merge partition, merge, new-determinant diagonals, end. *n_slots receives
+ * the slot count (21) and
  * *n_iterations the number of timed iterations. */
 fq_status fq_kernel_times(const fq_ctx *ctx, double *ms, int32_t cap, int32_t *n_slots,
                           int64_t *n_iterations);

@@ -216,18 +216,27 @@ __device__ __forceinline__ int key_cmp(const uint64_t (&a)[W], const uint64_t (&
 // Systems. One DevSys per replica lives in device memory; its tables are
 // built on the host from the system description.
 // ---------------------------------------------------------------------------
+// The UEG tables, as a small view that kernels can point at LDS copies.
+struct UegTables {
+    const int32_t *npk;   // [M] plane-wave vectors, 10 bits per component biased by 256
+    const double *eps;    // kinetic energy per plane wave
+    const double *vtab;   // v(|dn|^2)
+    const double *vx;     // [M][M] v(|n_p - n_q|^2), or nullptr: use vtab and npk
+    const int16_t *grid;  // momentum grid -> plane-wave index, -1 outside
+    int32_t M, nel, gmax, gdim;
+};
+
 struct DevSys {
     int32_t kind, n_spatial, n_so, nel, na, nb;
     int32_t periodic;
     double t, U;
-    int32_t gmax, gdim, vlen, pad0;
-    const int32_t *npk;   // [M] plane-wave vectors, 10 bits per component biased by 256
-    const double *eps;    // kinetic energy per plane wave
-    const double *vtab;   // v(|dn|^2)
-    const double *vx;     // [M][M] v(|n_p - n_q|^2) (0 on the diagonal)
-    const int16_t *grid;  // momentum grid -> plane-wave index, -1 outside
+    int32_t vlen, pad0;
+    UegTables u;
     const double *h1;     // [n][n]
     const double *eri;    // [n][n][n][n] chemists' notation
+    const double *hd;     // [n] h_pp
+    const double *Jt;     // [n][n] (pp|qq)
+    const double *Kt;     // [n][n] (pq|qp)
     const int64_t *hb_off;  // [n_so][n_so] first entry of pair (P<Q)
     const int32_t *hb_cnt;  // entries of pair
     const double *hb_S;     // [n_so][n_so] total weight of pair
@@ -248,6 +257,11 @@ __device__ __forceinline__ double eri_at(const DevSys &s, int p, int q, int r, i
 // packed plane-wave vectors: component c in bits [10c, 10c + 10), biased by 256;
 // sums and differences of a few vectors stay inside each 10-bit field
 __device__ __forceinline__ int pk_comp(int32_t v, int c) { return ((v >> (10 * c)) & 1023) - 256; }
+__device__ __forceinline__ int pk_dn2(int32_t u, int32_t v)
+{
+    const int dx = pk_comp(u, 0) - pk_comp(v, 0), dy = pk_comp(u, 1) - pk_comp(v, 1), dz = pk_comp(u, 2) - pk_comp(v, 2);
+    return dx * dx + dy * dy + dz * dz;
+}
 
 // calls f(P) for every set bit P of a key, in ascending order
 template <int W, typename F>
@@ -276,6 +290,40 @@ __device__ __forceinline__ void for_pairs(const uint64_t (&key)[W], F &&f)
     });
 }
 
+// UEG: <AB|PQ> - <AB|QP> with momentum conservation
+__device__ __forceinline__ double antisym_ueg(const UegTables &u, int A, int B, int P, int Q)
+{
+    const int sa = A & 1, sb = B & 1, sp = P & 1, sq = Q & 1;
+    const int a = A >> 1, b = B >> 1, p = P >> 1, q = Q >> 1;
+    const int32_t na = u.npk[a], np = u.npk[p], nq = u.npk[q];
+    if (na + u.npk[b] != np + nq) return 0.0;
+    double x = 0.0, y = 0.0;
+    if (u.vx) {
+        if (sa == sp && sb == sq) x = u.vx[p * u.M + a];
+        if (sa == sq && sb == sp) y = u.vx[q * u.M + a];
+    } else {
+        // the same values from v(|dn|^2)
+        if (sa == sp && sb == sq) x = u.vtab[pk_dn2(np, na)];
+        if (sa == sq && sb == sp) y = u.vtab[pk_dn2(nq, na)];
+    }
+    return x - y;
+}
+
+// UEG diagonal: kinetic energies, then same-spin exchange over pairs P < Q
+template <int W>
+__device__ double diag_ueg(const UegTables &u, const uint64_t (&key)[W])
+{
+    double e = 0.0;
+    for_bits<W>(key, [&](int P) { e = e + u.eps[P >> 1]; });
+    for_pairs<W>(key, [&](int P, int Q) {
+        if ((P & 1) == (Q & 1)) {
+            const double v = u.vx ? u.vx[(P >> 1) * u.M + (Q >> 1)] : u.vtab[pk_dn2(u.npk[P >> 1], u.npk[Q >> 1])];
+            e = e - v;
+        }
+    });
+    return e;
+}
+
 // Diagonal element <D|H|D> (Slater-Condon, fixed summation order: one
 // ascending sweep of the occupied orbitals, then all pairs P < Q ascending).
 template <int KIND, int W>
@@ -288,19 +336,14 @@ __device__ double diag_element(const DevSys &s, const uint64_t (&key)[W])
             if (((k >> (2 * p)) & 1) && ((k >> (2 * p + 1)) & 1)) e = e + s.U;
         return e;
     } else if constexpr (KIND == K_UEG) {
-        const int M = s.n_spatial;
-        for_bits<W>(key, [&](int P) { e = e + s.eps[P >> 1]; });
-        for_pairs<W>(key, [&](int P, int Q) {
-            if ((P & 1) == (Q & 1)) e = e - s.vx[(P >> 1) * M + (Q >> 1)];
-        });
-        return e;
+        return diag_ueg<W>(s.u, key);
     } else {
         const int n = s.n_spatial;
-        for_bits<W>(key, [&](int P) { e = e + s.h1[(size_t)(P >> 1) * n + (P >> 1)]; });
+        for_bits<W>(key, [&](int P) { e = e + s.hd[P >> 1]; });
         for_pairs<W>(key, [&](int P, int Q) {
             const int p = P >> 1, q = Q >> 1;
-            const double x = eri_at(s, p, p, q, q);
-            const double y = ((P & 1) == (Q & 1)) ? eri_at(s, p, q, q, p) : 0.0;
+            const double x = s.Jt[p * n + q];
+            const double y = ((P & 1) == (Q & 1)) ? s.Kt[p * n + q] : 0.0;
             e = e + (x - y);
         });
         return e;
@@ -316,11 +359,7 @@ __device__ __forceinline__ double antisym(const DevSys &s, int A, int B, int P, 
     if constexpr (KIND == K_HUBBARD) {
         return 0.0;
     } else if constexpr (KIND == K_UEG) {
-        if (s.npk[a] + s.npk[b] != s.npk[p] + s.npk[q]) return 0.0;  // momentum conservation
-        const int M = s.n_spatial;
-        const double x = (sa == sp && sb == sq) ? s.vx[p * M + a] : 0.0;
-        const double y = (sa == sq && sb == sp) ? s.vx[q * M + a] : 0.0;
-        return x - y;
+        return antisym_ueg(s.u, A, B, P, Q);
     } else {
         const double x = (sa == sp && sb == sq) ? eri_at(s, a, p, b, q) : 0.0;
         const double y = (sa == sq && sb == sp) ? eri_at(s, a, q, b, p) : 0.0;
@@ -458,20 +497,22 @@ __device__ bool gen_hubbard(const DevSys &s, const uint64_t (&D)[W], uint32_t w0
 // UEG: uniform pair of occupied spin-orbitals, uniform A (same spin as the
 // pair, or any spin for an opposite-spin pair), B fixed by momentum.
 template <int W>
-__device__ bool gen_ueg(const DevSys &s, const uint64_t (&D)[W], uint32_t w0, uint32_t w1,
+__device__ bool gen_ueg(const UegTables &s, const uint64_t (&D)[W], uint32_t w0, uint32_t w1,
                         uint64_t (&child)[W], double &pgen, double &h)
 {
     const int N = s.nel;
     const uint32_t npairs = (uint32_t)(N * (N - 1) / 2);
-    uint32_t rem = pick(w0, npairs);
-    int i = 0;
-    while (rem >= (uint32_t)(N - 1 - i)) {
-        rem -= (uint32_t)(N - 1 - i);
-        ++i;
-    }
-    const int j = i + 1 + (int)rem;
+    const int k = (int)pick(w0, npairs);
+    // lexicographic unranking: i is the largest with i (2N - i - 1) / 2 <= k
+    // (square-root estimate, then an exact integer correction)
+    const float bb = (float)(2 * N - 1);
+    int i = (int)((bb - sqrtf(bb * bb - 8.0f * (float)k)) * 0.5f);
+    i = i < 0 ? 0 : (i > N - 2 ? N - 2 : i);
+    while (i > 0 && i * (2 * N - i - 1) / 2 > k) --i;
+    while (i < N - 2 && (i + 1) * (2 * N - i - 2) / 2 <= k) ++i;
+    const int j = i + 1 + (k - i * (2 * N - i - 1) / 2);
     const int P = select_bit<W>(D, i), Q = select_bit<W>(D, j);
-    const int sP = P & 1, sQ = Q & 1, M = s.n_spatial;
+    const int sP = P & 1, sQ = Q & 1, M = s.M;
     int A, na;
     if (sP == sQ) {
         na = M;
@@ -498,7 +539,14 @@ __device__ bool gen_ueg(const DevSys &s, const uint64_t (&D)[W], uint32_t w0, ui
     flipbit<W>(child, lo);
     flipbit<W>(child, hi);
     pgen = 2.0 / (double)((int64_t)npairs * na);
-    h = double_element<K_UEG, W>(s, D, P, Q, lo, hi);
+    uint64_t tmp[W];
+#pragma unroll
+    for (int t2 = 0; t2 < W; ++t2) tmp[t2] = D[t2];
+    const double s1 = parity_between<W>(tmp, P, lo);
+    flipbit<W>(tmp, P);
+    flipbit<W>(tmp, lo);
+    const double s2 = parity_between<W>(tmp, Q, hi);
+    h = (s1 * s2) * antisym_ueg(s, lo, hi, P, Q);
     return true;
 }
 

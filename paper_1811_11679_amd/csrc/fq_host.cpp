@@ -73,7 +73,7 @@ struct HostSys {
     std::vector<int32_t> npk;
     std::vector<double> eps, vtab, vx;
     std::vector<int16_t> grid;
-    std::vector<double> h1, eri;
+    std::vector<double> h1, eri, hd, Jt, Kt;
     std::vector<int64_t> hb_off;
     std::vector<int32_t> hb_cnt;
     std::vector<double> hb_S, hb_cdf;
@@ -169,6 +169,17 @@ std::string build_system(const fq_system &d, HostSys &s)
         s.n_spatial = n;
         s.h1.assign(d.h1, d.h1 + (size_t)n * n);
         s.eri.assign(d.eri, d.eri + (size_t)n * n * n * n);
+        // exact copies of the integrals the diagonal element reads
+        s.hd.resize(n);
+        s.Jt.resize((size_t)n * n);
+        s.Kt.resize((size_t)n * n);
+        for (int p = 0; p < n; ++p) {
+            s.hd[p] = s.h1[(size_t)p * n + p];
+            for (int q = 0; q < n; ++q) {
+                s.Jt[(size_t)p * n + q] = s.eri[(((size_t)p * n + p) * n + q) * n + q];
+                s.Kt[(size_t)p * n + q] = s.eri[(((size_t)p * n + q) * n + q) * n + p];
+            }
+        }
         for (int i = 0; i < d.n_alpha; ++i) setbit_h(s.ref, 2 * i);
         for (int i = 0; i < d.n_beta; ++i) setbit_h(s.ref, 2 * i + 1);
         const int ns = 2 * n;
@@ -209,13 +220,13 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t table_bytes(const HostSys &s)
 {
     return al(4 * s.npk.size()) + al(8 * s.eps.size()) + al(8 * s.vtab.size()) + al(8 * s.vx.size()) + al(2 * s.grid.size()) +
-           al(8 * s.h1.size()) + al(8 * s.eri.size()) + al(8 * s.hb_off.size()) + al(4 * s.hb_cnt.size()) +
+           al(8 * s.h1.size()) + al(8 * s.eri.size()) + al(8 * s.hd.size()) + al(8 * s.Jt.size()) + al(8 * s.Kt.size()) + al(8 * s.hb_off.size()) + al(4 * s.hb_cnt.size()) +
            al(8 * s.hb_S.size()) + al(2 * s.hb_AB.size()) + al(8 * s.hb_cdf.size());
 }
 
 struct Layout {
     size_t total = 0;
-    size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge, st_spawn;
+    size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge, st_spawn, st_att;
     size_t main[2][6];
     size_t sp[7];
     size_t u[4];
@@ -252,6 +263,7 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
     L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 512));
     L.st_spawn = take(8 * (size_t)(span_capacity(mcap, scap) + 2));
+    L.st_att = take(8 * (size_t)tiles_of(mcap + scap, 512));
     for (int b = 0; b < 2; ++b) {
         L.main[b][0] = take(8 * (size_t)mcap);
         L.main[b][1] = take(8 * (size_t)mcap * W);
@@ -261,9 +273,9 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
         L.main[b][5] = take(4 * (size_t)mcap);
     }
     L.sp[0] = take(8 * (size_t)scap);
-    L.sp[1] = take(8 * (size_t)scap * W);
-    L.sp[2] = take(4 * (size_t)scap);
-    L.sp[3] = take((size_t)scap);
+    L.sp[1] = take(8 * (size_t)scap * (W + 1));
+    L.sp[2] = take(0);
+    L.sp[3] = take(0);
     L.sp[4] = take(8 * (size_t)scap);
     L.sp[5] = take(4 * (size_t)scap);
     L.sp[6] = take(4 * (size_t)scap);
@@ -432,6 +444,15 @@ fq_status upload_main(fq_ctx *c, const std::vector<HostEntry> &e)
         HIPCHK(c, hipMemcpy(m.dslot, ds.data(), 4 * n, hipMemcpyHostToDevice));
     }
     set_main_views(c);
+    {
+        Ctl ctl0;
+        HIPCHK(c, hipMemcpy(&ctl0, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+        ctl0.n_main = n;
+        ctl0.n_main_new = n;
+        std::memset(ctl0.tickets, 0, sizeof(ctl0.tickets));
+        HIPCHK(c, hipMemcpy(c->w.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice));
+    }
+    HIPCHK(c, hipMemset(c->ws + c->L.st_scan, 0, c->L.st_sort - c->L.st_scan));
     HIPCHK(c, enqueue_setup(1, c->kind, c->w, nullptr, 0, m, n, nullptr, nullptr, c->stream));
     Ctl ctl;
     HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
@@ -641,10 +662,9 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.st_red = (unsigned long long *)(c->ws + c->L.st_red);
     w.st_merge = (unsigned long long *)(c->ws + c->L.st_merge);
     w.st_spawn = (unsigned long long *)(c->ws + c->L.st_spawn);
+    w.st_att = (unsigned long long *)(c->ws + c->L.st_att);
     w.sp.skey = (uint64_t *)(c->ws + c->L.sp[0]);
-    w.sp.key = (uint64_t *)(c->ws + c->L.sp[1]);
-    w.sp.amp = (int32_t *)(c->ws + c->L.sp[2]);
-    w.sp.init = (uint8_t *)(c->ws + c->L.sp[3]);
+    w.sp.rec = (uint64_t *)(c->ws + c->L.sp[1]);
     w.sp.skey2 = (uint64_t *)(c->ws + c->L.sp[4]);
     w.sp.idx = (uint32_t *)(c->ws + c->L.sp[5]);
     w.sp.idx2 = (uint32_t *)(c->ws + c->L.sp[6]);
@@ -698,16 +718,21 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         d.periodic = s.periodic;
         d.t = s.t;
         d.U = s.U;
-        d.gmax = s.gmax;
-        d.gdim = s.gdim;
+        d.u.gmax = s.gmax;
+        d.u.gdim = s.gdim;
+        d.u.M = s.n_spatial;
+        d.u.nel = s.nel;
         d.vlen = s.vlen;
-        d.npk = (const int32_t *)put(s.npk.data(), 4 * s.npk.size());
-        d.vx = (const double *)put(s.vx.data(), 8 * s.vx.size());
-        d.eps = (const double *)put(s.eps.data(), 8 * s.eps.size());
-        d.vtab = (const double *)put(s.vtab.data(), 8 * s.vtab.size());
-        d.grid = (const int16_t *)put(s.grid.data(), 2 * s.grid.size());
+        d.u.npk = (const int32_t *)put(s.npk.data(), 4 * s.npk.size());
+        d.u.vx = (const double *)put(s.vx.data(), 8 * s.vx.size());
+        d.u.eps = (const double *)put(s.eps.data(), 8 * s.eps.size());
+        d.u.vtab = (const double *)put(s.vtab.data(), 8 * s.vtab.size());
+        d.u.grid = (const int16_t *)put(s.grid.data(), 2 * s.grid.size());
         d.h1 = (const double *)put(s.h1.data(), 8 * s.h1.size());
         d.eri = (const double *)put(s.eri.data(), 8 * s.eri.size());
+        d.hd = (const double *)put(s.hd.data(), 8 * s.hd.size());
+        d.Jt = (const double *)put(s.Jt.data(), 8 * s.Jt.size());
+        d.Kt = (const double *)put(s.Kt.data(), 8 * s.Kt.size());
         d.hb_off = (const int64_t *)put(s.hb_off.data(), 8 * s.hb_off.size());
         d.hb_cnt = (const int32_t *)put(s.hb_cnt.data(), 4 * s.hb_cnt.size());
         d.hb_S = (const double *)put(s.hb_S.data(), 8 * s.hb_S.size());
@@ -756,6 +781,22 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     c->grids.reduce = ncu * occupancy_blocks(2);
     c->grids.part = ncu * 4;
     c->grids.spawn = ncu * occupancy_blocks(4);
+    // diagonal tables staged in LDS by the single-replica new-determinant kernel
+    if (c->R == 1 && (c->kind == FQ_UEG || c->kind == FQ_MOLECULAR)) {
+        const size_t m = (size_t)c->sys[0].n_spatial;
+        const size_t bytes = c->kind == FQ_UEG ? 8 * (m + m * m) : 8 * (m + 2 * m * m);
+        if (bytes <= 65536) w.lds_diag = (int32_t)bytes;
+    }
+    // UEG generator tables staged in LDS by the single-replica spawn kernel
+    if (c->R == 1 && c->kind == FQ_UEG) {
+        const HostSys &s0 = c->sys[0];
+        const size_t bytes = ((4 * (size_t)s0.n_spatial + 15) & ~(size_t)15) + ((8 * (size_t)s0.vlen + 15) & ~(size_t)15) +
+                             2 * s0.grid.size();
+        if (bytes <= 32768) {
+            c->grids.spawn_lds = (int)bytes;
+            w.lds_tables = (int32_t)bytes;
+        }
+    }
     c->grids.hist = ncu * 4;
     c->grids.fixup = ncu * 2;
     c->grids.det = ncu * 4;
@@ -828,7 +869,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         if (c->timing) {
             // stage boundaries in the launch order: scan+partition, spawn, sort
             // (histogram + 8 passes), reduce (2 passes + fix-up), projection, merge
-            static const int stage_of[N_KERNEL_SLOTS] = {0, 0, 0, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 5, 5, 4, 4, 4};
+            static const int stage_of[N_KERNEL_SLOTS] = {0, 0, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 5, 5, 4, 4, 4, 4};
             for (int k = 0; k < nb; ++k) {
                 hipEvent_t *e = &evs[(size_t)k * NE];
                 float ms = 0.f;
@@ -855,6 +896,25 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             fix.t = (uint32_t)(tf - 1);
             fix.n_main_new = ctl.n_main;
             HIPCHK(c, hipMemcpy(c->w.ctl, &fix, sizeof(Ctl), hipMemcpyHostToDevice));
+            // the failing merge may have written attempt offsets and deterministic
+            // positions for a list that is discarded: rebuild them for the restored one
+            {
+                std::vector<HostEntry> e;
+                int64_t nres;
+                fq_status st2 = download_main(c, e, nres);
+                if (st2) return st2;
+                st2 = upload_main(c, e);
+                if (st2) return st2;
+                if (c->ss_active) {
+                    std::vector<int32_t> pos((size_t)c->D * c->R, 0);
+                    for (int64_t i = 0; i < nres; ++i)
+                        if (e[i].dslot >= 0) {
+                            const uint32_t rep = c->rb ? (uint32_t)(e[i].skey >> (64 - c->rb)) : 0u;
+                            pos[(size_t)rep * c->D + e[i].dslot] = (int32_t)i;
+                        }
+                    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[3], pos.data(), 4 * pos.size(), hipMemcpyHostToDevice));
+                }
+            }
             for (int64_t it = t0 + 1; it < tf; ++it)
                 for (int r = 0; r < c->R; ++r) {
                     fq_estimators_t e;
@@ -866,6 +926,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                 }
             c->t = tf - 1;
             if (ctl.err & (ERR_OVERFLOW | ERR_ATTEMPTS)) return fail(c, FQ_EOVERFLOW, "population or spawn exceeds the fixed-point range");
+            if (ctl.err & ERR_COLLISION) return fail(c, FQ_ESTATE, "spawned list holds an implausibly long run of equal sort keys");
             return fail(c, FQ_ECAPACITY, (ctl.err & ERR_SPAWN_CAP) ? "spawn capacity exceeded" : "main list capacity exceeded");
         }
         for (int64_t it = t0 + 1; it <= stop; ++it) {
@@ -1018,10 +1079,14 @@ fq_status fq_export_spawns(const fq_ctx *cc, int32_t instance, uint64_t *keys, i
     if (n) {
         HIPCHK(c, hipMemcpy(sk.data(), c->w.sp.skey, 8 * n, hipMemcpyDeviceToHost));
         HIPCHK(c, hipMemcpy(ix.data(), c->w.sp.idx, 4 * n, hipMemcpyDeviceToHost));
-        for (int q = 0; q < c->W; ++q)
-            HIPCHK(c, hipMemcpy(kk.data() + (size_t)q * n, c->w.sp.key + (size_t)q * c->spawn_cap, 8 * n, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(am.data(), c->w.sp.amp, 4 * n, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(in.data(), c->w.sp.init, n, hipMemcpyDeviceToHost));
+        std::vector<uint64_t> rec((size_t)n * (c->W + 1));
+        HIPCHK(c, hipMemcpy(rec.data(), c->w.sp.rec, 8 * rec.size(), hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < n; ++j) {
+            for (int q = 0; q < c->W; ++q) kk[(size_t)q * n + j] = rec[(size_t)j * (c->W + 1) + q];
+            const uint64_t ai = rec[(size_t)j * (c->W + 1) + c->W];
+            am[j] = (int32_t)(uint32_t)ai;
+            in[j] = (uint8_t)(ai >> 32);
+        }
     }
     int64_t o = 0;
     for (int64_t p = 0; p < n; ++p) {

@@ -27,6 +27,7 @@ enum : uint32_t {
     ERR_OVERFLOW = 4u,
     ERR_ATTEMPTS = 8u,
     ERR_UNIQ_CAP = 16u,
+    ERR_COLLISION = 32u,
 };
 
 enum : int {
@@ -43,6 +44,7 @@ struct Ctl {
     long long n_main;      // determinants in the current main list (all replicas)
     long long n_main_new;  // written by the merge
     long long n_att;       // total spawning attempts this iteration
+    long long n_att_new;   // attempts of the list the merge has just written
     unsigned long long n_spawn;  // spawned walkers written
     long long n_uniq;      // distinct spawned determinants
     uint32_t t;            // iteration counter (1 = first iteration)
@@ -73,9 +75,7 @@ struct MainList {
 
 struct SpawnList {
     uint64_t *skey;   // sort key (replica | hash)
-    uint64_t *key;    // word-major
-    int32_t *amp;
-    uint8_t *init;
+    uint64_t *rec;    // records of W + 1 words: key words, then amp | init << 32
     uint64_t *skey2;  // radix ping-pong
     uint32_t *idx;
     uint32_t *idx2;
@@ -113,26 +113,30 @@ struct Work {
     long long *att_off;    // [main_cap + 1]
     long long *span_lo;    // [spans + 1]
     long long *mpart;      // merge partition [tiles + 1]
-    unsigned long long *st_scan, *st_sort, *st_red, *st_merge, *st_spawn;  // look-back status
+    unsigned long long *st_scan, *st_sort, *st_red, *st_merge, *st_spawn, *st_att;  // look-back status
     MainList cur, nxt;
     SpawnList sp;
     UniqList u;
     DetSpace ds;
     long long main_cap, spawn_cap, span_cap;
     int32_t R, rb, W, hist_len;
+    int32_t lds_tables;  // bytes of UEG tables the spawn kernel stages in LDS (0: read from global)
+    int32_t lds_diag;    // bytes of diagonal tables the new-determinant kernel stages in LDS
 };
 
 // launch geometry of the persistent kernels
 struct Grids {
     int scan, part, spawn, hist, sort, reduce, fixup, merge, det;
+    int spawn_lds;  // dynamic LDS bytes of the spawn kernel
 };
 
 // kernels of one iteration, in launch order (per-kernel timing slots)
 constexpr int N_KERNEL_SLOTS = 21;
 // enqueue one whole iteration on a stream (ev: N_KERNEL_SLOTS + 1 events or nullptr)
 hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_t s, hipEvent_t *ev);
-// set-up work: 0 = H_00 of every system, 1 = K_ii - H_00 and attempts of a
-// list of n entries, 2 = K_DD of the deterministic space
+// set-up work: 0 = H_00 of every system, 1 = K_ii - H_00, attempt counts and
+// attempt offsets of the current list of n entries, 2 = K_DD of the
+// deterministic space
 hipError_t enqueue_setup(int what, int kind, const Work &w, DevSys *sys, int n_sys, MainList L, long long n,
                          const uint64_t *dk, double *K, hipStream_t s);
 int occupancy_blocks(int which);

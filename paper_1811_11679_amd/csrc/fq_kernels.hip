@@ -165,7 +165,7 @@ __global__ void k_begin(Work w)
         c->n_main = c->n_main_new;
         c->n_spawn = 0;
         c->n_uniq = 0;
-        c->n_att = 0;
+        c->n_att = c->n_att_new;
         c->collision = 0;
     }
     for (int i = threadIdx.x; i < TK_COUNT; i += blockDim.x) c->tickets[i] = 0;
@@ -186,7 +186,8 @@ __global__ void k_end(Work w)
 }
 
 // ---------------------------------------------------------------------------
-// attempt scan: att_off = exclusive prefix of natt over the main list
+// attempt scan (set-up only; iterations get the prefix from the merge):
+// att_off = exclusive prefix of natt over the main list
 // ---------------------------------------------------------------------------
 constexpr int SCAN_T = 256, SCAN_I = 8, SCAN_TILE = SCAN_T * SCAN_I;
 
@@ -227,13 +228,13 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_attempts(Work w)
         }
         if (tile == ntiles - 1 && threadIdx.x == 0) {
             w.att_off[n] = s_base + tot;
-            c->n_att = s_base + tot;
+            c->n_att_new = s_base + tot;
         }
         __syncthreads();
     }
     if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
         w.att_off[0] = 0;
-        c->n_att = 0;
+        c->n_att_new = 0;
     }
 }
 
@@ -297,6 +298,24 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
     const bool ss = c->ss_active != 0;
     const uint32_t epoch = epoch_of(t, 12);
     const int lane = lane_id(), wid = threadIdx.x >> 6;
+    // single replica, UEG: the small tables of the generator live in LDS
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    UegTables lu = w.sys[w.rep[0].sys].u;
+    if constexpr (!MULTI && KIND == K_UEG) {
+        if (w.lds_tables > 0) {
+            const int M = lu.M, nv = w.sys[w.rep[0].sys].vlen, ng = lu.gdim * lu.gdim * lu.gdim;
+            int32_t *tn = (int32_t *)dyn_lds;
+            double *tv = (double *)(dyn_lds + ((4 * M + 15) & ~15));
+            int16_t *tg = (int16_t *)((unsigned char *)tv + ((8 * nv + 15) & ~15));
+            for (int i = threadIdx.x; i < M; i += SP_T) tn[i] = lu.npk[i];
+            for (int i = threadIdx.x; i < nv; i += SP_T) tv[i] = lu.vtab[i];
+            for (int i = threadIdx.x; i < ng; i += SP_T) tg[i] = lu.grid[i];
+            lu.npk = tn;
+            lu.vtab = tv;
+            lu.grid = tg;
+            lu.vx = nullptr;
+        }
+    }
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[TK_SPAWN], 1u);
         __syncthreads();
@@ -314,6 +333,9 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
         int32_t amp[SP_I];
         uint8_t init[SP_I];
         uint32_t rep[SP_I];
+        // blocked: thread t takes attempts 4t .. 4t+3 of the tile; one search
+        // finds the first parent, later attempts advance from it
+        long long ip = -1;
 #pragma unroll
         for (int it = 0; it < SP_I; ++it) {
             has[it] = false;
@@ -322,16 +344,21 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
             rep[it] = 0;
 #pragma unroll
             for (int q = 0; q < W; ++q) child[it][q] = 0;
-            const long long a = span * SPAN + it * SP_T + threadIdx.x;
+            const long long a = span * SPAN + (long long)threadIdx.x * SP_I + it;
             if (a < total) {
                 long long i;
                 if (staged) {
-                    int l = 0, h = (int)len;
-                    while (l < h) {
-                        const int m = (l + h) >> 1;
-                        if (s_off[m] <= a) l = m + 1; else h = m;
+                    if (ip < 0) {
+                        int l = 0, h = (int)len;
+                        while (l < h) {
+                            const int m = (l + h) >> 1;
+                            if (s_off[m] <= a) l = m + 1; else h = m;
+                        }
+                        ip = lo + l - 1;
+                    } else {
+                        while (s_off[ip - lo + 1] <= a) ++ip;
                     }
-                    i = lo + l - 1;
+                    i = ip;
                 } else {
                     i = upper_bound_ll(w.att_off, lo, hi + 2, a) - 1;
                 }
@@ -357,7 +384,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 if constexpr (KIND == K_HUBBARD)
                     ok = gen_hubbard<W>(sy, key, r0.x, child[it], pgen, hv);
                 else if constexpr (KIND == K_UEG)
-                    ok = gen_ueg<W>(sy, key, r0.x, r0.y, child[it], pgen, hv);
+                    ok = gen_ueg<W>(MULTI ? sy.u : lu, key, r0.x, r0.y, child[it], pgen, hv);
                 else
                     ok = gen_heatbath<W>(sy, rp.p_single, key, r0, (uint32_t)k, t, h, rp.k0, rp.k1, child[it], pgen, hv);
                 if (ok && hv != 0.0) {
@@ -454,10 +481,10 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
             for (uint32_t p = threadIdx.x; p < tot; p += SP_T) {
                 const long long o = base + p;
                 w.sp.skey[o] = s_rk[p];
+                uint64_t *rec = w.sp.rec + (size_t)o * (W + 1);
 #pragma unroll
-                for (int q = 0; q < W; ++q) w.sp.key[(size_t)q * w.spawn_cap + o] = s_rkey[q][p];
-                w.sp.amp[o] = s_ramp[p];
-                w.sp.init[o] = s_rinit[p];
+                for (int q = 0; q < W; ++q) rec[q] = s_rkey[q][p];
+                rec[W] = (uint64_t)(uint32_t)s_ramp[p] | ((uint64_t)s_rinit[p] << 32);
                 w.u.sum[o] = 0;
                 w.u.flag[o] = 0;
             }
@@ -663,11 +690,12 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
             for (int q = 0; q < W; ++q) kk[i][q] = 0;
             if (valid[i]) {
                 sk[i] = skey[e];
-                const uint32_t j = idx[e];
+                const uint64_t *rec = w.sp.rec + (size_t)idx[e] * (W + 1);
 #pragma unroll
-                for (int q = 0; q < W; ++q) kk[i][q] = w.sp.key[(size_t)q * w.spawn_cap + j];
-                am[i] = w.sp.amp[j];
-                fl[i] = w.sp.init[j];
+                for (int q = 0; q < W; ++q) kk[i][q] = rec[q];
+                const uint64_t ai = rec[W];
+                am[i] = (int32_t)(uint32_t)ai;
+                fl[i] = (uint32_t)(ai >> 32);
             }
         }
         s_lasts[threadIdx.x] = sk[RD_I - 1];
@@ -683,9 +711,9 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
             for (int q = 0; q < W; ++q) pk[q] = s_lastk[threadIdx.x - 1][q];
         } else if (base > 0) {
             psk = skey[base - 1];
-            const uint32_t j = idx[base - 1];
+            const uint64_t *rec = w.sp.rec + (size_t)idx[base - 1] * (W + 1);
 #pragma unroll
-            for (int q = 0; q < W; ++q) pk[q] = w.sp.key[(size_t)q * w.spawn_cap + j];
+            for (int q = 0; q < W; ++q) pk[q] = rec[q];
         } else {
             psk = 0;
 #pragma unroll
@@ -765,7 +793,9 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
 }
 
 // Rare path: equal sort keys holding different determinants are put in key
-// order (insertion sort of the run), and the reduction is redone.
+// order (insertion sort of the run), and the reduction is redone. Runs are
+// bounded: such a run only arises from 64-bit hash collisions.
+constexpr long long FIXUP_MAX_RUN = 4096;
 template <int W>
 __global__ void k_fixup(Work w)
 {
@@ -787,19 +817,24 @@ __global__ void k_fixup(Work w)
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) {
         if (i > 0 && skey[i - 1] == skey[i]) continue;
         long long e = i + 1;
-        while (e < n && skey[e] == skey[i]) ++e;
+        while (e < n && e - i <= FIXUP_MAX_RUN && skey[e] == skey[i]) ++e;
         if (e - i < 2) continue;
+        if (e - i > FIXUP_MAX_RUN) {
+            // equal sort keys this long cannot come from hash collisions: refuse
+            atomicOr(&c->err, ERR_COLLISION);
+            continue;
+        }
         for (long long a = i + 1; a < e; ++a) {
             const uint32_t ja = idx[a];
             uint64_t ka[W];
 #pragma unroll
-            for (int q = 0; q < W; ++q) ka[q] = w.sp.key[(size_t)q * w.spawn_cap + ja];
+            for (int q = 0; q < W; ++q) ka[q] = w.sp.rec[(size_t)ja * (W + 1) + q];
             long long b = a - 1;
             while (b >= i) {
                 uint64_t kb[W];
                 const uint32_t jb = idx[b];
 #pragma unroll
-                for (int q = 0; q < W; ++q) kb[q] = w.sp.key[(size_t)q * w.spawn_cap + jb];
+                for (int q = 0; q < W; ++q) kb[q] = w.sp.rec[(size_t)jb * (W + 1) + q];
                 if (key_cmp<W>(kb, ka) <= 0) break;
                 idx[b + 1] = jb;
                 --b;
@@ -907,6 +942,18 @@ __device__ __forceinline__ void acc_switch(LocalAcc &acc, int rep, EstAcc *g)
     acc.rep = rep;
 }
 
+// spawning attempts of a determinant holding p units: |p| for integer walkers,
+// ceil(|p| 2^-b) for fixed point
+__device__ __forceinline__ long long attempts_of(long long p, int bits, Ctl *c)
+{
+    const long long ap = p < 0 ? -p : p;
+    if (bits == 0) {
+        if (ap >= (1ll << 28)) atomicOr(&c->err, ERR_ATTEMPTS);
+        return ap;
+    }
+    return (ap + (1ll << bits) - 1) >> bits;
+}
+
 template <int KIND, int W, bool MULTI>
 __global__ __launch_bounds__(MG_T) void k_merge(Work w)
 {
@@ -925,14 +972,12 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
     __shared__ uint64_t s_nb_sk, s_nb_key[W];  // spawned entry after the tile
     __shared__ long long s_nb_sum;
     __shared__ int s_pa_ok, s_nb_ok;
-    __shared__ uint16_t s_newq[TILE];  // accepted new determinants (slots) awaiting K_jj
-    __shared__ int s_nnew;
-    __shared__ long long s_tile, s_base;
+    __shared__ long long s_tile, s_base, s_abase;
     __shared__ long long s_red[8];
     const long long na = c->n_main, nb = c->n_uniq;
     const long long ntiles = (na + nb + TILE - 1) / TILE;
     const uint32_t t = c->t;
-    const uint32_t epoch = epoch_of(t, 11);
+    const uint32_t epoch = epoch_of(t, 11), epoch_att = epoch_of(t, 13);
     const bool ss = c->ss_active != 0;
     LocalAcc acc;
     acc.clear();
@@ -965,7 +1010,6 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
             s_meta[la + q] = (int32_t)w.u.flag[g];
         }
         if (threadIdx.x == 0) {
-            s_nnew = 0;
             s_pa_ok = i0 > 0;
             if (i0 > 0) {
                 s_pa_sk = w.cur.skey[i0 - 1];
@@ -1082,7 +1126,8 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                     const bool accept = (!rp.initiator || fl) && sum != 0;
                     if (accept) {
                         if (sum > 2147483647ll || sum < -2147483647ll) atomicOr(&c->err, ERR_OVERFLOW);
-                        s_newq[atomicAdd(&s_nnew, 1)] = (uint16_t)slot;
+                        // K_jj - H_00 is filled in by k_new_diag (off the merge's critical path)
+                        s_kd[slot] = __longlong_as_double(0x7FF8000000000000ll);
                         s_meta[slot] = -1;
                         s_keep[m] = 1;
                     } else {
@@ -1092,25 +1137,27 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                 }
             }
         }
-        __syncthreads();
-        // K_jj - H_00 of the accepted new determinants, one per thread
-        for (int q = threadIdx.x; q < s_nnew; q += MG_T) {
-            const int slot = s_newq[q];
-            uint64_t key[W];
-#pragma unroll
-            for (int x = 0; x < W; ++x) key[x] = s_key[x][slot];
-            const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
-            const DevSys &sy = w.sys[w.rep[rep].sys];
-            s_kd[slot] = diag_element<KIND, W>(sy, key) - sy.H00;
-        }
-        // ranks of the kept entries in merge order
+        // ranks of the kept entries in merge order, and their spawning attempts
+        // for the next iteration (the attempt prefix replaces a separate scan)
         int cnt = 0;
-        for (int st = 0; st < steps; ++st) cnt += s_keep[dl + st];
-        long long tot;
+        long long asum = 0;
+        for (int st = 0; st < steps; ++st) {
+            const int m = dl + st;
+            if (!s_keep[m]) continue;
+            ++cnt;
+            const int slot = s_src[m];
+            const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
+            asum += attempts_of(s_val[slot], w.rep[rep].bits, c);
+        }
+        long long tot, atot;
         const long long ex = block_excl_scan<long long>((long long)cnt, tot, s_red);
+        const long long aex = block_excl_scan<long long>(asum, atot, s_red);
         if (threadIdx.x < 64) {
             const long long lb_ = lookback(w.st_merge, tile, epoch, tot);
             if (threadIdx.x == 0) s_base = lb_;
+        } else if (threadIdx.x < 128) {
+            const long long lb_ = lookback(w.st_att, tile, epoch_att, atot);
+            if (threadIdx.x == 64) s_abase = lb_;
         }
         {
             int r = (int)ex;
@@ -1118,6 +1165,17 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                 if (s_keep[dl + st]) s_dst[dl + st] = (uint16_t)r++;
         }
         __syncthreads();
+        if (s_base + tot <= w.main_cap) {
+            long long ar = s_abase + aex;
+            for (int st = 0; st < steps; ++st) {
+                const int m = dl + st;
+                if (!s_keep[m]) continue;
+                const int slot = s_src[m];
+                const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
+                w.att_off[s_base + s_dst[m]] = ar;
+                ar += attempts_of(s_val[slot], w.rep[rep].bits, c);
+            }
+        }
         const long long obase = s_base;
         if (obase + tot > w.main_cap) {
             if (threadIdx.x == 0) atomicOr(&c->err, ERR_MAIN_CAP);
@@ -1144,14 +1202,6 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                 w.nxt.dslot[o] = ds;
                 if (ds >= 0) w.ds.pos[(size_t)rep * w.ds.n + ds] = (int32_t)o;
                 const long long ap = p < 0 ? -(long long)p : (long long)p;
-                long long nat;
-                if (rp.bits == 0) {
-                    nat = ap;
-                    if (ap >= (1ll << 28)) atomicOr(&c->err, ERR_ATTEMPTS);
-                } else {
-                    nat = (ap + (1ll << rp.bits) - 1) >> rp.bits;
-                }
-                w.nxt.natt[o] = (int32_t)nat;
                 acc_switch(acc, rep, w.acc);
                 any = true;
                 acc.v[F_NW] += ap;
@@ -1168,11 +1218,101 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                 }
             }
         }
-        if (tile == ntiles - 1 && threadIdx.x == 0) c->n_main_new = obase + tot;
+        if (tile == ntiles - 1 && threadIdx.x == 0) {
+            c->n_main_new = obase + tot;
+            if (obase + tot <= w.main_cap) w.att_off[obase + tot] = s_abase + atot;
+            c->n_att_new = s_abase + atot;
+        }
         __syncthreads();
     }
     flush_acc(acc, w.acc, any && acc.rep >= 0);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && ntiles == 0) c->n_main_new = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ntiles == 0) {
+        c->n_main_new = 0;
+        w.att_off[0] = 0;
+        c->n_att_new = 0;
+    }
+}
+
+// K_jj - H_00 of the determinants the merge has just created (marked NaN).
+// Each block scans a chunk of the new list, queues the marked entries in LDS
+// and evaluates them one per thread, so no lane idles on unmarked entries;
+// for a single replica the diagonal's tables are read from LDS.
+constexpr int ND_T = 256, ND_CHUNK = 4096;
+
+template <int KIND, int W>
+__global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
+{
+    const Ctl *c = w.ctl;
+    if (c->err) return;
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    __shared__ uint32_t s_q[ND_CHUNK];
+    __shared__ int s_n;
+    const long long n = c->n_main_new;
+    const DevSys &s0 = w.sys[w.rep[0].sys];
+    const bool local = w.R == 1 && w.lds_diag > 0 && (KIND == K_UEG || KIND == K_MOLECULAR);
+    UegTables lu = s0.u;
+    const double *lhd = s0.hd, *lJ = s0.Jt, *lK = s0.Kt;
+    if (local) {
+        double *t0 = (double *)dyn_lds;
+        const int m = s0.n_spatial;
+        if (KIND == K_UEG) {
+            double *t1 = t0 + m;
+            for (int i = threadIdx.x; i < m; i += ND_T) t0[i] = lu.eps[i];
+            for (int i = threadIdx.x; i < m * m; i += ND_T) t1[i] = lu.vx[i];
+            lu.eps = t0;
+            lu.vx = t1;
+        } else {
+            double *t1 = t0 + m, *t2 = t1 + m * m;
+            for (int i = threadIdx.x; i < m; i += ND_T) t0[i] = lhd[i];
+            for (int i = threadIdx.x; i < m * m; i += ND_T) {
+                t1[i] = lJ[i];
+                t2[i] = lK[i];
+            }
+            lhd = t0;
+            lJ = t1;
+            lK = t2;
+        }
+    }
+    for (long long base = (long long)blockIdx.x * ND_CHUNK; base < n; base += (long long)gridDim.x * ND_CHUNK) {
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+        for (int q = threadIdx.x; q < ND_CHUNK; q += ND_T) {
+            const long long i = base + q;
+            if (i < n) {
+                const double kd = w.nxt.kdiag[i];
+                if (kd != kd) s_q[atomicAdd(&s_n, 1)] = (uint32_t)q;
+            }
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < s_n; q += ND_T) {
+            const long long i = base + s_q[q];
+            uint64_t key[W];
+#pragma unroll
+            for (int x = 0; x < W; ++x) key[x] = w.nxt.key[(size_t)x * w.main_cap + i];
+            if (local) {
+                double e;
+                if constexpr (KIND == K_UEG) {
+                    e = diag_ueg<W>(lu, key);
+                } else {
+                    const int m = s0.n_spatial;
+                    e = 0.0;
+                    for_bits<W>(key, [&](int P) { e = e + lhd[P >> 1]; });
+                    for_pairs<W>(key, [&](int P, int Q) {
+                        const int p = P >> 1, q = Q >> 1;
+                        const double x = lJ[p * m + q];
+                        const double y = ((P & 1) == (Q & 1)) ? lK[p * m + q] : 0.0;
+                        e = e + (x - y);
+                    });
+                }
+                w.nxt.kdiag[i] = e - s0.H00;
+            } else {
+                const int rep = (int)skey_rep(w.nxt.skey[i], w.rb);
+                const DevSys &sy = w.sys[w.rep[rep].sys];
+                w.nxt.kdiag[i] = diag_element<KIND, W>(sy, key) - sy.H00;
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1224,6 +1364,7 @@ __global__ __launch_bounds__(256) void k_det_project_fp64(Work w)
 
 // explicit instantiations
 #define FQ_INST(KIND, W)                                   \
+    template __global__ void k_new_diag<KIND, W>(Work);     \
     template __global__ void k_spawn<KIND, W, false>(Work); \
     template __global__ void k_spawn<KIND, W, true>(Work);  \
     template __global__ void k_merge<KIND, W, false>(Work); \
@@ -1333,14 +1474,12 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     rec();
     k_begin<<<1, 256, 0, s>>>(w);
     rec();
-    k_scan_attempts<<<g.scan, SCAN_T, 0, s>>>(w);
-    rec();
     k_spawn_partition<<<g.part, 256, 0, s>>>(w);
     rec();
     if (w.R > 1)
         k_spawn<KIND, W, true><<<g.spawn, SP_T, 0, s>>>(w);
     else
-        k_spawn<KIND, W, false><<<g.spawn, SP_T, 0, s>>>(w);
+        k_spawn<KIND, W, false><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
     rec();
     k_sort_hist<<<g.hist, 256, 0, s>>>(w);
     rec();
@@ -1368,6 +1507,8 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     else
         k_merge<KIND, W, false><<<g.merge, MG_T, 0, s>>>(w);
     rec();
+    k_new_diag<KIND, W><<<g.det * 2, ND_T, w.lds_diag, s>>>(w);
+    rec();
     k_end<<<1, 64, 0, s>>>(w);
     rec();
 }
@@ -1392,7 +1533,12 @@ static void setup_kind(int what, const Work &w, DevSys *sys, int n_sys, MainList
                        double *K, hipStream_t s)
 {
     if (what == 0) k_h00<KIND, W><<<(n_sys + 63) / 64, 64, 0, s>>>(sys, n_sys);
-    if (what == 1 && n > 0) k_kdiag<KIND, W><<<(int)std::min<long long>((n + 255) / 256, 4096), 256, 0, s>>>(w, L, n);
+    if (what == 1) {
+        if (n > 0) k_kdiag<KIND, W><<<(int)std::min<long long>((n + 255) / 256, 4096), 256, 0, s>>>(w, L, n);
+        Work w2 = w;
+        w2.cur = L;
+        k_scan_attempts<<<256, SCAN_T, 0, s>>>(w2);
+    }
     if (what == 2) k_build_kdd<KIND, W><<<2048, 256, 0, s>>>(w, dk, K);
 }
 
@@ -1420,7 +1566,7 @@ int occupancy_blocks(int which)
     case 1: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false>, MG_T, 0); break;
     case 2: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce<2>, RD_T, 0); break;
     case 3: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan_attempts, SCAN_T, 0); break;
-    case 4: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false>, SP_T, 0); break;
+    case 4: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false>, SP_T, 16384); break;
     default: break;
     }
     return nb < 1 ? 1 : nb;

@@ -25,9 +25,9 @@ C_API = ["fq_workspace_bytes", "fq_init_system", "fq_step", "fq_estimators", "fq
          "fq_export_walkers", "fq_import_walkers", "fq_export_spawns", "fq_detspace", "fq_info",
          "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_last_error", "fq_destroy"]
 
-KERNEL_SLOTS = ["begin", "scan_attempts", "spawn_partition", "spawn", "sort_hist"] + \
+KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "sort_hist"] + \
     [f"sort_pass{p}" for p in range(8)] + ["reduce", "fixup", "reduce2", "det_gather", "det_project",
-                                            "merge_partition", "merge", "end"]
+                                            "merge_partition", "merge", "new_diag", "end"]
 
 
 class FqError(RuntimeError):
