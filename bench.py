@@ -44,6 +44,25 @@ def algorithmic_bytes(hist_prev, hist, W):
     return out
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if the
+    kernel sources are the ones it was measured on (else None)."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_ueg14.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1811_11679_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(f, "rb").read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec["kernels"].get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
 def cpu_baseline(budget_s=15.0, max_iter=400):
     """The oracle on the same workload from its initial state, single thread."""
     from oracle import oracle as O
@@ -78,6 +97,8 @@ def main():
     ap.add_argument("--main-capacity", type=int, default=1 << 28)
     ap.add_argument("--spawn-capacity", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of 1 GiB (4 times) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded path is a design, "
@@ -151,7 +172,7 @@ def main():
                    "timed_iterations": f"{e_start['iteration'] + 1}..{hist[-1]['iteration']}",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": best, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(best),
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch},
         "annihilation_gbps_algorithmic": ann_bytes / (ann_ms * 1e-3) / 1e9 if ann_ms > 0 else None,
         "stage_ms_per_iteration": {k: v / max(niter, 1) for k, v in stages.items()},
@@ -165,6 +186,15 @@ def main():
         "warmup_s": warm_s,
     }
     ctx.close()
+    if args.calibrate_copy:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE per
+        # dispatch scale the counters of the FCIQMC kernels to bytes
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 1 << 30
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
