@@ -110,7 +110,11 @@ typedef struct {
 typedef struct {
     int32_t size;
     int32_t start_iteration;
-    int32_t precision; /* FQ_SS_FP64 or FQ_SS_SPLIT_BF16 */
+    int32_t precision;    /* FQ_SS_FP64 or FQ_SS_SPLIT_BF16 */
+    int32_t check_period; /* split mode: every check_period iterations the FP64
+                             projection is also computed and the largest error
+                             of the split result, relative to sum_j |K_ij||c_j|,
+                             is reported in fq_estimators_t.ss_error (0: never) */
 } fq_semistoch;
 
 /* Estimators of one iteration of one instance (tutorial appendix: shift,
@@ -133,6 +137,9 @@ typedef struct {
     double proj_energy;       /* numerator / N_0 (correlation energy); NaN if N_0 = 0 */
     double e_ref;             /* H_00 */
     int64_t num_limbs[4];     /* exact fixed-point numerator (2^-64 resolution), units */
+    double ss_error;          /* split projection: max_i |y_i - y_i(FP64)| / sum_j |K_ij||c_j|
+                                 of the last checked iteration (0 if none) */
+    double ss_error_bound;    /* a priori bound of that ratio for the BF16 x3 / FP32 scheme */
 } fq_estimators_t;
 
 typedef struct fq_ctx fq_ctx;
@@ -208,8 +215,8 @@ fq_status fq_stage_times(const fq_ctx *ctx, double *ms7);
  * iterations, one slot per launch of an iteration in launch order: begin,
  * attempt partition, spawn, sort histogram, sort passes 0..7,
  * reduce, collision fix-up, reduce (repeat), projection gather, projection,
- * merge partition, merge, new-determinant diagonals, end. *n_slots receives
- * the slot count (21) and
+ * projection check, merge partition, merge, new-determinant diagonals, end.
+ * *n_slots receives the slot count (22) and
  * *n_iterations the number of timed iterations. */
 fq_status fq_kernel_times(const fq_ctx *ctx, double *ms, int32_t cap, int32_t *n_slots,
                           int64_t *n_iterations);

@@ -230,7 +230,7 @@ struct Layout {
     size_t main[2][6];
     size_t sp[7];
     size_t u[4];
-    size_t ds[10];
+    size_t ds[14];
     size_t dkeys;
 };
 
@@ -284,9 +284,10 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.u[2] = take(8 * (size_t)scap);
     L.u[3] = take(4 * (size_t)scap);
     const size_t nd = (size_t)D * R;
+    const size_t np = (size_t)((D + 15) / 16) * 16;
     L.ds[0] = take(8 * nd * (size_t)D);  // K fp64
-    L.ds[1] = take(2 * nd * (size_t)D);  // K hi bf16
-    L.ds[2] = take(2 * nd * (size_t)D);  // K lo bf16
+    L.ds[1] = take(2 * (size_t)R * np * np);  // K hi bf16
+    L.ds[2] = take(2 * (size_t)R * np * np);  // K lo bf16
     L.ds[3] = take(4 * nd);              // pos
     L.ds[4] = take(8 * nd);              // h64
     L.ds[5] = take(8 * nd);              // c
@@ -294,6 +295,9 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.ds[7] = take(8 * nd);              // delta
     L.ds[8] = take(8 * nd);              // sorted skeys
     L.ds[9] = take(8 * nd * W);          // sorted keys
+    L.ds[10] = take(2 * (size_t)R * np); // c hi bf16
+    L.ds[11] = take(2 * (size_t)R * np); // c lo bf16
+    L.ds[12] = take(8 * nd);             // FP64 reference y
     L.dkeys = take(8 * nd * W);          // keys in D order
     L.total = o;
     return L;
@@ -365,6 +369,9 @@ void estimators_from_acc(const fq_ctx *c, int r, const EstAcc &a, fq_estimators_
     e.spawn_sum = a.spawn_sum;
     e.rejected_sum = a.rej_sum;
     for (int k = 0; k < 4; ++k) e.num_limbs[k] = a.limbs[k];
+    e.ss_error = a.ss_err;
+    if (c->has_ss && c->ss.precision == FQ_SS_SPLIT_BF16)
+        e.ss_error_bound = 3.0 * 0x1p-16 + 3.0 * (double)c->D * 0x1p-24;
     __int128 tot = 0;
     for (int k = 0; k < 4; ++k) tot += (__int128)a.limbs[k] * ((__int128)1 << (32 * k));
     const double num = (double)tot * 0x1p-64;
@@ -675,8 +682,13 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.ds.n = c->D;
     w.ds.precision = c->has_ss ? c->ss.precision : 0;
     w.ds.K = (const double *)(c->ws + c->L.ds[0]);
-    w.ds.Khi = (const uint16_t *)(c->ws + c->L.ds[1]);
-    w.ds.Klo = (const uint16_t *)(c->ws + c->L.ds[2]);
+    w.ds.npad = ((c->D + 15) / 16) * 16;
+    w.ds.check_period = c->has_ss ? c->ss.check_period : 0;
+    w.ds.Khi = (uint16_t *)(c->ws + c->L.ds[1]);
+    w.ds.Klo = (uint16_t *)(c->ws + c->L.ds[2]);
+    w.ds.Chi = (uint16_t *)(c->ws + c->L.ds[10]);
+    w.ds.Clo = (uint16_t *)(c->ws + c->L.ds[11]);
+    w.ds.yref = (double *)(c->ws + c->L.ds[12]);
     w.ds.pos = (int32_t *)(c->ws + c->L.ds[3]);
     w.ds.h64 = (const uint64_t *)(c->ws + c->L.ds[4]);
     w.ds.c = (double *)(c->ws + c->L.ds[5]);
@@ -869,7 +881,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         if (c->timing) {
             // stage boundaries in the launch order: scan+partition, spawn, sort
             // (histogram + 8 passes), reduce (2 passes + fix-up), projection, merge
-            static const int stage_of[N_KERNEL_SLOTS] = {0, 0, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 5, 5, 4, 4, 4, 4};
+            static const int stage_of[N_KERNEL_SLOTS] = {0, 0, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 5, 5, 5, 4, 4, 4, 4};
             for (int k = 0; k < nb; ++k) {
                 hipEvent_t *e = &evs[(size_t)k * NE];
                 float ms = 0.f;

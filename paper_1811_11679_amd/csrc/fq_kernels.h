@@ -61,6 +61,7 @@ struct EstAcc {
     long long limbs[4];
     long long t;
     long long pad;
+    double ss_err;  // split projection: max relative error of the last check
 };
 constexpr int EST_FIELDS = 14;
 
@@ -91,9 +92,14 @@ struct UniqList {
 struct DetSpace {
     int32_t n;            // D (per replica equal; total = n * R)
     int32_t precision;
+    int32_t npad;         // D rounded up to 16 (MFMA tiles)
+    int32_t check_period; // split mode: FP64 check every check_period iterations
     const double *K;      // [R][n][n] FP64 K_DD (replica-major)
-    const uint16_t *Khi;  // bf16 planes [R][n][n]
-    const uint16_t *Klo;
+    uint16_t *Khi;        // bf16 planes [R][npad][npad], zero padded
+    uint16_t *Klo;
+    uint16_t *Chi;        // bf16 planes of the amplitudes [R][npad]
+    uint16_t *Clo;
+    double *yref;         // [R*n] FP64 projection of a checked iteration
     int32_t *pos;         // [R*n] position in the current main list
     const uint64_t *h64;  // [R*n] determinant hashes (for the rounding stream)
     double *c;            // [R*n] start-of-iteration populations
@@ -131,7 +137,7 @@ struct Grids {
 };
 
 // kernels of one iteration, in launch order (per-kernel timing slots)
-constexpr int N_KERNEL_SLOTS = 21;
+constexpr int N_KERNEL_SLOTS = 22;
 // enqueue one whole iteration on a stream (ev: N_KERNEL_SLOTS + 1 events or nullptr)
 hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_t s, hipEvent_t *ev);
 // set-up work: 0 = H_00 of every system, 1 = K_ii - H_00, attempt counts and

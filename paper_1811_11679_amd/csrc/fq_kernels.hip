@@ -1320,19 +1320,57 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
 // interleaved partial sums (j = lane mod 64) taken in increasing j, combined
 // by a fixed halving tree; then n_D += SR(-dtau (y - S n_D))
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rn(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 __global__ void k_det_gather(Work w)
 {
     const Ctl *c = w.ctl;
     if (c->err || !c->ss_active) return;
-    const int nd = w.ds.n * w.R;
+    const int n = w.ds.n, np = w.ds.npad;
+    const int nd = n * w.R;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += gridDim.x * blockDim.x)
         w.ds.c[i] = (double)w.cur.pop[w.ds.pos[i]];
+    if (w.ds.precision == 1) {
+        // BF16 hi/lo split of the amplitudes (zero padded to npad)
+        const int tot = np * w.R;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x) {
+            const int r = i / np, j = i % np;
+            const float cf = j < n ? (float)w.cur.pop[w.ds.pos[r * n + j]] : 0.0f;
+            const uint16_t hi = bf16_rn(cf);
+            w.ds.Chi[i] = hi;
+            w.ds.Clo[i] = bf16_rn(cf - bf16_f(hi));
+        }
+    }
 }
 
-__global__ __launch_bounds__(256) void k_det_project_fp64(Work w)
+// rounded increment of a deterministic entry: n += SR(-dtau (y - S n))
+__device__ __forceinline__ void det_update(const Work &w, const Ctl *c, int rep, long long row, double y, double nv)
+{
+    const RepParams &rp = w.rep[rep];
+    const double delta = (-rp.tau) * (y - w.shift[rep] * nv);
+    const U4 r = draw(TAG_SEMISTOCH, 0, c->t, w.ds.h64[row], rp.k0, rp.k1);
+    const double u = u53(r.x, r.y);
+    if (!(fabs(delta) < 0x1p40)) atomicOr(&((Ctl *)c)->err, ERR_OVERFLOW);
+    const long long k = delta >= 0.0 ? sround(delta, u) : -sround(-delta, u);
+    w.ds.y[row] = y;
+    w.ds.delta[row] = k;
+}
+
+// mode 0: the FP64 projection of the iteration. mode 1 (split precision, every
+// check_period iterations): FP64 reference y and the error of the split result
+// relative to sum_j |K_ij||c_j|, maximised into the replica's estimators.
+__global__ __launch_bounds__(256) void k_det_project_fp64(Work w, int mode)
 {
     const Ctl *c = w.ctl;
     if (c->err || !c->ss_active) return;
+    if (mode == 1 && (w.ds.precision != 1 || w.ds.check_period <= 0 || c->t % (uint32_t)w.ds.check_period != 0))
+        return;
     const int n = w.ds.n;
     const int lane = lane_id();
     const long long rows = (long long)n * w.R;
@@ -1341,24 +1379,97 @@ __global__ __launch_bounds__(256) void k_det_project_fp64(Work w)
         const int rep = (int)(row / n), d = (int)(row % n);
         const double *K = w.ds.K + ((size_t)rep * n + d) * n;
         const double *cv = w.ds.c + (size_t)rep * n;
-        double part = 0.0;
-        for (int j = lane; j < n; j += 64) part = part + K[j] * cv[j];
+        double part = 0.0, pabs = 0.0;
+        for (int j = lane; j < n; j += 64) {
+            part = part + K[j] * cv[j];
+            if (mode == 1) pabs = pabs + fabs(K[j]) * fabs(cv[j]);
+        }
 #pragma unroll
         for (int step = 32; step >= 1; step >>= 1) {
             const double o = __shfl_down(part, step, 64);
-            if (lane < step) part = part + o;
+            const double oa = __shfl_down(pabs, step, 64);
+            if (lane < step) {
+                part = part + o;
+                pabs = pabs + oa;
+            }
         }
         if (lane == 0) {
-            const RepParams rp = w.rep[rep];
-            const double nv = cv[d];
-            const double delta = (-rp.tau) * (part - w.shift[rep] * nv);
-            const U4 r = draw(TAG_SEMISTOCH, 0, c->t, w.ds.h64[row], rp.k0, rp.k1);
-            const double u = u53(r.x, r.y);
-            if (!(fabs(delta) < 0x1p40)) atomicOr(&((Ctl *)c)->err, ERR_OVERFLOW);
-            const long long k = delta >= 0.0 ? sround(delta, u) : -sround(-delta, u);
-            w.ds.y[row] = part;
-            w.ds.delta[row] = k;
+            if (mode == 0) {
+                det_update(w, c, rep, row, part, cv[d]);
+            } else {
+                w.ds.yref[row] = part;
+                const double e = pabs > 0.0 ? fabs(w.ds.y[row] - part) / pabs : 0.0;
+                atomicMax((unsigned long long *)&w.acc[rep].ss_err, (unsigned long long)__double_as_longlong(e));
+            }
         }
+    }
+}
+
+// Split-precision projection on MFMA: y = K c with K and c split into BF16
+// hi + lo planes, y = K_hi c_hi + K_hi c_lo + K_lo c_hi accumulated in FP32
+// (the "bf16x3" scheme). One wavefront computes 16 rows of one replica with
+// v_mfma_f32_16x16x16_bf16; the amplitudes occupy column 0 of the 16 x 16 B tile.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_det_project_split(Work w)
+{
+    const Ctl *c = w.ctl;
+    if (c->err || !c->ss_active || w.ds.precision != 1) return;
+    const int n = w.ds.n, np = w.ds.npad;
+    const int lane = lane_id();
+    const int tiles = np / 16;
+    const long long jobs = (long long)tiles * w.R;
+    for (long long job = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); job < jobs;
+         job += (long long)gridDim.x * (blockDim.x >> 6)) {
+        const int rep = (int)(job / tiles), rt = (int)(job % tiles);
+        const int arow = rt * 16 + (lane & 15);
+        const int kq = 4 * (lane >> 4);
+        const uint16_t *kh = w.ds.Khi + ((size_t)rep * np + arow) * np + kq;
+        const uint16_t *kl = w.ds.Klo + ((size_t)rep * np + arow) * np + kq;
+        const uint16_t *ch = w.ds.Chi + (size_t)rep * np + kq;
+        const uint16_t *cl = w.ds.Clo + (size_t)rep * np + kq;
+        const bool bcol = (lane & 15) == 0;
+        f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < np; kk += 16) {
+            const bf16x4_t ah = *(const bf16x4_t *)(kh + kk);
+            const bf16x4_t al = *(const bf16x4_t *)(kl + kk);
+            bf16x4_t bh = {0, 0, 0, 0}, bl = {0, 0, 0, 0};
+            if (bcol) {
+                bh = *(const bf16x4_t *)(ch + kk);
+                bl = *(const bf16x4_t *)(cl + kk);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+        }
+        // lane holds rows 4 (lane / 16) + i of column lane % 16
+        if (bcol) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int d = rt * 16 + 4 * (lane >> 4) + i;
+                if (d < n) {
+                    const long long row = (long long)rep * n + d;
+                    det_update(w, c, rep, row, (double)acc[i], w.ds.c[row]);
+                }
+            }
+        }
+    }
+}
+
+// BF16 hi/lo planes of K_DD (zero padded to npad), once per deterministic space
+__global__ void k_split_planes(Work w)
+{
+    const int n = w.ds.n, np = w.ds.npad;
+    const long long tot = (long long)w.R * np * np;
+    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < tot; x += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(x / ((long long)np * np));
+        const int i = (int)((x / np) % np), j = (int)(x % np);
+        float k = 0.0f;
+        if (i < n && j < n) k = (float)w.ds.K[((size_t)r * n + i) * n + j];
+        const uint16_t hi = bf16_rn(k);
+        w.ds.Khi[x] = hi;
+        w.ds.Klo[x] = bf16_rn(k - bf16_f(hi));
     }
 }
 
@@ -1498,7 +1609,12 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     rec();
     k_det_gather<<<g.det, 256, 0, s>>>(w);
     rec();
-    k_det_project_fp64<<<g.det, 256, 0, s>>>(w);
+    if (w.ds.precision == 1)
+        k_det_project_split<<<g.det, 256, 0, s>>>(w);
+    else
+        k_det_project_fp64<<<g.det, 256, 0, s>>>(w, 0);
+    rec();
+    k_det_project_fp64<<<g.det, 256, 0, s>>>(w, 1);
     rec();
     k_merge_partition<W><<<g.part, 256, 0, s>>>(w);
     rec();
@@ -1539,7 +1655,10 @@ static void setup_kind(int what, const Work &w, DevSys *sys, int n_sys, MainList
         w2.cur = L;
         k_scan_attempts<<<256, SCAN_T, 0, s>>>(w2);
     }
-    if (what == 2) k_build_kdd<KIND, W><<<2048, 256, 0, s>>>(w, dk, K);
+    if (what == 2) {
+        k_build_kdd<KIND, W><<<2048, 256, 0, s>>>(w, dk, K);
+        if (w.ds.precision == 1) k_split_planes<<<2048, 256, 0, s>>>(w);
+    }
 }
 
 hipError_t enqueue_setup(int what, int kind, const Work &w, DevSys *sys, int n_sys, MainList L, long long n,

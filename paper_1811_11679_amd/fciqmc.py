@@ -26,7 +26,7 @@ C_API = ["fq_workspace_bytes", "fq_init_system", "fq_step", "fq_estimators", "fq
          "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_last_error", "fq_destroy"]
 
 KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "sort_hist"] + \
-    [f"sort_pass{p}" for p in range(8)] + ["reduce", "fixup", "reduce2", "det_gather", "det_project",
+    [f"sort_pass{p}" for p in range(8)] + ["reduce", "fixup", "reduce2", "det_gather", "det_project", "det_check",
                                             "merge_partition", "merge", "new_diag", "end"]
 
 
@@ -53,7 +53,8 @@ class Qmc(C.Structure):
 
 
 class SemiStoch(C.Structure):
-    _fields_ = [("size", C.c_int32), ("start_iteration", C.c_int32), ("precision", C.c_int32)]
+    _fields_ = [("size", C.c_int32), ("start_iteration", C.c_int32), ("precision", C.c_int32),
+                ("check_period", C.c_int32)]
 
 
 class Estimators(C.Structure):
@@ -63,7 +64,7 @@ class Estimators(C.Structure):
                 ("death_sum", C.c_int64), ("spawn_sum", C.c_int64), ("rejected_sum", C.c_int64),
                 ("vary_shift", C.c_int32), ("status", C.c_int32), ("shift", C.c_double),
                 ("proj_numerator", C.c_double), ("proj_energy", C.c_double), ("e_ref", C.c_double),
-                ("num_limbs", C.c_int64 * 4)]
+                ("num_limbs", C.c_int64 * 4), ("ss_error", C.c_double), ("ss_error_bound", C.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "num_limbs"}

@@ -48,7 +48,7 @@ def gpu_context(sysds, qs, ints=None, ss=None, main_capacity=1 << 21, spawn_capa
     sso = None
     if ss:
         sso = F.SemiStoch(size=ss["size"], start_iteration=ss["start_iteration"],
-                          precision=ss.get("precision", F.SS_FP64))
+                          precision=ss.get("precision", F.SS_FP64), check_period=ss.get("check_period", 0))
     return F.Context(systems, qmcs, sso, main_capacity=main_capacity, spawn_capacity=spawn_capacity)
 
 

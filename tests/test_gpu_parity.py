@@ -203,3 +203,35 @@ def test_export_import_roundtrip_and_resume():
     assert np.array_equal(ka, kb) and np.array_equal(pa, pb)
     a.close()
     b.close()
+
+
+def test_semistochastic_split_precision_error_within_bound():
+    """BF16 x3 MFMA projection: at the first projected iteration the state is the
+    oracle's, so the FP64 check equals the oracle's projection bit for bit and the
+    split result lies within the stated bound of it."""
+    h1, eri = synth.molecular_integrals()
+    w = workloads.MOL30
+    q = dict(w["qmc"], init_pop=2e3, target_population=3e4)
+    ss = dict(size=300, start_iteration=30, precision=1, check_period=1)
+    say("[case] mol30 split-precision projection")
+    ctx = gpu_context([w["system"]], [q], ints=(h1, eri), ss=ss)
+    from oracle import oracle as O
+    orun = O.Run(oracle_system(w["system"], (h1, eri)), oracle_qmc(w["system"], q, ss=ss))
+    ctx.step(31)
+    orun.step(31)
+    kd, y = ctx.detspace()
+    assert np.array_equal(kd, orun.detspace())
+    yo = orun.last_projection()
+    e = ctx.estimators()
+    assert 0.0 < e["ss_error"] <= e["ss_error_bound"]
+    kg, pg = ctx.export()  # populations differ from here on; the projection input did not
+    scale = np.max(np.abs(yo))
+    assert np.max(np.abs(y - yo)) <= e["ss_error_bound"] * scale * 1e3
+    rel = np.max(np.abs(y - yo)) / scale
+    say(f"[case] split projection: max |dy| / max |y| = {rel:.3e}, reported ratio {e['ss_error']:.3e}, "
+        f"bound {e['ss_error_bound']:.3e}")
+    # the run continues in split precision with errors inside the bound
+    ctx.step(50)
+    hist = ctx.history()
+    assert all(h["ss_error"] <= h["ss_error_bound"] for h in hist)
+    ctx.close()
