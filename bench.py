@@ -89,6 +89,122 @@ def cpu_baseline(budget_s=15.0, max_iter=400):
                       f"({run.estimators()['n_occupied']} determinants at the end), single thread"}
 
 
+def batch_capacity(inst):
+    """Determinant and spawn capacities for a group of instances. Death and
+    cloning shrink populations continuously, so an instance can hold tens of
+    determinants per walker (up to about 30 measured at 123 plane waves): the
+    main list gets 40 entries per target walker, the spawn list 4 spawns."""
+    def cap(members, n_now=0):
+        tot = sum(inst[i][1]["target_population"] for i in members)
+        return int(max(40 * tot, 2 * n_now)), int(4 * tot)
+    return cap
+
+
+HIST_FIELDS = ("iteration", "n_walkers_units", "n_occupied", "ref_pop_units", "n_spawned", "n_spawn_events",
+               "death_sum", "spawn_sum", "rejected_sum", "n_rejected_units", "n_sign_flips", "num_limbs", "shift")
+
+
+def run_batch64(args):
+    """64 independent electron-gas instances batched (one context per key width,
+    graph replay, autotuned launch geometry) against the same 64 instances run
+    one after another by the plain path: same keys, same iterations, timed over
+    the same window. Batched instance i and plain run i are the same
+    computation, so their estimator histories over the window must agree
+    exactly; the count of instances that do is reported."""
+    import torch
+    from paper_1811_11679_amd import autotune
+    from paper_1811_11679_amd import batch as B
+    from paper_1811_11679_amd import fciqmc as F
+    from paper_1811_11679_amd import workloads
+
+    inst = workloads.batch64()
+    n = len(inst)
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
+    cap = batch_capacity(inst)
+    bt = B.Batch(inst, capacity=cap)
+    log(f"batch: {n} instances in {len(bt.contexts)} contexts "
+        f"(key words {[c.W for c in bt.contexts]}, instances {[len(g) for g in bt.groups]})")
+    t_w0 = time.perf_counter()
+
+    def warm_to(target):
+        done = int(bt.estimators(0)["iteration"])
+        while done < target:
+            k = min(250, target - done)
+            bt.step(k)
+            done += k
+            tot = sum(bt.estimators(i)["n_walkers_units"] for i in range(n)) / 256.0
+            log(f"batch warmup {done}: total N_w {tot:.4g}, {time.perf_counter() - t_w0:.1f} s")
+
+    # launch geometry is searched near the end of the equilibration, where the
+    # populations are close to their targets, one context at a time; it does
+    # not change the results
+    warm_to(int(args.warmup * 0.8))
+    tuned = [autotune.tune(c, iters=3, log=lambda m, k=k: log(f"context {k}: {m}"))
+             for k, c in enumerate(bt.contexts)]
+    warm_to(args.warmup)
+    t_start = int(bt.estimators(0)["iteration"])
+    e_start = [bt.estimators(i) for i in range(n)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(args.steps)
+    bt.synchronize()
+    dt_b = time.perf_counter() - t0
+    hist_b = [bt.history(i) for i in range(n)]
+    upd_b = sum((e_start[i]["n_walkers_units"] + sum(x["n_walkers_units"] for x in hist_b[i][:-1])) / 256.0
+                for i in range(n))
+    groups = [len(g) for g in bt.groups]
+    bt.close()
+    torch.cuda.empty_cache()
+    log(f"batched: iterations {t_start + 1}..{t_start + args.steps} in {dt_b:.2f} s, "
+        f"{upd_b / dt_b:.4g} walker updates/s")
+    # plain path, one instance after another from the same initial state with
+    # the same keys; only the same window of iterations is timed
+    upd_p, dt_p, same = 0.0, 0.0, 0
+    for i, (sysd, q) in enumerate(inst):
+        mc, sc = cap([i])
+        ctx = F.Context([F.make_system(F.UEG, **{k: v for k, v in sysd.items() if k != "kind"})],
+                        [F.make_qmc(excit_gen=F.UEG, **q)], main_capacity=mc, spawn_capacity=sc, graph=True)
+        ctx.step(t_start)
+        e0 = ctx.estimators()
+        ctx.stream.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(args.steps)
+        ctx.stream.synchronize()
+        dt = time.perf_counter() - t0
+        h = ctx.history()
+        ctx.close()
+        u = (e0["n_walkers_units"] + sum(x["n_walkers_units"] for x in h[:-1])) / 256.0
+        ok = len(h) == len(hist_b[i]) and all(a[f] == b[f] for a, b in zip(h, hist_b[i]) for f in HIST_FIELDS)
+        same += int(ok)
+        upd_p += u
+        dt_p += dt
+        log(f"plain instance {i}: {u / dt:.4g} walker updates/s over the window ({dt:.2f} s), "
+            f"{'identical to' if ok else 'DIFFERENT from'} the batched instance")
+    out = {
+        "metric": METRIC,
+        "value": upd_b / dt_b,
+        "unit": "walker updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt_b * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch64_ueg14_rs{0.5,1,2,4}_pw{19,27,57,123}_targets1e5-2e6",
+                   "instances": n, "contexts": len(groups), "instances_per_context": groups,
+                   "timed_iterations": f"{t_start + 1}..{t_start + args.steps}", "graph_replay": True,
+                   "autotuned_blocks": tuned, "parallelism": "single GPU"},
+        "plain_sequential": {"value": upd_p / dt_p, "unit": "walker updates/s", "seconds": dt_p,
+                             "instances_identical_to_batched": same},
+        "batched_over_plain": (upd_b / dt_b) / (upd_p / dt_p),
+        "walker_updates": upd_b,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +213,8 @@ def main():
     ap.add_argument("--main-capacity", type=int, default=1 << 28)
     ap.add_argument("--spawn-capacity", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64"],
+                    help="ueg14: the plain single-instance path; batch64: 64 batched instances vs plain runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (4 times) for counter calibration")
     args = ap.parse_args()
@@ -104,6 +222,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sharded path is a design, "
               "not part of this build", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        return run_batch64(args)
 
     import torch
     from paper_1811_11679_amd import fciqmc as F

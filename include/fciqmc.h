@@ -189,6 +189,15 @@ fq_status fq_import_walkers(fq_ctx *ctx, int32_t instance, const uint64_t *keys,
                             const int32_t *pops, int64_t n, double shift, int64_t iteration,
                             int32_t vary_shift, int64_t n_prev);
 
+/* Shift state of one instance after the last completed iteration: the shift
+ * S (Hartree, relative to H_00), the population (units) at the last shift
+ * update and whether S is being varied. With fq_export_walkers and
+ * fq_estimators this is everything fq_import_walkers needs to continue the run
+ * exactly (Section 4.1.2: S is updated every A iterations from the ratio of
+ * populations). Any output pointer may be NULL. */
+fq_status fq_shift_state(const fq_ctx *ctx, int32_t instance, double *shift, int64_t *n_prev,
+                         int32_t *vary_shift);
+
 /* Spawned walkers of the last iteration of one instance (unordered):
  * keys[i*W + w], amps[i] (units), init[i] (1 if the parent was an initiator). */
 fq_status fq_export_spawns(const fq_ctx *ctx, int32_t instance, uint64_t *keys, int32_t *amps,
@@ -220,6 +229,20 @@ fq_status fq_stage_times(const fq_ctx *ctx, double *ms7);
  * *n_iterations the number of timed iterations. */
 fq_status fq_kernel_times(const fq_ctx *ctx, double *ms, int32_t cap, int32_t *n_slots,
                           int64_t *n_iterations);
+
+/* Graph replay: with on = 1, every block of shift_period iterations between
+ * two host shift updates is captured once into a HIP graph (per main-list
+ * parity) and replayed with one launch. The stream given to fq_init_system
+ * must not be the legacy default stream. Timing (fq_set_timing) launches
+ * kernels one by one and takes precedence. */
+fq_status fq_set_graph(fq_ctx *ctx, int32_t on);
+
+/* Launch geometry of the persistent kernels, in blocks: [0] spawn, [1] merge,
+ * [2] radix-sort pass, [3] segmented reduction, [4] new-determinant
+ * diagonals. A value <= 0 keeps the current one. Results do not depend on
+ * the geometry (work is taken by ticket or grid stride); only speed does. */
+fq_status fq_set_launch(fq_ctx *ctx, const int32_t *blocks, int32_t n);
+fq_status fq_get_launch(const fq_ctx *ctx, int32_t *blocks, int32_t n);
 
 const char *fq_last_error(const fq_ctx *ctx);
 void fq_destroy(fq_ctx *ctx);

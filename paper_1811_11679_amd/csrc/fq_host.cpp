@@ -227,6 +227,7 @@ size_t table_bytes(const HostSys &s)
 struct Layout {
     size_t total = 0;
     size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge, st_spawn, st_att;
+    size_t part_red, part_mrg;
     size_t main[2][6];
     size_t sp[7];
     size_t u[4];
@@ -264,6 +265,8 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 512));
     L.st_spawn = take(8 * (size_t)(span_capacity(mcap, scap) + 2));
     L.st_att = take(8 * (size_t)tiles_of(mcap + scap, 512));
+    L.part_red = take(8 * (size_t)PART_MAX_BLOCKS * acc_rows(R) * EST_FIELDS);
+    L.part_mrg = take(8 * (size_t)PART_MAX_BLOCKS * acc_rows(R) * EST_FIELDS);
     for (int b = 0; b < 2; ++b) {
         L.main[b][0] = take(8 * (size_t)mcap);
         L.main[b][1] = take(8 * (size_t)mcap * W);
@@ -334,6 +337,10 @@ struct fq_ctx {
     double h00[64] = {0};
     std::vector<double> h00v;
     bool timing = false;
+    bool graph = false;
+    hipGraph_t graphs[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_len[2] = {0, 0};
     double stage_ms[7] = {0};
     double kernel_ms[N_KERNEL_SLOTS] = {0};
     int64_t timed_iterations = 0;
@@ -341,6 +348,26 @@ struct fq_ctx {
 };
 
 namespace {
+
+// Every copy and fill of a context is ordered on the context's stream (the
+// caller's stream need not synchronise with the legacy default stream); the
+// host waits for the stream before it reads a result or lets a host buffer go.
+hipError_t h2d(hipStream_t s, void *dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+}
+
+hipError_t d2h(hipStream_t s, void *dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+}
+
+hipError_t fill0(hipStream_t s, void *dst, size_t bytes)
+{
+    return hipMemsetAsync(dst, 0, bytes, s);
+}
 
 fq_status fail(fq_ctx *c, fq_status s, const std::string &m)
 {
@@ -395,6 +422,17 @@ void set_main_views(fq_ctx *c)
     c->w.nxt = c->buf[c->cur ^ 1];
 }
 
+void drop_graphs(fq_ctx *c)
+{
+    for (int b = 0; b < 2; ++b) {
+        if (c->gexec[b]) (void)hipGraphExecDestroy(c->gexec[b]);
+        if (c->graphs[b]) (void)hipGraphDestroy(c->graphs[b]);
+        c->gexec[b] = nullptr;
+        c->graphs[b] = nullptr;
+        c->graph_len[b] = 0;
+    }
+}
+
 struct HostEntry {
     uint64_t skey;
     uint64_t key[MAXW];
@@ -412,11 +450,11 @@ fq_status download_main(fq_ctx *c, std::vector<HostEntry> &out, int64_t &n)
     std::vector<uint64_t> sk(n), kk((size_t)n * c->W);
     std::vector<int32_t> pp(n), ds(n);
     if (n) {
-        HIPCHK(c, hipMemcpy(sk.data(), m.skey, 8 * n, hipMemcpyDeviceToHost));
+        HIPCHK(c, d2h(c->stream, sk.data(), m.skey, 8 * n));
         for (int q = 0; q < c->W; ++q)
-            HIPCHK(c, hipMemcpy(kk.data() + (size_t)q * n, m.key + (size_t)q * c->main_cap, 8 * n, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(pp.data(), m.pop, 4 * n, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(ds.data(), m.dslot, 4 * n, hipMemcpyDeviceToHost));
+            HIPCHK(c, d2h(c->stream, kk.data() + (size_t)q * n, m.key + (size_t)q * c->main_cap, 8 * n));
+        HIPCHK(c, d2h(c->stream, pp.data(), m.pop, 4 * n));
+        HIPCHK(c, d2h(c->stream, ds.data(), m.dslot, 4 * n));
     }
     out.resize(n);
     for (int64_t i = 0; i < n; ++i) {
@@ -434,6 +472,7 @@ fq_status upload_main(fq_ctx *c, const std::vector<HostEntry> &e)
 {
     const int64_t n = (int64_t)e.size();
     if (n > c->main_cap) return fail(c, FQ_ECAPACITY, "main list capacity exceeded");
+    drop_graphs(c);  // captured blocks are rebuilt from the current state on the next step
     const MainList &m = c->buf[c->cur];
     std::vector<uint64_t> sk(n), kk((size_t)n * c->W);
     std::vector<int32_t> pp(n), ds(n);
@@ -444,28 +483,28 @@ fq_status upload_main(fq_ctx *c, const std::vector<HostEntry> &e)
         ds[i] = e[i].dslot;
     }
     if (n) {
-        HIPCHK(c, hipMemcpy(m.skey, sk.data(), 8 * n, hipMemcpyHostToDevice));
+        HIPCHK(c, h2d(c->stream, m.skey, sk.data(), 8 * n));
         for (int q = 0; q < c->W; ++q)
-            HIPCHK(c, hipMemcpy(m.key + (size_t)q * c->main_cap, kk.data() + (size_t)q * n, 8 * n, hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(m.pop, pp.data(), 4 * n, hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(m.dslot, ds.data(), 4 * n, hipMemcpyHostToDevice));
+            HIPCHK(c, h2d(c->stream, m.key + (size_t)q * c->main_cap, kk.data() + (size_t)q * n, 8 * n));
+        HIPCHK(c, h2d(c->stream, m.pop, pp.data(), 4 * n));
+        HIPCHK(c, h2d(c->stream, m.dslot, ds.data(), 4 * n));
     }
     set_main_views(c);
     {
         Ctl ctl0;
-        HIPCHK(c, hipMemcpy(&ctl0, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+        HIPCHK(c, d2h(c->stream, &ctl0, c->w.ctl, sizeof(Ctl)));
         ctl0.n_main = n;
         ctl0.n_main_new = n;
         std::memset(ctl0.tickets, 0, sizeof(ctl0.tickets));
-        HIPCHK(c, hipMemcpy(c->w.ctl, &ctl0, sizeof(Ctl), hipMemcpyHostToDevice));
+        HIPCHK(c, h2d(c->stream, c->w.ctl, &ctl0, sizeof(Ctl)));
     }
-    HIPCHK(c, hipMemset(c->ws + c->L.st_scan, 0, c->L.st_sort - c->L.st_scan));
+    HIPCHK(c, fill0(c->stream, c->ws + c->L.st_scan, c->L.st_sort - c->L.st_scan));
     HIPCHK(c, enqueue_setup(1, c->kind, c->w, nullptr, 0, m, n, nullptr, nullptr, c->stream));
     Ctl ctl;
-    HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    HIPCHK(c, d2h(c->stream, &ctl, c->w.ctl, sizeof(Ctl)));
     ctl.n_main = n;
     ctl.n_main_new = n;
-    HIPCHK(c, hipMemcpy(c->w.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice));
+    HIPCHK(c, h2d(c->stream, c->w.ctl, &ctl, sizeof(Ctl)));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return FQ_OK;
 }
@@ -564,20 +603,20 @@ fq_status select_detspace(fq_ctx *c)
     std::vector<int32_t> ds(n);
     for (int64_t i = 0; i < n; ++i) ds[i] = e[i].dslot;
     const MainList &m = c->buf[c->cur];
-    if (n) HIPCHK(c, hipMemcpy(m.dslot, ds.data(), 4 * n, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[3], pos.data(), 4 * nd, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[4], h64.data(), 8 * nd, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[8], ssk.data(), 8 * nd, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[9], skk.data(), 8 * nd * W, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->ws + c->L.dkeys, dk.data(), 8 * nd * W, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemset(c->ws + c->L.ds[6], 0, 8 * nd));
+    if (n) HIPCHK(c, h2d(c->stream, m.dslot, ds.data(), 4 * n));
+    HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[3], pos.data(), 4 * nd));
+    HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[4], h64.data(), 8 * nd));
+    HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[8], ssk.data(), 8 * nd));
+    HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[9], skk.data(), 8 * nd * W));
+    HIPCHK(c, h2d(c->stream, c->ws + c->L.dkeys, dk.data(), 8 * nd * W));
+    HIPCHK(c, fill0(c->stream, c->ws + c->L.ds[6], 8 * nd));
     HIPCHK(c, enqueue_setup(2, c->kind, c->w, nullptr, 0, m, 0, (const uint64_t *)(c->ws + c->L.dkeys),
                             (double *)(c->ws + c->L.ds[0]), c->stream));
     Ctl ctl;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    HIPCHK(c, d2h(c->stream, &ctl, c->w.ctl, sizeof(Ctl)));
     ctl.ss_active = 1;
-    HIPCHK(c, hipMemcpy(c->w.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice));
+    HIPCHK(c, h2d(c->stream, c->w.ctl, &ctl, sizeof(Ctl)));
     c->ss_active = true;
     return FQ_OK;
 }
@@ -670,6 +709,8 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.st_merge = (unsigned long long *)(c->ws + c->L.st_merge);
     w.st_spawn = (unsigned long long *)(c->ws + c->L.st_spawn);
     w.st_att = (unsigned long long *)(c->ws + c->L.st_att);
+    w.part_red = (long long *)(c->ws + c->L.part_red);
+    w.part_mrg = (long long *)(c->ws + c->L.part_mrg);
     w.sp.skey = (uint64_t *)(c->ws + c->L.sp[0]);
     w.sp.rec = (uint64_t *)(c->ws + c->L.sp[1]);
     w.sp.skey2 = (uint64_t *)(c->ws + c->L.sp[4]);
@@ -710,10 +751,11 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     std::vector<DevSys> ds(c->R);
     std::vector<RepParams> rp(c->R);
     size_t toff = c->L.tables;
+    bool put_failed = false;
     auto put = [&](const void *src, size_t bytes) -> const void * {
         if (!bytes) return nullptr;
         char *dst = c->ws + toff;
-        (void)hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+        if (h2d(c->stream, dst, src, bytes) != hipSuccess) put_failed = true;
         toff += al(bytes);
         return dst;
     };
@@ -765,17 +807,17 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         p.initiator = q.initiator ? 1 : 0;
         p.sys = r;
     }
-    hipError_t he = hipMemcpy((void *)w.sys, ds.data(), sizeof(DevSys) * c->R, hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMemcpy((void *)w.rep, rp.data(), sizeof(RepParams) * c->R, hipMemcpyHostToDevice);
-    if (he == hipSuccess) he = hipMemset(w.ctl, 0, sizeof(Ctl));
-    if (he == hipSuccess) he = hipMemset(c->ws + c->L.st_scan, 0, c->L.main[0][0] - c->L.st_scan);
+    hipError_t he = put_failed ? hipErrorInvalidValue : h2d(c->stream, (void *)w.sys, ds.data(), sizeof(DevSys) * c->R);
+    if (he == hipSuccess) he = h2d(c->stream, (void *)w.rep, rp.data(), sizeof(RepParams) * c->R);
+    if (he == hipSuccess) he = fill0(c->stream, w.ctl, sizeof(Ctl));
+    if (he == hipSuccess) he = fill0(c->stream, c->ws + c->L.st_scan, c->L.main[0][0] - c->L.st_scan);
     if (he == hipSuccess) he = enqueue_setup(0, c->kind, w, (DevSys *)w.sys, c->R, c->buf[0], 0, nullptr, nullptr, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) { delete c; return FQ_EHIP; }
     c->h00v.resize(c->R);
     for (int r = 0; r < c->R; ++r) {
         DevSys d;
-        hipMemcpy(&d, w.sys + r, sizeof(DevSys), hipMemcpyDeviceToHost);
+        if (d2h(c->stream, &d, w.sys + r, sizeof(DevSys)) != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
         c->h00v[r] = d.H00;
     }
     he = hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), 0);
@@ -789,8 +831,8 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     c->grids.scan = ncu * occupancy_blocks(3);
     c->grids.sort = ncu * occupancy_blocks(0);
-    c->grids.merge = ncu * occupancy_blocks(1);
-    c->grids.reduce = ncu * occupancy_blocks(2);
+    c->grids.merge = std::min(ncu * occupancy_blocks(1), PART_MAX_BLOCKS);
+    c->grids.reduce = std::min(ncu * occupancy_blocks(2), PART_MAX_BLOCKS);
     c->grids.part = ncu * 4;
     c->grids.spawn = ncu * occupancy_blocks(4);
     // diagonal tables staged in LDS by the single-replica new-determinant kernel
@@ -812,6 +854,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     c->grids.hist = ncu * 4;
     c->grids.fixup = ncu * 2;
     c->grids.det = ncu * 4;
+    c->grids.newdiag = ncu * 8;
 
     c->shift.assign(c->R, 0.0);
     c->vary.assign(c->R, 0);
@@ -837,7 +880,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         if (e.pop != 0) nz.push_back(e);
     std::sort(nz.begin(), nz.end(), [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, c->W); });
     for (int r = 0; r < c->R; ++r) c->h_shift[r] = c->shift[r];
-    if (hipMemcpy(w.shift, c->h_shift, 8 * c->R, hipMemcpyHostToDevice) != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
+    if (h2d(c->stream, w.shift, c->h_shift, 8 * c->R) != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
     if (upload_main(c, nz) != FQ_OK || host_estimators(c) != FQ_OK) { fq_destroy(c); return FQ_EHIP; }
     *out = c;
     return FQ_OK;
@@ -869,11 +912,43 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             evs.resize((size_t)nb * NE);
             for (auto &e : evs) (void)hipEventCreate(&e);
         }
-        for (int k = 0; k < nb; ++k) {
-            hipError_t he = enqueue_iteration(c->w, c->kind, c->grids, c->stream, c->timing ? &evs[(size_t)k * NE] : nullptr);
-            if (he != hipSuccess) return fail(c, FQ_EHIP, std::string("launch: ") + hipGetErrorString(he));
-            c->cur ^= 1;
+        const bool use_graph = c->graph && !c->timing && nb == A;
+        if (use_graph) {
+            // one captured block of A iterations per main-list parity, replayed
+            const int b = c->cur;
+            if (!c->gexec[b] || c->graph_len[b] != nb) {
+                if (c->gexec[b]) (void)hipGraphExecDestroy(c->gexec[b]);
+                if (c->graphs[b]) (void)hipGraphDestroy(c->graphs[b]);
+                c->gexec[b] = nullptr;
+                c->graphs[b] = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < nb; ++k) {
+                    hipError_t he = enqueue_iteration(c->w, c->kind, c->grids, c->stream, nullptr);
+                    if (he != hipSuccess) {
+                        hipGraph_t junk;
+                        (void)hipStreamEndCapture(c->stream, &junk);
+                        if (junk) (void)hipGraphDestroy(junk);
+                        return fail(c, FQ_EHIP, std::string("capture: ") + hipGetErrorString(he));
+                    }
+                    c->cur ^= 1;
+                    set_main_views(c);
+                }
+                HIPCHK(c, hipStreamEndCapture(c->stream, &c->graphs[b]));
+                HIPCHK(c, hipGraphInstantiate(&c->gexec[b], c->graphs[b], nullptr, nullptr, 0));
+                c->graph_len[b] = nb;
+                c->cur = b;
+                set_main_views(c);
+            }
+            HIPCHK(c, hipGraphLaunch(c->gexec[b], c->stream));
+            c->cur = b ^ (nb & 1);
             set_main_views(c);
+        } else {
+            for (int k = 0; k < nb; ++k) {
+                hipError_t he = enqueue_iteration(c->w, c->kind, c->grids, c->stream, c->timing ? &evs[(size_t)k * NE] : nullptr);
+                if (he != hipSuccess) return fail(c, FQ_EHIP, std::string("launch: ") + hipGetErrorString(he));
+                c->cur ^= 1;
+                set_main_views(c);
+            }
         }
         HIPCHK(c, hipMemcpyAsync(c->h_ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->h_hist, c->w.hist, sizeof(EstAcc) * c->R * HIST_LEN, hipMemcpyDeviceToHost, c->stream));
@@ -898,6 +973,9 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             evs.clear();
         }
         const Ctl &ctl = *c->h_ctl;
+        if (!ctl.err && (int64_t)ctl.t != stop)
+            return fail(c, FQ_ESTATE, "device iteration counter " + std::to_string(ctl.t) + " after a block ending at " +
+                                          std::to_string(stop));
         if (ctl.err) {
             const int64_t tf = ctl.t;  // failing iteration
             c->cur = cur0 ^ (int)((tf - 1 - t0) & 1);
@@ -907,7 +985,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             fix.err = 0;
             fix.t = (uint32_t)(tf - 1);
             fix.n_main_new = ctl.n_main;
-            HIPCHK(c, hipMemcpy(c->w.ctl, &fix, sizeof(Ctl), hipMemcpyHostToDevice));
+            HIPCHK(c, h2d(c->stream, c->w.ctl, &fix, sizeof(Ctl)));
             // the failing merge may have written attempt offsets and deterministic
             // positions for a list that is discarded: rebuild them for the restored one
             {
@@ -924,7 +1002,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                             const uint32_t rep = c->rb ? (uint32_t)(e[i].skey >> (64 - c->rb)) : 0u;
                             pos[(size_t)rep * c->D + e[i].dslot] = (int32_t)i;
                         }
-                    HIPCHK(c, hipMemcpy(c->ws + c->L.ds[3], pos.data(), 4 * pos.size(), hipMemcpyHostToDevice));
+                    HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[3], pos.data(), 4 * pos.size()));
                 }
             }
             for (int64_t it = t0 + 1; it < tf; ++it)
@@ -997,27 +1075,71 @@ fq_status fq_estimator_history(const fq_ctx *c, int32_t instance, fq_estimators_
     return FQ_OK;
 }
 
+// [lo, hi) of one instance in the current main list: the replica id is the
+// most significant field of the sort key, so each instance is one contiguous
+// run, found by binary search over the device array
+fq_status instance_range(fq_ctx *c, int instance, int64_t &lo, int64_t &hi)
+{
+    HIPCHK(c, d2h(c->stream, c->h_ctl, c->w.ctl, sizeof(Ctl)));
+    const int64_t n = c->h_ctl->n_main_new;
+    if (c->rb == 0) {
+        lo = 0;
+        hi = n;
+        return FQ_OK;
+    }
+    const uint64_t *sk = c->buf[c->cur].skey;
+    auto first_rep_at_least = [&](uint64_t r, int64_t &pos) -> fq_status {
+        int64_t a = 0, b = n;
+        while (a < b) {
+            const int64_t m = a + (b - a) / 2;
+            uint64_t v;
+            HIPCHK(c, d2h(c->stream, &v, sk + m, 8));
+            if ((v >> (64 - c->rb)) < r) a = m + 1;
+            else b = m;
+        }
+        pos = a;
+        return FQ_OK;
+    };
+    fq_status st = first_rep_at_least((uint64_t)instance, lo);
+    if (st) return st;
+    return first_rep_at_least((uint64_t)instance + 1, hi);
+}
+
 fq_status fq_export_walkers(const fq_ctx *cc, int32_t instance, uint64_t *keys, int32_t *pops, int64_t cap,
                             int64_t *n_out)
 {
     fq_ctx *c = const_cast<fq_ctx *>(cc);
     if (!c || instance < 0 || instance >= c->R || !n_out) return FQ_EINVAL;
-    std::vector<HostEntry> e;
-    int64_t n;
-    fq_status st = download_main(c, e, n);
+    int64_t lo, hi;
+    fq_status st = instance_range(c, instance, lo, hi);
     if (st) return st;
-    std::vector<const HostEntry *> sel;
-    for (const HostEntry &x : e) {
-        const uint32_t rep = c->rb ? (uint32_t)(x.skey >> (64 - c->rb)) : 0u;
-        if ((int)rep == instance) sel.push_back(&x);
+    const int64_t n = hi - lo;
+    const int W = c->W;
+    *n_out = n;
+    if (n > cap) return fail(c, FQ_ECAPACITY, "export buffer too small");
+    if (!keys && !pops) return FQ_OK;
+    const MainList &m = c->buf[c->cur];
+    std::vector<uint64_t> kk((size_t)n * W);
+    std::vector<int32_t> pp(n);
+    if (n) {
+        for (int q = 0; q < W; ++q)
+            HIPCHK(c, d2h(c->stream, kk.data() + (size_t)q * n, m.key + (size_t)q * c->main_cap + lo, 8 * n));
+        HIPCHK(c, d2h(c->stream, pp.data(), m.pop + lo, 4 * n));
     }
-    std::sort(sel.begin(), sel.end(), [&](const HostEntry *a, const HostEntry *b) { return key_cmp_host(a->key, b->key, c->W) < 0; });
-    *n_out = (int64_t)sel.size();
-    if ((int64_t)sel.size() > cap) return fail(c, FQ_ECAPACITY, "export buffer too small");
-    for (size_t i = 0; i < sel.size(); ++i) {
+    // key order: most significant word first
+    std::vector<int64_t> ord(n);
+    for (int64_t i = 0; i < n; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+        for (int q = W - 1; q >= 0; --q) {
+            const uint64_t x = kk[(size_t)q * n + a], y = kk[(size_t)q * n + b];
+            if (x != y) return x < y;
+        }
+        return false;
+    });
+    for (int64_t i = 0; i < n; ++i) {
         if (keys)
-            for (int q = 0; q < c->W; ++q) keys[i * c->W + q] = sel[i]->key[q];
-        if (pops) pops[i] = sel[i]->pop;
+            for (int q = 0; q < W; ++q) keys[(size_t)i * W + q] = kk[(size_t)q * n + ord[i]];
+        if (pops) pops[i] = pp[ord[i]];
     }
     return FQ_OK;
 }
@@ -1059,14 +1181,14 @@ fq_status fq_import_walkers(fq_ctx *c, int32_t instance, const uint64_t *keys, c
     c->nprev[instance] = n_prev;
     c->t = iteration;
     Ctl ctl;
-    HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    HIPCHK(c, d2h(c->stream, &ctl, c->w.ctl, sizeof(Ctl)));
     ctl.t = (uint32_t)iteration;
     ctl.err = 0;
     ctl.ss_active = 0;
-    HIPCHK(c, hipMemcpy(c->w.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice));
+    HIPCHK(c, h2d(c->stream, c->w.ctl, &ctl, sizeof(Ctl)));
     c->ss_active = false;
     for (int r = 0; r < c->R; ++r) c->h_shift[r] = c->shift[r];
-    HIPCHK(c, hipMemcpy(c->w.shift, c->h_shift, 8 * c->R, hipMemcpyHostToDevice));
+    HIPCHK(c, h2d(c->stream, c->w.shift, c->h_shift, 8 * c->R));
     st = upload_main(c, out);
     if (st) return st;
     st = host_estimators(c);
@@ -1082,17 +1204,17 @@ fq_status fq_export_spawns(const fq_ctx *cc, int32_t instance, uint64_t *keys, i
     if (!c || instance < 0 || instance >= c->R || !n_out) return FQ_EINVAL;
     Ctl ctl;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(&ctl, c->w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    HIPCHK(c, d2h(c->stream, &ctl, c->w.ctl, sizeof(Ctl)));
     const int64_t n = (int64_t)std::min<unsigned long long>(ctl.n_spawn, (unsigned long long)c->spawn_cap);
     std::vector<uint64_t> sk(n), kk((size_t)n * c->W);
     std::vector<uint32_t> ix(n);
     std::vector<int32_t> am(n);
     std::vector<uint8_t> in(n);
     if (n) {
-        HIPCHK(c, hipMemcpy(sk.data(), c->w.sp.skey, 8 * n, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy(ix.data(), c->w.sp.idx, 4 * n, hipMemcpyDeviceToHost));
+        HIPCHK(c, d2h(c->stream, sk.data(), c->w.sp.skey, 8 * n));
+        HIPCHK(c, d2h(c->stream, ix.data(), c->w.sp.idx, 4 * n));
         std::vector<uint64_t> rec((size_t)n * (c->W + 1));
-        HIPCHK(c, hipMemcpy(rec.data(), c->w.sp.rec, 8 * rec.size(), hipMemcpyDeviceToHost));
+        HIPCHK(c, d2h(c->stream, rec.data(), c->w.sp.rec, 8 * rec.size()));
         for (int64_t j = 0; j < n; ++j) {
             for (int q = 0; q < c->W; ++q) kk[(size_t)q * n + j] = rec[(size_t)j * (c->W + 1) + q];
             const uint64_t ai = rec[(size_t)j * (c->W + 1) + c->W];
@@ -1130,7 +1252,7 @@ fq_status fq_detspace(const fq_ctx *cc, int32_t instance, uint64_t *keys, double
     if (keys) std::memcpy(keys, c->dkeys[instance].data(), 8 * (size_t)c->D * c->W);
     if (last_y) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        HIPCHK(c, hipMemcpy(last_y, c->w.ds.y + (size_t)instance * c->D, 8 * (size_t)c->D, hipMemcpyDeviceToHost));
+        HIPCHK(c, d2h(c->stream, last_y, c->w.ds.y + (size_t)instance * c->D, 8 * (size_t)c->D));
     }
     return FQ_OK;
 }
@@ -1158,6 +1280,47 @@ fq_status fq_stage_times(const fq_ctx *c, double *ms7)
     return FQ_OK;
 }
 
+fq_status fq_shift_state(const fq_ctx *c, int32_t instance, double *shift, int64_t *n_prev, int32_t *vary_shift)
+{
+    if (!c || instance < 0 || instance >= c->R) return FQ_EINVAL;
+    if (shift) *shift = c->shift[instance];
+    if (n_prev) *n_prev = c->nprev[instance];
+    if (vary_shift) *vary_shift = c->vary[instance];
+    return FQ_OK;
+}
+
+fq_status fq_set_graph(fq_ctx *c, int32_t on)
+{
+    if (!c) return FQ_EINVAL;
+    if (on && (c->stream == nullptr || c->stream == hipStreamLegacy))
+        return fail(c, FQ_EINVAL, "graph replay needs a stream other than the legacy default stream");
+    c->graph = on != 0;
+    if (!c->graph) drop_graphs(c);
+    return FQ_OK;
+}
+
+fq_status fq_set_launch(fq_ctx *c, const int32_t *blocks, int32_t n)
+{
+    if (!c || !blocks || n < 0) return FQ_EINVAL;
+    int *dst[5] = {&c->grids.spawn, &c->grids.merge, &c->grids.sort, &c->grids.reduce, &c->grids.newdiag};
+    // the merge and the reduction keep one row of estimator partials per block
+    const int cap[5] = {1 << 20, PART_MAX_BLOCKS, 1 << 20, PART_MAX_BLOCKS, 1 << 20};
+    for (int i = 0; i < n && i < 5; ++i)
+        if (blocks[i] > cap[i]) return fail(c, FQ_EINVAL, "launch geometry out of range");
+    for (int i = 0; i < n && i < 5; ++i)
+        if (blocks[i] > 0) *dst[i] = blocks[i];
+    drop_graphs(c);
+    return FQ_OK;
+}
+
+fq_status fq_get_launch(const fq_ctx *c, int32_t *blocks, int32_t n)
+{
+    if (!c || !blocks || n < 0) return FQ_EINVAL;
+    const int src[5] = {c->grids.spawn, c->grids.merge, c->grids.sort, c->grids.reduce, c->grids.newdiag};
+    for (int i = 0; i < n && i < 5; ++i) blocks[i] = src[i];
+    return FQ_OK;
+}
+
 fq_status fq_kernel_times(const fq_ctx *c, double *ms, int32_t cap, int32_t *n_slots, int64_t *n_iterations)
 {
     if (!c || (!ms && cap > 0)) return FQ_EINVAL;
@@ -1172,7 +1335,8 @@ const char *fq_last_error(const fq_ctx *c) { return c ? c->err.c_str() : "null c
 void fq_destroy(fq_ctx *c)
 {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
     if (c->h_ctl) hipHostFree(c->h_ctl);
     if (c->h_hist) hipHostFree(c->h_hist);
     if (c->h_shift) hipHostFree(c->h_shift);

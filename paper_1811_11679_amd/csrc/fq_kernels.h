@@ -64,6 +64,12 @@ struct EstAcc {
     double ss_err;  // split projection: max relative error of the last check
 };
 constexpr int EST_FIELDS = 14;
+// replicas whose estimator partials a block keeps in LDS (the rest are added
+// to global memory directly), and the largest grid of the kernels that write
+// partials
+constexpr int ACC_LDS_R = 64;
+constexpr int PART_MAX_BLOCKS = 8192;
+__host__ __device__ inline int acc_rows(int R) { return R < ACC_LDS_R ? R : ACC_LDS_R; }
 
 struct MainList {
     uint64_t *skey;
@@ -120,6 +126,9 @@ struct Work {
     long long *span_lo;    // [spans + 1]
     long long *mpart;      // merge partition [tiles + 1]
     unsigned long long *st_scan, *st_sort, *st_red, *st_merge, *st_spawn, *st_att;  // look-back status
+    // per-block estimator partials of the reduction and the merge:
+    // [block][acc_rows(R)][EST_FIELDS], folded into acc by the epilogue
+    long long *part_red, *part_mrg;
     MainList cur, nxt;
     SpawnList sp;
     UniqList u;
@@ -134,6 +143,7 @@ struct Work {
 struct Grids {
     int scan, part, spawn, hist, sort, reduce, fixup, merge, det;
     int spawn_lds;  // dynamic LDS bytes of the spawn kernel
+    int newdiag;    // blocks of the new-determinant diagonal kernel
 };
 
 // kernels of one iteration, in launch order (per-kernel timing slots)

@@ -109,8 +109,13 @@ __device__ T block_excl_scan(T v, T &total, T *lds /* 8 entries */)
 }
 
 // ---------------------------------------------------------------------------
-// estimator accumulation: per-thread values, reduced over the wave when all
-// active lanes belong to one replica, else added lane by lane
+// estimator accumulation. A thread sums its values in registers for one
+// replica at a time; when it moves on to another replica (and at the end of
+// the kernel) the values go to the block's table in LDS (replicas below
+// acc_rows(R); others are added to global memory directly). At the end each
+// block stores its table as one row of partials with plain stores and the
+// iteration epilogue folds the rows. The accumulators are a few addresses
+// that every block would otherwise hit with device-scope atomics.
 // ---------------------------------------------------------------------------
 struct LocalAcc {
     long long v[EST_FIELDS];
@@ -122,32 +127,60 @@ struct LocalAcc {
     }
 };
 
-__device__ void flush_acc(LocalAcc &a, EstAcc *acc, bool active)
+__device__ __forceinline__ void acc_table_clear(long long *tab, int rl)
+{
+    for (int i = threadIdx.x; i < rl * EST_FIELDS; i += blockDim.x) tab[i] = 0;
+}
+
+__device__ __forceinline__ void acc_add(long long *tab, int rl, EstAcc *g, int rep, int f, long long v)
+{
+    if (rep < rl)
+        atomicAdd((unsigned long long *)&tab[rep * EST_FIELDS + f], (unsigned long long)v);
+    else
+        atomicAdd((unsigned long long *)(&g[rep].nw + f), (unsigned long long)v);
+}
+
+// the thread's values to the block table, lane by lane
+__device__ __forceinline__ void acc_spill(LocalAcc &a, long long *tab, int rl, EstAcc *g)
+{
+    if (a.rep < 0) return;
+#pragma unroll
+    for (int f = 0; f < EST_FIELDS; ++f)
+        if (a.v[f]) acc_add(tab, rl, g, a.rep, f, a.v[f]);
+    a.clear();
+}
+
+__device__ __forceinline__ void acc_switch(LocalAcc &acc, int rep, long long *tab, int rl, EstAcc *g)
+{
+    if (rep == acc.rep) return;
+    acc_spill(acc, tab, rl, g);
+    acc.rep = rep;
+}
+
+// end of a kernel (all threads): reduce over the wave when its active lanes
+// hold one replica, then store the block's table as partial row blockIdx.x
+__device__ void acc_finish(LocalAcc &a, bool active, long long *tab, int rl, EstAcc *g, long long *part)
 {
     const uint64_t act = __ballot(active);
-    if (!act) return;
-    const int leader = __ffsll((unsigned long long)act) - 1;
-    const int rep0 = __shfl(a.rep, leader, 64);
-    const bool uniform = __ballot(active && a.rep != rep0) == 0;
-    long long *dst;
-    if (uniform) {
+    if (act) {
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const int rep0 = __shfl(a.rep, leader, 64);
+        const bool uniform = __ballot(active && a.rep != rep0) == 0;
+        if (uniform) {
 #pragma unroll
-        for (int i = 0; i < EST_FIELDS; ++i) {
-            const long long s = wave_sum<long long>(active ? a.v[i] : 0);
-            if (lane_id() == leader && s != 0) {
-                dst = &acc[rep0].nw + i;
-                atomicAdd((unsigned long long *)dst, (unsigned long long)s);
+            for (int f = 0; f < EST_FIELDS; ++f) {
+                const long long sv = wave_sum<long long>(active ? a.v[f] : 0);
+                if (lane_id() == leader && sv != 0) acc_add(tab, rl, g, rep0, f, sv);
             }
+        } else if (active) {
+            acc_spill(a, tab, rl, g);
         }
-    } else if (active) {
-#pragma unroll
-        for (int i = 0; i < EST_FIELDS; ++i)
-            if (a.v[i] != 0) {
-                dst = &acc[a.rep].nw + i;
-                atomicAdd((unsigned long long *)dst, (unsigned long long)a.v[i]);
-            }
     }
     a.clear();
+    __syncthreads();
+    // partials are laid out [replica][field][block] so that the fold reads
+    // each (replica, field) as one contiguous run
+    for (int i = threadIdx.x; i < rl * EST_FIELDS; i += blockDim.x) part[(size_t)i * PART_MAX_BLOCKS + blockIdx.x] = tab[i];
 }
 
 enum { F_NW = 0, F_NOCC, F_N0, F_NSPAWN, F_NUNIQ, F_FLIPS, F_REJU, F_DEATH, F_SPAWN, F_REJ, F_L0, F_L1, F_L2, F_L3 };
@@ -173,15 +206,29 @@ __global__ void k_begin(Work w)
     for (int i = threadIdx.x; i < w.R * (int)(sizeof(EstAcc) / 8); i += blockDim.x) ((long long *)w.acc)[i] = 0;
 }
 
-__global__ void k_end(Work w)
+__global__ __launch_bounds__(1024) void k_end(Work w, int nb_red, int nb_mrg)
 {
+    // one block per replica, one wave per estimator field: fold the partials
+    // of the reduction and the merge into the accumulators, then record them
+    // in the history ring
     const Ctl *c = w.ctl;
     if (c->err) return;
-    const int slot = (int)(c->t % (uint32_t)w.hist_len);
-    for (int r = threadIdx.x; r < w.R; r += blockDim.x) {
+    const int r = blockIdx.x;
+    const int f = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (r < acc_rows(w.R) && f < EST_FIELDS) {
+        const long long *pr = w.part_red + (size_t)(r * EST_FIELDS + f) * PART_MAX_BLOCKS;
+        const long long *pm = w.part_mrg + (size_t)(r * EST_FIELDS + f) * PART_MAX_BLOCKS;
+        long long sum = 0;
+        for (int b = lane; b < nb_red; b += 64) sum += pr[b];
+        for (int b = lane; b < nb_mrg; b += 64) sum += pm[b];
+        sum = wave_sum<long long>(sum);
+        if (lane == 0) (&w.acc[r].nw)[f] += sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         EstAcc a = w.acc[r];
         a.t = c->t;
-        w.hist[(size_t)slot * w.R + r] = a;
+        w.hist[(size_t)(c->t % (uint32_t)w.hist_len) * w.R + r] = a;
     }
 }
 
@@ -656,6 +703,10 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
     Ctl *c = w.ctl;
     if (c->err) return;
     if (second && !c->collision) return;
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    long long *tab = (long long *)dyn_lds;  // estimator table, acc_rows(R) rows
+    const int rl = acc_rows(w.R);
+    acc_table_clear(tab, rl);
     __shared__ uint64_t s_lastk[RD_T][W];
     __shared__ uint64_t s_lasts[RD_T];
     __shared__ long long s_tile, s_base;
@@ -767,16 +818,7 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
             }
             run_sum += am[i];
             run_flag |= fl[i];
-            const int rep = (int)skey_rep(sk[i], w.rb);
-            if (rep != acc.rep) {
-                if (acc.rep >= 0) {
-#pragma unroll
-                    for (int f = 0; f < EST_FIELDS; ++f)
-                        if (acc.v[f]) atomicAdd((unsigned long long *)(&w.acc[acc.rep].nw + f), (unsigned long long)acc.v[f]);
-                    acc.clear();
-                }
-                acc.rep = rep;
-            }
+            acc_switch(acc, (int)skey_rep(sk[i], w.rb), tab, rl, w.acc);
             acc.v[F_NSPAWN] += 1;
             acc.v[F_SPAWN] += am[i];
             acc.v[F_NUNIQ] += head[i] ? 1 : 0;
@@ -789,7 +831,7 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
         if (tile == ntiles - 1 && threadIdx.x == 0) c->n_uniq = s_base + tot;
         __syncthreads();
     }
-    flush_acc(acc, w.acc, any && acc.rep >= 0);
+    acc_finish(acc, any && acc.rep >= 0, tab, rl, w.acc, w.part_red);
 }
 
 // Rare path: equal sort keys holding different determinants are put in key
@@ -930,18 +972,6 @@ __device__ __forceinline__ void add_limbs(long long (&v)[EST_FIELDS], double x)
     v[F_L3] += neg ? -l3 : l3;
 }
 
-__device__ __forceinline__ void acc_switch(LocalAcc &acc, int rep, EstAcc *g)
-{
-    if (rep == acc.rep) return;
-    if (acc.rep >= 0) {
-#pragma unroll
-        for (int f = 0; f < EST_FIELDS; ++f)
-            if (acc.v[f]) atomicAdd((unsigned long long *)(&g[acc.rep].nw + f), (unsigned long long)acc.v[f]);
-        acc.clear();
-    }
-    acc.rep = rep;
-}
-
 // spawning attempts of a determinant holding p units: |p| for integer walkers,
 // ceil(|p| 2^-b) for fixed point
 __device__ __forceinline__ long long attempts_of(long long p, int bits, Ctl *c)
@@ -979,6 +1009,10 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
     const uint32_t t = c->t;
     const uint32_t epoch = epoch_of(t, 11), epoch_att = epoch_of(t, 13);
     const bool ss = c->ss_active != 0;
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    long long *tab = (long long *)dyn_lds;  // estimator table, acc_rows(R) rows
+    const int rl = acc_rows(w.R);
+    acc_table_clear(tab, rl);
     LocalAcc acc;
     acc.clear();
     acc.rep = -1;
@@ -1060,7 +1094,7 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                 const int32_t n0 = (int32_t)s_val[a];
                 const int32_t dsl = s_meta[a];
                 const int rep = MULTI ? (int)skey_rep(sk, w.rb) : 0;
-                acc_switch(acc, rep, w.acc);
+                acc_switch(acc, rep, tab, rl, w.acc);
                 any = true;
                 // matching spawned determinant: the next unconsumed one
                 long long add = 0;
@@ -1121,7 +1155,7 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                     const int32_t fl = s_meta[slot];
                     const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
                     const RepParams &rp = w.rep[rep];
-                    acc_switch(acc, rep, w.acc);
+                    acc_switch(acc, rep, tab, rl, w.acc);
                     any = true;
                     const bool accept = (!rp.initiator || fl) && sum != 0;
                     if (accept) {
@@ -1202,7 +1236,7 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                 w.nxt.dslot[o] = ds;
                 if (ds >= 0) w.ds.pos[(size_t)rep * w.ds.n + ds] = (int32_t)o;
                 const long long ap = p < 0 ? -(long long)p : (long long)p;
-                acc_switch(acc, rep, w.acc);
+                acc_switch(acc, rep, tab, rl, w.acc);
                 any = true;
                 acc.v[F_NW] += ap;
                 acc.v[F_NOCC] += 1;
@@ -1225,7 +1259,7 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
         }
         __syncthreads();
     }
-    flush_acc(acc, w.acc, any && acc.rep >= 0);
+    acc_finish(acc, any && acc.rep >= 0, tab, rl, w.acc, w.part_mrg);
     if (blockIdx.x == 0 && threadIdx.x == 0 && ntiles == 0) {
         c->n_main_new = 0;
         w.att_off[0] = 0;
@@ -1601,11 +1635,12 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
                                              I[(p + 1) & 1]);
         rec();
     }
-    k_reduce<W><<<g.reduce, RD_T, 0, s>>>(w, 0);
+    const int accb = acc_rows(w.R) * EST_FIELDS * 8;
+    k_reduce<W><<<g.reduce, RD_T, accb, s>>>(w, 0);
     rec();
     k_fixup<W><<<g.fixup, 256, 0, s>>>(w);
     rec();
-    k_reduce<W><<<g.reduce, RD_T, 0, s>>>(w, 1);
+    k_reduce<W><<<g.reduce, RD_T, accb, s>>>(w, 1);
     rec();
     k_det_gather<<<g.det, 256, 0, s>>>(w);
     rec();
@@ -1619,13 +1654,13 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     k_merge_partition<W><<<g.part, 256, 0, s>>>(w);
     rec();
     if (w.R > 1)
-        k_merge<KIND, W, true><<<g.merge, MG_T, 0, s>>>(w);
+        k_merge<KIND, W, true><<<g.merge, MG_T, accb, s>>>(w);
     else
-        k_merge<KIND, W, false><<<g.merge, MG_T, 0, s>>>(w);
+        k_merge<KIND, W, false><<<g.merge, MG_T, accb, s>>>(w);
     rec();
-    k_new_diag<KIND, W><<<g.det * 2, ND_T, w.lds_diag, s>>>(w);
+    k_new_diag<KIND, W><<<g.newdiag, ND_T, w.lds_diag, s>>>(w);
     rec();
-    k_end<<<1, 64, 0, s>>>(w);
+    k_end<<<w.R, 1024, 0, s>>>(w, g.reduce, g.merge);
     rec();
 }
 

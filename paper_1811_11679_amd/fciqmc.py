@@ -23,7 +23,9 @@ SS_FP64, SS_SPLIT_BF16 = 0, 1
 # every function the header declares
 C_API = ["fq_workspace_bytes", "fq_init_system", "fq_step", "fq_estimators", "fq_estimator_history",
          "fq_export_walkers", "fq_import_walkers", "fq_export_spawns", "fq_detspace", "fq_info",
-         "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_last_error", "fq_destroy"]
+         "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_set_graph", "fq_set_launch", "fq_shift_state",
+         "fq_get_launch", "fq_last_error", "fq_destroy"]
+LAUNCH_KERNELS = ["spawn", "merge", "sort", "reduce", "new_diag"]
 
 KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "sort_hist"] + \
     [f"sort_pass{p}" for p in range(8)] + ["reduce", "fixup", "reduce2", "det_gather", "det_project", "det_check",
@@ -114,6 +116,15 @@ def load_library():
     L.fq_kernel_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int64)]
     L.fq_kernel_times.restype = C.c_int32
+    L.fq_shift_state.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int32)]
+    L.fq_shift_state.restype = C.c_int32
+    L.fq_set_graph.argtypes = [P, C.c_int32]
+    L.fq_set_graph.restype = C.c_int32
+    L.fq_set_launch.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
+    L.fq_set_launch.restype = C.c_int32
+    L.fq_get_launch.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
+    L.fq_get_launch.restype = C.c_int32
     L.fq_last_error.argtypes = [P]
     L.fq_last_error.restype = C.c_char_p
     L.fq_destroy.argtypes = [P]
@@ -155,7 +166,7 @@ class Context:
     """One FCIQMC context on a HIP device: n_instances replicas of one system shape."""
 
     def __init__(self, systems, qmcs, semistoch=None, main_capacity=1 << 16, spawn_capacity=1 << 16,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, graph=False):
         import torch
 
         L = load_library()
@@ -178,6 +189,9 @@ class Context:
         if nbytes == 0:
             raise FqError(FQ_EINVAL, "invalid system description")
         self.device = torch.device(device)
+        self.n_cu = torch.cuda.get_device_properties(self.device).multi_processor_count
+        if stream is None and graph:
+            stream = torch.cuda.Stream(self.device)  # default priority; graph capture needs a real stream
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
@@ -192,6 +206,8 @@ class Context:
         L.fq_info(self.ctx, C.byref(W), C.byref(nso), C.byref(e0))
         self.W, self.n_so, self.e_ref = W.value, nso.value, e0.value
         self.main_capacity, self.spawn_capacity = main_capacity, spawn_capacity
+        if graph:
+            self._check(L.fq_set_graph(self.ctx, 1))
 
     def _check(self, st):
         if st != FQ_OK:
@@ -239,6 +255,12 @@ class Context:
         self._check(self.lib.fq_import_walkers(self.ctx, instance, keys.ctypes.data, pops.ctypes.data,
                                                len(pops), shift, iteration, vary, n_prev))
 
+    def shift_state(self, instance=0):
+        """(shift, n_prev, vary): with export() and estimators(), what import_walkers needs"""
+        sh, npv, va = C.c_double(), C.c_int64(), C.c_int32()
+        self._check(self.lib.fq_shift_state(self.ctx, instance, C.byref(sh), C.byref(npv), C.byref(va)))
+        return sh.value, npv.value, va.value
+
     def spawns(self, instance=0):
         n = C.c_int64()
         self.lib.fq_export_spawns(self.ctx, instance, None, None, None, 0, C.byref(n))
@@ -259,6 +281,19 @@ class Context:
         self._check(self.lib.fq_detspace(self.ctx, instance, keys.ctypes.data, y.ctypes.data, n.value,
                                          C.byref(n)))
         return keys[: n.value * self.W].reshape(n.value, self.W), y[: n.value]
+
+    def set_graph(self, on=True):
+        self._check(self.lib.fq_set_graph(self.ctx, int(on)))
+
+    def set_launch(self, blocks):
+        """blocks: {kernel name: blocks} for names in LAUNCH_KERNELS"""
+        arr = (C.c_int32 * len(LAUNCH_KERNELS))(*[int(blocks.get(k, 0)) for k in LAUNCH_KERNELS])
+        self._check(self.lib.fq_set_launch(self.ctx, arr, len(LAUNCH_KERNELS)))
+
+    def get_launch(self):
+        arr = (C.c_int32 * len(LAUNCH_KERNELS))()
+        self._check(self.lib.fq_get_launch(self.ctx, arr, len(LAUNCH_KERNELS)))
+        return dict(zip(LAUNCH_KERNELS, list(arr)))
 
     def set_timing(self, on=True):
         self._check(self.lib.fq_set_timing(self.ctx, int(on)))

@@ -41,3 +41,20 @@ UEG54 = dict(
 )
 
 UEG_ECUT_FOR_BASIS = {19: 2, 27: 3, 57: 5, 123: 9}
+
+
+def batch64(n_replicas=64, seed=7):
+    """64 independent electron-gas instances of 14 electrons (7 + 7): rs and
+    the basis size drawn uniformly from {0.5, 1, 2, 4} x {19, 27, 57, 123}
+    plane waves, targets log-uniform in [1e5, 2e6] walkers, initial population
+    target / 20, dtau = 0.002 min(1, rs^2) (energies grow as 1 / rs^2), one
+    Philox stream per replica (key word 1 xor replica id); everything else as
+    UEG14. Returns a list of (system, qmc) dicts."""
+    from .synth import batched_ueg_draws
+    out = []
+    for r, (rs, m, tgt) in enumerate(batched_ueg_draws(n_replicas, seed)):
+        system = dict(kind="ueg", rs=rs, ecut_n2=UEG_ECUT_FOR_BASIS[m], n_alpha=7, n_beta=7)
+        qmc = dict(UEG14["qmc"], tau=0.002 * min(1.0, rs * rs), init_pop=tgt / 20.0, target_population=tgt,
+                   replica_id=r)
+        out.append((system, qmc))
+    return out
