@@ -63,10 +63,17 @@ def measured_traffic(kernel):
     return None if k is None else k["bytes_per_launch"]
 
 
-def cpu_baseline(budget_s=15.0, max_iter=400):
-    """The oracle on the same workload from its initial state, single thread."""
+def cpu_baseline(state, budget_s=20.0, max_iter=50, max_dets=4_000_000):
+    """The oracle, single thread, continuing from a bounded sample of the GPU's
+    state at the start of the timed window: every k-th determinant of the list
+    in key order (at most max_dets), with the same shift and iteration, for as
+    many whole iterations as fit in about budget_s seconds. Work per walker
+    update is what is compared; the sample keeps the oracle's run short."""
     from oracle import oracle as O
     from paper_1811_11679_amd import workloads
+    keys_all, pops_all, e, (sh, nprev, vary) = state
+    k = max(1, -(-len(pops_all) // max_dets))
+    keys, pops = keys_all[::k], pops_all[::k]
     w = workloads.UEG14
     s, q = w["system"], w["qmc"]
     sysd = O.System.ueg(s["rs"], s["ecut_n2"], s["n_alpha"], s["n_beta"])
@@ -75,6 +82,7 @@ def cpu_baseline(budget_s=15.0, max_iter=400):
                                  shift_damping=q["shift_damping"], excit_gen=O.EXGEN_UEG, initiator=1,
                                  initiator_threshold=q["initiator_threshold"], fixed_point_bits=8,
                                  spawn_cutoff=q["spawn_cutoff"]))
+    run.import_walkers(keys, pops, shift=sh, iteration=int(e["iteration"]), vary=vary, n_prev=max(1, nprev // k))
     nw_prev = run.estimators()["n_walkers_units"]
     upd, it = 0.0, 0
     t0 = time.perf_counter()
@@ -83,21 +91,13 @@ def cpu_baseline(budget_s=15.0, max_iter=400):
         upd += nw_prev / 256.0
         nw_prev = run.estimators()["n_walkers_units"]
         it += 1
+        print(f"# oracle iteration {it}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
     return {"value": upd / dt, "unit": "walker updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {it} iterations of the same workload from its initial state "
-                      f"({run.estimators()['n_occupied']} determinants at the end), single thread"}
-
-
-def batch_capacity(inst):
-    """Determinant and spawn capacities for a group of instances. Death and
-    cloning shrink populations continuously, so an instance can hold tens of
-    determinants per walker (up to about 30 measured at 123 plane waves): the
-    main list gets 40 entries per target walker, the spawn list 4 spawns."""
-    def cap(members, n_now=0):
-        tot = sum(inst[i][1]["target_population"] for i in members)
-        return int(max(40 * tot, 2 * n_now)), int(4 * tot)
-    return cap
+            "sample": f"{it} iterations ({e['iteration'] + 1}..{e['iteration'] + it}) from every {k}-th "
+                      f"determinant of the GPU list at the start of the timed window ({len(pops)} of "
+                      f"{len(pops_all)} determinants, {abs(pops.astype('int64')).sum() / 256:.4g} walkers), "
+                      f"single thread"}
 
 
 HIST_FIELDS = ("iteration", "n_walkers_units", "n_occupied", "ref_pop_units", "n_spawned", "n_spawn_events",
@@ -247,6 +247,10 @@ def main():
               f"{time.perf_counter() - t_w0:.1f} s", file=sys.stderr, flush=True)
     warm_s = time.perf_counter() - t_w0
     e_start = ctx.estimators()
+    start_state = None
+    if not args.no_cpu_baseline:
+        keys, pops = ctx.export()
+        start_state = (keys, pops, e_start, ctx.shift_state())
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -260,6 +264,9 @@ def main():
     dt = t1 - t0
     ktimes, niter = ctx.kernel_times()
     stages = ctx.stage_times()
+    it_ms = sorted(ctx.iteration_times())
+    dets = sum(h["n_occupied"] for h in prev)
+    spawned = sum(h["n_spawned"] for h in hist)
     # algorithmic bytes per kernel summed over the timed iterations
     tot_bytes = {}
     for a, b in zip(prev, hist):
@@ -296,6 +303,10 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(best),
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch},
         "annihilation_gbps_algorithmic": ann_bytes / (ann_ms * 1e-3) / 1e9 if ann_ms > 0 else None,
+        "iteration_ms_device": {"median": it_ms[len(it_ms) // 2], "p90": it_ms[(9 * len(it_ms)) // 10],
+                                "min": it_ms[0], "max": it_ms[-1]} if it_ms else None,
+        "determinant_updates_per_s": dets / dt,
+        "spawns_per_s": spawned / dt,
         "stage_ms_per_iteration": {k: v / max(niter, 1) for k, v in stages.items()},
         "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in ktimes.items()},
         "walkers_start": e_start["n_walkers_units"] / 256.0,
@@ -316,8 +327,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 1 << 30
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+    if start_state is not None:
+        out["cpu_baseline"] = cpu_baseline(start_state)
     print(json.dumps(out))
 
 

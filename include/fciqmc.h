@@ -230,6 +230,11 @@ fq_status fq_stage_times(const fq_ctx *ctx, double *ms7);
 fq_status fq_kernel_times(const fq_ctx *ctx, double *ms, int32_t cap, int32_t *n_slots,
                           int64_t *n_iterations);
 
+/* Device time of each iteration of the last fq_step call made with timing on
+ * (first event of the iteration to its last), ms, oldest first; *n_out
+ * receives the number written (at most cap). */
+fq_status fq_iteration_times(const fq_ctx *ctx, double *ms, int64_t cap, int64_t *n_out);
+
 /* Graph replay: with on = 1, every block of shift_period iterations between
  * two host shift updates is captured once into a HIP graph (per main-list
  * parity) and replayed with one launch. The stream given to fq_init_system

@@ -833,8 +833,17 @@ static int spawn_attempt(or_run *r, const uint64_t *key, uint64_t h, int32_t n0,
         double an = (double)(n0 < 0 ? -(int64_t)n0 : (int64_t)n0);
         m = (((r->q.tau * ah) / pgen) * an) / (double)nat;
     }
-    draw(r, TAG_SPAWN_ROUND, (uint32_t)k, t, h, rnd);
-    double u = u53(rnd[0], rnd[1]);
+    /* the uniform of the stochastic rounding: the Hubbard and electron-gas
+       generators use only the first one or two words of the selection block,
+       so its last two words serve; heat-bath uses every word and draws a
+       block of its own */
+    double u;
+    if (r->q.excit_gen == OR_EXGEN_HEATBATH) {
+        draw(r, TAG_SPAWN_ROUND, (uint32_t)k, t, h, rnd);
+        u = u53(rnd[0], rnd[1]);
+    } else {
+        u = u53(w[2], w[3]);
+    }
     if (!(m < 0x1p31)) return OR_EOVERFLOW;
     int64_t kk;
     if (r->q.fixed_point_bits != 0 && m < (double)r->cu)

@@ -238,7 +238,7 @@ struct Layout {
 int64_t tiles_of(int64_t n, int64_t tile) { return (n + tile - 1) / tile + 1; }
 
 // spans of 256 attempts the attempt partition can hold
-int64_t span_capacity(int64_t mcap, int64_t scap) { return tiles_of(std::max(mcap * 16, scap * 4), 1024); }
+int64_t span_capacity(int64_t mcap, int64_t scap) { return tiles_of(std::max(mcap * 16, scap * 4), SPAN); }
 
 Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D)
 {
@@ -344,6 +344,7 @@ struct fq_ctx {
     double stage_ms[7] = {0};
     double kernel_ms[N_KERNEL_SLOTS] = {0};
     int64_t timed_iterations = 0;
+    std::vector<double> iter_ms;  // per-iteration device time of the last timed fq_step
     std::string err;
 };
 
@@ -895,6 +896,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
     std::fill(c->stage_ms, c->stage_ms + 7, 0.0);
     std::fill(c->kernel_ms, c->kernel_ms + N_KERNEL_SLOTS, 0.0);
     c->timed_iterations = 0;
+    c->iter_ms.clear();
     constexpr int NE = N_KERNEL_SLOTS + 1;
     std::vector<hipEvent_t> evs;
     int done = 0;
@@ -967,6 +969,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                 }
                 (void)hipEventElapsedTime(&ms, e[0], e[N_KERNEL_SLOTS]);
                 c->stage_ms[6] += ms;
+                c->iter_ms.push_back(ms);
             }
             c->timed_iterations += nb;
             for (auto &e : evs) (void)hipEventDestroy(e);
@@ -1286,6 +1289,15 @@ fq_status fq_shift_state(const fq_ctx *c, int32_t instance, double *shift, int64
     if (shift) *shift = c->shift[instance];
     if (n_prev) *n_prev = c->nprev[instance];
     if (vary_shift) *vary_shift = c->vary[instance];
+    return FQ_OK;
+}
+
+fq_status fq_iteration_times(const fq_ctx *c, double *ms, int64_t cap, int64_t *n_out)
+{
+    if (!c || !n_out || (cap > 0 && !ms)) return FQ_EINVAL;
+    const int64_t n = std::min<int64_t>(cap, (int64_t)c->iter_ms.size());
+    for (int64_t i = 0; i < n; ++i) ms[i] = c->iter_ms[i];
+    *n_out = n;
     return FQ_OK;
 }
 

@@ -68,6 +68,11 @@ constexpr int EST_FIELDS = 14;
 // to global memory directly), and the largest grid of the kernels that write
 // partials
 constexpr int ACC_LDS_R = 64;
+// spawn tiles: SP_T threads, SP_I attempts per thread, SPAN attempts per tile
+#ifndef FQ_SPAWN_ITEMS
+#define FQ_SPAWN_ITEMS 4
+#endif
+constexpr int SP_T = 256, SP_I = FQ_SPAWN_ITEMS, SPAN = SP_T * SP_I;
 constexpr int PART_MAX_BLOCKS = 8192;
 __host__ __device__ inline int acc_rows(int R) { return R < ACC_LDS_R ? R : ACC_LDS_R; }
 

@@ -292,7 +292,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_attempts(Work w)
 // finds its spawn count, takes its output offset by decoupled look-back (no
 // contended counter) and writes its records contiguously.
 // ---------------------------------------------------------------------------
-constexpr int SP_T = 256, SP_I = 4, SPAN = SP_T * SP_I;
+
 
 __device__ __forceinline__ long long upper_bound_ll(const long long *a, long long lo, long long hi, long long x)
 {
@@ -325,19 +325,26 @@ __global__ void k_spawn_partition(Work w)
 
 // MULTI = false: a single replica (rb = 0), so the replica index is 0, its
 // parameters are uniform over the grid and a determinant's hash is its sort key.
-template <int KIND, int W, bool MULTI>
+// LT (single-replica electron gas): the generator's small tables are staged in
+// LDS; a compile-time choice, so that their loads are LDS loads.
+//
+// LDS per block: the attempt offsets of the tile's parents and the first
+// SP_STAGE spawn records (written out coalesced); records beyond that, rare at
+// the spawn rates of the method, go to global memory directly.
+constexpr int SP_STAGE = 256;
+template <int KIND, int W, bool MULTI, bool LT>
 __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 {
     Ctl *c = w.ctl;
     if (c->err) return;
-    constexpr int LCAP = 2 * SPAN + 2;
+    constexpr int LCAP = SPAN + 2;
     __shared__ long long s_off[LCAP];
     __shared__ uint32_t s_cnt[SP_I][SP_T / 64];
     __shared__ long long s_tile, s_base;
-    __shared__ uint64_t s_rk[SPAN];
-    __shared__ uint64_t s_rkey[W][SPAN];
-    __shared__ int32_t s_ramp[SPAN];
-    __shared__ uint8_t s_rinit[SPAN];
+    __shared__ uint64_t s_rk[SP_STAGE];
+    __shared__ uint64_t s_rkey[W][SP_STAGE];
+    __shared__ int32_t s_ramp[SP_STAGE];
+    __shared__ uint8_t s_rinit[SP_STAGE];
     const long long total = c->n_att;
     const long long nspans = (total + SPAN - 1) / SPAN;
     if (nspans + 1 > w.span_cap) return;
@@ -345,23 +352,20 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
     const bool ss = c->ss_active != 0;
     const uint32_t epoch = epoch_of(t, 12);
     const int lane = lane_id(), wid = threadIdx.x >> 6;
-    // single replica, UEG: the small tables of the generator live in LDS
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     UegTables lu = w.sys[w.rep[0].sys].u;
-    if constexpr (!MULTI && KIND == K_UEG) {
-        if (w.lds_tables > 0) {
-            const int M = lu.M, nv = w.sys[w.rep[0].sys].vlen, ng = lu.gdim * lu.gdim * lu.gdim;
-            int32_t *tn = (int32_t *)dyn_lds;
-            double *tv = (double *)(dyn_lds + ((4 * M + 15) & ~15));
-            int16_t *tg = (int16_t *)((unsigned char *)tv + ((8 * nv + 15) & ~15));
-            for (int i = threadIdx.x; i < M; i += SP_T) tn[i] = lu.npk[i];
-            for (int i = threadIdx.x; i < nv; i += SP_T) tv[i] = lu.vtab[i];
-            for (int i = threadIdx.x; i < ng; i += SP_T) tg[i] = lu.grid[i];
-            lu.npk = tn;
-            lu.vtab = tv;
-            lu.grid = tg;
-            lu.vx = nullptr;
-        }
+    if constexpr (LT) {
+        const int M = lu.M, nv = w.sys[w.rep[0].sys].vlen, ng = lu.gdim * lu.gdim * lu.gdim;
+        int32_t *tn = (int32_t *)dyn_lds;
+        double *tv = (double *)(dyn_lds + ((4 * M + 15) & ~15));
+        int16_t *tg = (int16_t *)((unsigned char *)tv + ((8 * nv + 15) & ~15));
+        for (int i = threadIdx.x; i < M; i += SP_T) tn[i] = lu.npk[i];
+        for (int i = threadIdx.x; i < nv; i += SP_T) tv[i] = lu.vtab[i];
+        for (int i = threadIdx.x; i < ng; i += SP_T) tg[i] = lu.grid[i];
+        lu.npk = tn;
+        lu.vtab = tv;
+        lu.grid = tg;
+        lu.vx = nullptr;
     }
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[TK_SPAWN], 1u);
@@ -380,9 +384,58 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
         int32_t amp[SP_I];
         uint8_t init[SP_I];
         uint32_t rep[SP_I];
-        // blocked: thread t takes attempts 4t .. 4t+3 of the tile; one search
-        // finds the first parent, later attempts advance from it
-        long long ip = -1;
+        // phase 1: the parent of each attempt (blocked: thread t takes attempts
+        // 4t .. 4t+3 of the tile; one search finds the first parent, later
+        // attempts advance from it), its first attempt and its attempt count
+        long long pi[SP_I], pa0[SP_I], pnat[SP_I];
+        {
+            long long ip = -1;
+#pragma unroll
+            for (int it = 0; it < SP_I; ++it) {
+                pi[it] = -1;
+                pa0[it] = 0;
+                pnat[it] = 1;
+                const long long a = span * SPAN + (long long)threadIdx.x * SP_I + it;
+                if (a < total) {
+                    long long i;
+                    if (staged) {
+                        if (ip < 0) {
+                            int l = 0, h = (int)len;
+                            while (l < h) {
+                                const int m = (l + h) >> 1;
+                                if (s_off[m] <= a) l = m + 1; else h = m;
+                            }
+                            ip = lo + l - 1;
+                        } else {
+                            while (s_off[ip - lo + 1] <= a) ++ip;
+                        }
+                        i = ip;
+                    } else {
+                        i = upper_bound_ll(w.att_off, lo, hi + 2, a) - 1;
+                    }
+                    pi[it] = i;
+                    pa0[it] = staged ? s_off[i - lo] : w.att_off[i];
+                    pnat[it] = (staged ? s_off[i - lo + 1] : w.att_off[i + 1]) - pa0[it];
+                }
+            }
+        }
+        // phase 2 (short keys): every parent load of the thread in flight at once
+        constexpr bool PF = W <= 2;
+        uint64_t pkey[PF ? SP_I : 1][W];
+        int32_t pn0[PF ? SP_I : 1], pdsl[PF ? SP_I : 1];
+        uint64_t ppsk[PF ? SP_I : 1];
+        if constexpr (PF) {
+#pragma unroll
+            for (int it = 0; it < SP_I; ++it) {
+                const long long i = pi[it] < 0 ? 0 : pi[it];
+#pragma unroll
+                for (int q = 0; q < W; ++q) pkey[it][q] = w.cur.key[(size_t)q * w.main_cap + i];
+                pn0[it] = w.cur.pop[i];
+                pdsl[it] = w.cur.dslot[i];
+                ppsk[it] = w.cur.skey[i];
+            }
+        }
+        // phase 3: excitation, matrix element, amplitude
 #pragma unroll
         for (int it = 0; it < SP_I; ++it) {
             has[it] = false;
@@ -391,33 +444,26 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
             rep[it] = 0;
 #pragma unroll
             for (int q = 0; q < W; ++q) child[it][q] = 0;
-            const long long a = span * SPAN + (long long)threadIdx.x * SP_I + it;
-            if (a < total) {
-                long long i;
-                if (staged) {
-                    if (ip < 0) {
-                        int l = 0, h = (int)len;
-                        while (l < h) {
-                            const int m = (l + h) >> 1;
-                            if (s_off[m] <= a) l = m + 1; else h = m;
-                        }
-                        ip = lo + l - 1;
-                    } else {
-                        while (s_off[ip - lo + 1] <= a) ++ip;
-                    }
-                    i = ip;
-                } else {
-                    i = upper_bound_ll(w.att_off, lo, hi + 2, a) - 1;
-                }
-                const long long a0 = staged ? s_off[i - lo] : w.att_off[i];
-                const long long nat = (staged ? s_off[i - lo + 1] : w.att_off[i + 1]) - a0;
-                const long long k = a - a0;
+            if (pi[it] >= 0) {
+                const long long i = pi[it];
+                const long long nat = pnat[it];
+                const long long k = span * SPAN + (long long)threadIdx.x * SP_I + it - pa0[it];
                 uint64_t key[W];
+                int32_t n0, dsl;
+                uint64_t psk;
+                if constexpr (PF) {
 #pragma unroll
-                for (int q = 0; q < W; ++q) key[q] = w.cur.key[(size_t)q * w.main_cap + i];
-                const int32_t n0 = w.cur.pop[i];
-                const int32_t dsl = w.cur.dslot[i];
-                const uint64_t psk = w.cur.skey[i];
+                    for (int q = 0; q < W; ++q) key[q] = pkey[it][q];
+                    n0 = pn0[it];
+                    dsl = pdsl[it];
+                    psk = ppsk[it];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) key[q] = w.cur.key[(size_t)q * w.main_cap + i];
+                    n0 = w.cur.pop[i];
+                    dsl = w.cur.dslot[i];
+                    psk = w.cur.skey[i];
+                }
                 rep[it] = MULTI ? skey_rep(psk, w.rb) : 0u;
                 const RepParams &rp = w.rep[MULTI ? rep[it] : 0u];
                 const DevSys &sy = w.sys[rp.sys];
@@ -431,7 +477,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 if constexpr (KIND == K_HUBBARD)
                     ok = gen_hubbard<W>(sy, key, r0.x, child[it], pgen, hv);
                 else if constexpr (KIND == K_UEG)
-                    ok = gen_ueg<W>(MULTI ? sy.u : lu, key, r0.x, r0.y, child[it], pgen, hv);
+                    ok = gen_ueg<W>(LT ? lu : sy.u, key, r0.x, r0.y, child[it], pgen, hv);
                 else
                     ok = gen_heatbath<W>(sy, rp.p_single, key, r0, (uint32_t)k, t, h, rp.k0, rp.k1, child[it], pgen, hv);
                 if (ok && hv != 0.0) {
@@ -467,8 +513,16 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                             m = (rp.tau * ah) / pgen;
                         else
                             m = (((rp.tau * ah) / pgen) * (double)an) / (double)nat;
-                        const U4 rr = draw(TAG_SPAWN_ROUND, (uint32_t)k, t, h, rp.k0, rp.k1);
-                        const double u = u53(rr.x, rr.y);
+                        // the Hubbard and electron-gas generators leave the last two
+                        // words of the selection block unused: they give the
+                        // rounding uniform; heat-bath uses a block of its own
+                        double u;
+                        if constexpr (KIND == K_MOLECULAR) {
+                            const U4 rr = draw(TAG_SPAWN_ROUND, (uint32_t)k, t, h, rp.k0, rp.k1);
+                            u = u53(rr.x, rr.y);
+                        } else {
+                            u = u53(r0.z, r0.w);
+                        }
                         long long kk = 0;
                         if (!(m < 0x1p31)) {
                             atomicOr(&c->err, ERR_OVERFLOW);
@@ -508,16 +562,23 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
             const long long lb_ = lookback(w.st_spawn, span, epoch, (long long)tot);
             if (threadIdx.x == 0) s_base = lb_;
         }
+        uint32_t rk[SP_I];
+        uint64_t csk[SP_I];
 #pragma unroll
         for (int it = 0; it < SP_I; ++it) {
             const uint64_t m = __ballot(has[it]);
+            rk[it] = before[it] + (uint32_t)__popcll(m & lanemask_lt());
+            csk[it] = 0;
             if (has[it]) {
-                const uint32_t r = before[it] + (uint32_t)__popcll(m & lanemask_lt());
-                s_rk[r] = make_skey(hash64<W>(child[it]), rep[it], w.rb);
+                csk[it] = make_skey(hash64<W>(child[it]), rep[it], w.rb);
+                const uint32_t r = rk[it];
+                if (r < SP_STAGE) {
+                    s_rk[r] = csk[it];
 #pragma unroll
-                for (int q = 0; q < W; ++q) s_rkey[q][r] = child[it][q];
-                s_ramp[r] = amp[it];
-                s_rinit[r] = init[it];
+                    for (int q = 0; q < W; ++q) s_rkey[q][r] = child[it][q];
+                    s_ramp[r] = amp[it];
+                    s_rinit[r] = init[it];
+                }
             }
         }
         __syncthreads();
@@ -525,7 +586,8 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
         if (base + tot > w.spawn_cap) {
             if (threadIdx.x == 0) atomicOr(&c->err, ERR_SPAWN_CAP);
         } else {
-            for (uint32_t p = threadIdx.x; p < tot; p += SP_T) {
+            const uint32_t ns = tot < SP_STAGE ? tot : SP_STAGE;
+            for (uint32_t p = threadIdx.x; p < ns; p += SP_T) {
                 const long long o = base + p;
                 w.sp.skey[o] = s_rk[p];
                 uint64_t *rec = w.sp.rec + (size_t)o * (W + 1);
@@ -535,6 +597,18 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 w.u.sum[o] = 0;
                 w.u.flag[o] = 0;
             }
+#pragma unroll
+            for (int it = 0; it < SP_I; ++it)
+                if (has[it] && rk[it] >= SP_STAGE) {
+                    const long long o = base + rk[it];
+                    w.sp.skey[o] = csk[it];
+                    uint64_t *rec = w.sp.rec + (size_t)o * (W + 1);
+#pragma unroll
+                    for (int q = 0; q < W; ++q) rec[q] = child[it][q];
+                    rec[W] = (uint64_t)(uint32_t)amp[it] | ((uint64_t)init[it] << 32);
+                    w.u.sum[o] = 0;
+                    w.u.flag[o] = 0;
+                }
         }
         if (span == nspans - 1 && threadIdx.x == 0) c->n_spawn = (unsigned long long)(base + tot);
         __syncthreads();
@@ -900,9 +974,12 @@ __global__ void k_fixup(Work w)
 // slot, and the kept entries leave in merge order with coalesced stores.
 // ---------------------------------------------------------------------------
 constexpr int MG_T = 256;
+#ifndef FQ_MERGE_ITEMS
+#define FQ_MERGE_ITEMS 4  // merge positions per thread and tile, keys of up to two words
+#endif
 template <int W>
 struct MergeCfg {
-    static constexpr int I = W <= 2 ? 4 : 2;
+    static constexpr int I = W <= 2 ? FQ_MERGE_ITEMS : 2;
     static constexpr int TILE = MG_T * I;
 };
 
@@ -1508,17 +1585,21 @@ __global__ void k_split_planes(Work w)
 }
 
 // explicit instantiations
-#define FQ_INST(KIND, W)                                   \
-    template __global__ void k_new_diag<KIND, W>(Work);     \
-    template __global__ void k_spawn<KIND, W, false>(Work); \
-    template __global__ void k_spawn<KIND, W, true>(Work);  \
-    template __global__ void k_merge<KIND, W, false>(Work); \
+#define FQ_INST(KIND, W)                                          \
+    template __global__ void k_new_diag<KIND, W>(Work);            \
+    template __global__ void k_spawn<KIND, W, false, false>(Work); \
+    template __global__ void k_spawn<KIND, W, true, false>(Work);  \
+    template __global__ void k_merge<KIND, W, false>(Work);        \
     template __global__ void k_merge<KIND, W, true>(Work);
 FQ_INST(K_HUBBARD, 1)
 FQ_INST(K_UEG, 1)
 FQ_INST(K_UEG, 2)
 FQ_INST(K_UEG, 4)
 FQ_INST(K_UEG, 8)
+template __global__ void k_spawn<K_UEG, 1, false, true>(Work);
+template __global__ void k_spawn<K_UEG, 2, false, true>(Work);
+template __global__ void k_spawn<K_UEG, 4, false, true>(Work);
+template __global__ void k_spawn<K_UEG, 8, false, true>(Work);
 FQ_INST(K_MOLECULAR, 1)
 FQ_INST(K_MOLECULAR, 2)
 #define FQ_INSTW(W)                                        \
@@ -1622,9 +1703,11 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     k_spawn_partition<<<g.part, 256, 0, s>>>(w);
     rec();
     if (w.R > 1)
-        k_spawn<KIND, W, true><<<g.spawn, SP_T, 0, s>>>(w);
+        k_spawn<KIND, W, true, false><<<g.spawn, SP_T, 0, s>>>(w);
+    else if (KIND == K_UEG && w.lds_tables > 0)
+        k_spawn<KIND, W, false, KIND == K_UEG><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
     else
-        k_spawn<KIND, W, false><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
+        k_spawn<KIND, W, false, false><<<g.spawn, SP_T, 0, s>>>(w);
     rec();
     k_sort_hist<<<g.hist, 256, 0, s>>>(w);
     rec();
@@ -1720,7 +1803,7 @@ int occupancy_blocks(int which)
     case 1: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false>, MG_T, 0); break;
     case 2: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce<2>, RD_T, 0); break;
     case 3: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan_attempts, SCAN_T, 0); break;
-    case 4: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false>, SP_T, 16384); break;
+    case 4: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false, true>, SP_T, 8192); break;
     default: break;
     }
     return nb < 1 ? 1 : nb;

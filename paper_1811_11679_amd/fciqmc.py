@@ -22,9 +22,9 @@ SS_FP64, SS_SPLIT_BF16 = 0, 1
 
 # every function the header declares
 C_API = ["fq_workspace_bytes", "fq_init_system", "fq_step", "fq_estimators", "fq_estimator_history",
-         "fq_export_walkers", "fq_import_walkers", "fq_export_spawns", "fq_detspace", "fq_info",
-         "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_set_graph", "fq_set_launch", "fq_shift_state",
-         "fq_get_launch", "fq_last_error", "fq_destroy"]
+         "fq_export_walkers", "fq_import_walkers", "fq_shift_state", "fq_export_spawns", "fq_detspace", "fq_info",
+         "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_iteration_times", "fq_set_graph",
+         "fq_set_launch", "fq_get_launch", "fq_last_error", "fq_destroy"]
 LAUNCH_KERNELS = ["spawn", "merge", "sort", "reduce", "new_diag"]
 
 KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "sort_hist"] + \
@@ -116,6 +116,8 @@ def load_library():
     L.fq_kernel_times.argtypes = [P, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int64)]
     L.fq_kernel_times.restype = C.c_int32
+    L.fq_iteration_times.argtypes = [P, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64)]
+    L.fq_iteration_times.restype = C.c_int32
     L.fq_shift_state.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int32)]
     L.fq_shift_state.restype = C.c_int32
@@ -303,6 +305,13 @@ class Context:
         self._check(self.lib.fq_stage_times(self.ctx, arr))
         names = ["scan", "spawn", "sort", "reduce", "merge", "detproj", "iteration"]
         return dict(zip(names, list(arr)))
+
+    def iteration_times(self, cap=1 << 20):
+        """device ms of each iteration of the last timed step call"""
+        arr = (C.c_double * cap)()
+        n = C.c_int64()
+        self._check(self.lib.fq_iteration_times(self.ctx, arr, cap, C.byref(n)))
+        return list(arr[: n.value])
 
     def kernel_times(self):
         """{slot name: summed ms}, and the number of timed iterations"""
