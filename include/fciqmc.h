@@ -115,6 +115,12 @@ typedef struct {
                              projection is also computed and the largest error
                              of the split result, relative to sum_j |K_ij||c_j|,
                              is reported in fq_estimators_t.ss_error (0: never) */
+    int32_t shared;       /* 0: each instance selects its own D. 1: one D for all
+                             instances (all must describe the same system): the
+                             size determinants of largest summed |n| over the
+                             instances (key ascending on ties), present in every
+                             instance's list (with n = 0 where unoccupied), so that
+                             K_DD C over all instances is one matrix product */
 } fq_semistoch;
 
 /* Estimators of one iteration of one instance (tutorial appendix: shift,

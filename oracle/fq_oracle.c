@@ -893,6 +893,53 @@ static int top_cmp(const void *a, const void *b)
     return key_cmp(r->keys + (size_t)i * r->W, r->keys + (size_t)j * r->W, r->W);
 }
 
+/* D given as nd keys in D order: mark the entries, build K_DD and the sorted
+   copy used for membership tests. Every key must be in the list. */
+static void install_detspace(or_run *r, const uint64_t *dkeys, int64_t nd)
+{
+    int W = r->W;
+    r->nd = nd;
+    r->dkeys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nd ? nd : 1) * W);
+    r->kdd = (double *)malloc(sizeof(double) * (size_t)(nd ? nd * nd : 1));
+    r->last_y = (double *)calloc((size_t)(nd ? nd : 1), sizeof(double));
+    memcpy(r->dkeys, dkeys, sizeof(uint64_t) * (size_t)nd * W);
+    int64_t *at = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd ? nd : 1));
+    for (int64_t d = 0; d < nd; ++d) {
+        /* the list is sorted by key */
+        int64_t lo = 0, hi = r->n;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (key_cmp(r->keys + (size_t)mid * W, dkeys + (size_t)d * W, W) < 0) lo = mid + 1; else hi = mid;
+        }
+        at[d] = lo;
+        r->dslot[lo] = (int32_t)d;
+    }
+    for (int64_t d = 0; d < nd; ++d)
+        for (int64_t e = 0; e < nd; ++e) {
+            double v;
+            if (d == e)
+                v = r->kdiag[at[d]];
+            else
+                v = or_hij(r->s, r->dkeys + (size_t)d * W, r->dkeys + (size_t)e * W);
+            r->kdd[d * nd + e] = v;
+        }
+    free(at);
+    /* sorted copy for membership tests */
+    g_sort.keys = r->dkeys;
+    g_sort.W = W;
+    int64_t *sx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd ? nd : 1));
+    for (int64_t d = 0; d < nd; ++d) sx[d] = d;
+    qsort(sx, (size_t)nd, sizeof(int64_t), idx_cmp);
+    r->dsorted = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nd ? nd : 1) * W);
+    r->dsorted_ix = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nd ? nd : 1));
+    for (int64_t d = 0; d < nd; ++d) {
+        memcpy(r->dsorted + (size_t)d * W, r->dkeys + (size_t)sx[d] * W, sizeof(uint64_t) * W);
+        r->dsorted_ix[d] = (int32_t)sx[d];
+    }
+    free(sx);
+    r->ss_active = 1;
+}
+
 static void select_detspace(or_run *r)
 {
     int64_t nd = r->q.ss_size < r->n ? r->q.ss_size : r->n;
@@ -901,38 +948,116 @@ static void select_detspace(or_run *r)
     for (int64_t i = 0; i < r->n; ++i) ix[i] = i;
     g_top.r = r;
     qsort(ix, (size_t)r->n, sizeof(int64_t), top_cmp);
-    r->nd = nd;
-    r->dkeys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nd ? nd : 1) * r->W);
-    r->kdd = (double *)malloc(sizeof(double) * (size_t)(nd ? nd * nd : 1));
-    r->last_y = (double *)calloc((size_t)(nd ? nd : 1), sizeof(double));
-    for (int64_t d = 0; d < nd; ++d) {
-        memcpy(r->dkeys + (size_t)d * r->W, r->keys + (size_t)ix[d] * r->W, sizeof(uint64_t) * r->W);
-        r->dslot[ix[d]] = (int32_t)d;
-    }
-    for (int64_t d = 0; d < nd; ++d)
-        for (int64_t e = 0; e < nd; ++e) {
-            double v;
-            if (d == e)
-                v = r->kdiag[ix[d]];
-            else
-                v = or_hij(r->s, r->dkeys + (size_t)d * r->W, r->dkeys + (size_t)e * r->W);
-            r->kdd[d * nd + e] = v;
-        }
-    /* sorted copy for membership tests */
-    g_sort.keys = r->dkeys;
-    g_sort.W = r->W;
-    int64_t *sx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nd ? nd : 1));
-    for (int64_t d = 0; d < nd; ++d) sx[d] = d;
-    qsort(sx, (size_t)nd, sizeof(int64_t), idx_cmp);
-    r->dsorted = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nd ? nd : 1) * r->W);
-    r->dsorted_ix = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nd ? nd : 1));
-    for (int64_t d = 0; d < nd; ++d) {
-        memcpy(r->dsorted + (size_t)d * r->W, r->dkeys + (size_t)sx[d] * r->W, sizeof(uint64_t) * r->W);
-        r->dsorted_ix[d] = (int32_t)sx[d];
-    }
-    free(sx);
+    uint64_t *dk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nd ? nd : 1) * r->W);
+    for (int64_t d = 0; d < nd; ++d) memcpy(dk + (size_t)d * r->W, r->keys + (size_t)ix[d] * r->W, sizeof(uint64_t) * r->W);
     free(ix);
-    r->ss_active = 1;
+    install_detspace(r, dk, nd);
+    free(dk);
+}
+
+/* ---- one deterministic space shared by several runs of one system ---- */
+typedef struct { const uint64_t *key; int64_t sum; } tot_t;
+static int g_tot_w;
+static int tot_key_cmp(const void *a, const void *b)
+{
+    return key_cmp(((const tot_t *)a)->key, ((const tot_t *)b)->key, g_tot_w);
+}
+static int tot_rank_cmp(const void *a, const void *b)
+{
+    const tot_t *x = (const tot_t *)a, *y = (const tot_t *)b;
+    if (x->sum != y->sum) return x->sum > y->sum ? -1 : 1;
+    return key_cmp(x->key, y->key, g_tot_w);
+}
+
+/* insert the given keys (sorted, absent from the list) with n = 0 */
+static void insert_zero_entries(or_run *r, const uint64_t *add, int64_t na)
+{
+    int W = r->W;
+    int64_t n = r->n, tot = n + na;
+    uint64_t *nk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(tot ? tot : 1) * W);
+    int32_t *np = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tot ? tot : 1));
+    double *nkd = (double *)malloc(sizeof(double) * (size_t)(tot ? tot : 1));
+    int32_t *nds = (int32_t *)malloc(sizeof(int32_t) * (size_t)(tot ? tot : 1));
+    int64_t i = 0, j = 0, o = 0;
+    while (i < n || j < na) {
+        int take_old = j >= na || (i < n && key_cmp(r->keys + (size_t)i * W, add + (size_t)j * W, W) < 0);
+        if (take_old) {
+            memcpy(nk + (size_t)o * W, r->keys + (size_t)i * W, sizeof(uint64_t) * W);
+            np[o] = r->pops[i];
+            nkd[o] = r->kdiag[i];
+            nds[o] = r->dslot[i];
+            ++i;
+        } else {
+            memcpy(nk + (size_t)o * W, add + (size_t)j * W, sizeof(uint64_t) * W);
+            np[o] = 0;
+            nkd[o] = or_diag(r->s, add + (size_t)j * W) - r->s->H00;
+            nds[o] = -1;
+            ++j;
+        }
+        ++o;
+    }
+    free(r->keys); free(r->pops); free(r->kdiag); free(r->dslot);
+    r->keys = nk; r->pops = np; r->kdiag = nkd; r->dslot = nds;
+    r->n = tot;
+    r->cap = tot;
+}
+
+int or_runs_select_shared(or_run **runs, int nr)
+{
+    if (nr <= 0) return OR_EINVAL;
+    int W = runs[0]->W;
+    int64_t size = runs[0]->q.ss_size, total = 0;
+    for (int k = 0; k < nr; ++k) total += runs[k]->n;
+    /* summed |n| over the runs of every occupied determinant */
+    tot_t *all = (tot_t *)malloc(sizeof(tot_t) * (size_t)(total ? total : 1));
+    int64_t m = 0;
+    for (int k = 0; k < nr; ++k)
+        for (int64_t i = 0; i < runs[k]->n; ++i) {
+            all[m].key = runs[k]->keys + (size_t)i * W;
+            all[m].sum = runs[k]->pops[i] < 0 ? -(int64_t)runs[k]->pops[i] : runs[k]->pops[i];
+            ++m;
+        }
+    g_tot_w = W;
+    qsort(all, (size_t)m, sizeof(tot_t), tot_key_cmp);
+    int64_t u = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        if (u > 0 && key_cmp(all[u - 1].key, all[i].key, W) == 0)
+            all[u - 1].sum += all[i].sum;
+        else
+            all[u++] = all[i];
+    }
+    if (u < size) { free(all); return OR_EINVAL; }
+    qsort(all, (size_t)u, sizeof(tot_t), tot_rank_cmp);
+    uint64_t *dk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(size ? size : 1) * W);
+    for (int64_t d = 0; d < size; ++d) memcpy(dk + (size_t)d * W, all[d].key, sizeof(uint64_t) * W);
+    free(all);
+    /* sorted copy of D, for the members a run does not hold */
+    int64_t *sx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(size ? size : 1));
+    for (int64_t d = 0; d < size; ++d) sx[d] = d;
+    g_sort.keys = dk;
+    g_sort.W = W;
+    qsort(sx, (size_t)size, sizeof(int64_t), idx_cmp);
+    uint64_t *add = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(size ? size : 1) * W);
+    for (int k = 0; k < nr; ++k) {
+        or_run *r = runs[k];
+        int64_t na = 0;
+        for (int64_t x = 0; x < size; ++x) {
+            const uint64_t *key = dk + (size_t)sx[x] * W;
+            int64_t lo = 0, hi = r->n;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) / 2;
+                if (key_cmp(r->keys + (size_t)mid * W, key, W) < 0) lo = mid + 1; else hi = mid;
+            }
+            if (lo == r->n || key_cmp(r->keys + (size_t)lo * W, key, W) != 0)
+                memcpy(add + (size_t)(na++) * W, key, sizeof(uint64_t) * W);
+        }
+        if (na) insert_zero_entries(r, add, na);
+        install_detspace(r, dk, size);
+    }
+    free(add);
+    free(sx);
+    free(dk);
+    return OR_OK;
 }
 
 static int step_once(or_run *r)
@@ -1099,7 +1224,7 @@ static int step_once(or_run *r)
         r->est.vary_shift = r->vary;
     }
     /* deterministic space chosen from the most highly weighted determinants */
-    if (r->q.ss_size > 0 && !r->ss_active && r->t >= r->q.ss_start_iteration) select_detspace(r);
+    if (r->q.ss_size > 0 && !r->q.ss_shared && !r->ss_active && r->t >= r->q.ss_start_iteration) select_detspace(r);
     return OR_OK;
 }
 
@@ -1158,7 +1283,7 @@ int or_run_import(or_run *r, const uint64_t *keys, const int32_t *pops, int64_t 
     r->ss_active = 0;
     r->nd = 0;
     compute_estimators(r);
-    if (r->q.ss_size > 0 && r->t >= r->q.ss_start_iteration) select_detspace(r);
+    if (r->q.ss_size > 0 && !r->q.ss_shared && r->t >= r->q.ss_start_iteration) select_detspace(r);
     return OR_OK;
 }
 

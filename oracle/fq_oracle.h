@@ -57,6 +57,7 @@ typedef struct {
     double spawn_cutoff;        /* walkers, real mode only */
     int32_t ss_size;            /* 0: no semi-stochastic */
     int32_t ss_start_iteration;
+    int32_t ss_shared;          /* 1: D chosen jointly with other runs (or_runs_select_shared) */
 } or_qmc;
 
 /* estimators of the last completed iteration */
@@ -94,6 +95,10 @@ int or_exgen(const or_sys *s, int exgen, double p_single, const uint64_t *key,
 or_run *or_run_new(const or_sys *s, const or_qmc *q);
 void or_run_free(or_run *r);
 int or_run_step(or_run *r, int n_iter);
+/* one deterministic space for several runs of one system (qmc.ss_shared = 1):
+   the ss_size determinants of largest sum over the runs of |n| (key ascending
+   on ties), inserted with n = 0 where a run does not hold them */
+int or_runs_select_shared(or_run **runs, int n_runs);
 void or_run_estimators(const or_run *r, or_estimators *out);
 int64_t or_run_size(const or_run *r);
 void or_run_export(const or_run *r, uint64_t *keys, int32_t *pops);

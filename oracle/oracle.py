@@ -38,7 +38,7 @@ class Qmc(C.Structure):
                 ("p_single", C.c_double), ("initiator", C.c_int32),
                 ("initiator_threshold", C.c_double), ("fixed_point_bits", C.c_int32),
                 ("spawn_cutoff", C.c_double), ("ss_size", C.c_int32),
-                ("ss_start_iteration", C.c_int32)]
+                ("ss_start_iteration", C.c_int32), ("ss_shared", C.c_int32)]
 
 
 class Estimators(C.Structure):
@@ -98,6 +98,8 @@ def lib():
         L.or_run_free.argtypes = [P]
         L.or_run_step.argtypes = [P, C.c_int]
         L.or_run_step.restype = C.c_int
+        L.or_runs_select_shared.argtypes = [C.POINTER(P), C.c_int]
+        L.or_runs_select_shared.restype = C.c_int
         L.or_run_estimators.argtypes = [P, C.POINTER(Estimators)]
         L.or_run_size.argtypes = [P]
         L.or_run_size.restype = C.c_int64
@@ -192,7 +194,7 @@ def make_qmc(**kw) -> Qmc:
     d = dict(tau=0.01, seed=7, replica_id=0, init_pop=500.0, target_population=1e4,
              shift_period=10, shift_damping=0.05, initial_shift=0.0, excit_gen=EXGEN_HUB,
              p_single=0.1, initiator=0, initiator_threshold=3.0, fixed_point_bits=0,
-             spawn_cutoff=0.0, ss_size=0, ss_start_iteration=0)
+             spawn_cutoff=0.0, ss_size=0, ss_start_iteration=0, ss_shared=0)
     d.update(kw)
     return Qmc(**d)
 
@@ -255,3 +257,24 @@ class Run:
         y = np.zeros(max(n, 1), np.float64)
         lib().or_run_last_projection(self.ptr, y)
         return y[:n]
+
+
+def select_shared(runs):
+    """Choose one deterministic space for runs of one system (qmc.ss_shared = 1)
+    from their current lists."""
+    arr = (C.c_void_p * len(runs))(*[r.ptr for r in runs])
+    st = lib().or_runs_select_shared(arr, len(runs))
+    if st:
+        raise RuntimeError(f"shared deterministic space selection failed with status {st}")
+
+
+def step_shared(runs, n):
+    """Advance runs that share one deterministic space (qmc.ss_shared = 1) by n
+    iterations: each iteration steps every run, and at the end of iteration
+    ss_start_iteration D is chosen jointly over the runs."""
+    for _ in range(n):
+        for r in runs:
+            r.step(1)
+        q = runs[0].qmc
+        if q.ss_size > 0 and runs[0].estimators()["iteration"] == q.ss_start_iteration:
+            select_shared(runs)

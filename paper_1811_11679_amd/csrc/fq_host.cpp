@@ -237,10 +237,22 @@ struct Layout {
 
 int64_t tiles_of(int64_t n, int64_t tile) { return (n + tile - 1) / tile + 1; }
 
+// two descriptions of the same Hamiltonian (integral arrays compared by value)
+bool same_system(const fq_system &a, const fq_system &b)
+{
+    if (a.kind != b.kind || a.n_alpha != b.n_alpha || a.n_beta != b.n_beta) return false;
+    if (a.kind == FQ_HUBBARD_REAL)
+        return a.n_sites == b.n_sites && a.periodic == b.periodic && a.t == b.t && a.U == b.U;
+    if (a.kind == FQ_UEG) return a.rs == b.rs && a.ecut_n2 == b.ecut_n2;
+    if (a.n_orb != b.n_orb || !a.h1 || !b.h1 || !a.eri || !b.eri) return false;
+    const size_t n2 = (size_t)a.n_orb * a.n_orb;
+    return std::memcmp(a.h1, b.h1, 8 * n2) == 0 && std::memcmp(a.eri, b.eri, 8 * n2 * n2) == 0;
+}
+
 // spans of 256 attempts the attempt partition can hold
 int64_t span_capacity(int64_t mcap, int64_t scap) { return tiles_of(std::max(mcap * 16, scap * 4), SPAN); }
 
-Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D)
+Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D, int nk)
 {
     Layout L;
     size_t o = 0;
@@ -288,9 +300,9 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.u[3] = take(4 * (size_t)scap);
     const size_t nd = (size_t)D * R;
     const size_t np = (size_t)((D + 15) / 16) * 16;
-    L.ds[0] = take(8 * nd * (size_t)D);  // K fp64
-    L.ds[1] = take(2 * (size_t)R * np * np);  // K hi bf16
-    L.ds[2] = take(2 * (size_t)R * np * np);  // K lo bf16
+    L.ds[0] = take(8 * (size_t)nk * D * (size_t)D);  // K fp64
+    L.ds[1] = take(2 * (size_t)nk * np * np);        // K hi bf16
+    L.ds[2] = take(2 * (size_t)nk * np * np);        // K lo bf16
     L.ds[3] = take(4 * nd);              // pos
     L.ds[4] = take(8 * nd);              // h64
     L.ds[5] = take(8 * nd);              // c
@@ -552,31 +564,84 @@ fq_status select_detspace(fq_ctx *c)
     const size_t nd = (size_t)D * R;
     std::vector<int32_t> pos(nd, 0);
     std::vector<uint64_t> h64(nd, 0), dk(nd * W, 0);
-    c->dkeys.assign(R, std::vector<uint64_t>());
-    for (int r = 0; r < R; ++r) {
-        std::vector<int64_t> ix;
-        for (int64_t i = 0; i < n; ++i) {
-            const uint32_t rep = c->rb ? (uint32_t)(e[i].skey >> (64 - c->rb)) : 0u;
-            if ((int)rep == r) ix.push_back(i);
+    c->dkeys.assign(R, std::vector<uint64_t>((size_t)D * W, 0));
+    auto rep_of = [&](const HostEntry &x) { return c->rb ? (uint32_t)(x.skey >> (64 - c->rb)) : 0u; };
+    if (!c->ss.shared) {
+        // each replica: its D most highly weighted determinants
+        for (int r = 0; r < R; ++r) {
+            std::vector<int64_t> ix;
+            for (int64_t i = 0; i < n; ++i)
+                if ((int)rep_of(e[i]) == r) ix.push_back(i);
+            if ((int64_t)ix.size() < D)
+                return fail(c, FQ_ESTATE, "fewer occupied determinants than the deterministic space size");
+            std::sort(ix.begin(), ix.end(), [&](int64_t a, int64_t b) {
+                const long long pa = std::llabs((long long)e[a].pop), pb = std::llabs((long long)e[b].pop);
+                if (pa != pb) return pa > pb;
+                return key_cmp_host(e[a].key, e[b].key, W) < 0;
+            });
+            for (int d = 0; d < D; ++d)
+                for (int q = 0; q < W; ++q) c->dkeys[r][(size_t)d * W + q] = e[ix[d]].key[q];
         }
-        if ((int64_t)ix.size() < D) return fail(c, FQ_ESTATE, "fewer occupied determinants than the deterministic space size");
-        std::sort(ix.begin(), ix.end(), [&](int64_t a, int64_t b) {
-            const long long pa = std::llabs((long long)e[a].pop), pb = std::llabs((long long)e[b].pop);
-            if (pa != pb) return pa > pb;
-            return key_cmp_host(e[a].key, e[b].key, W) < 0;
+    } else {
+        // one D for all replicas: largest summed |n| over the replicas, key
+        // ascending on ties
+        std::vector<int64_t> ix(n);
+        std::iota(ix.begin(), ix.end(), 0);
+        std::sort(ix.begin(), ix.end(), [&](int64_t a, int64_t b) { return key_cmp_host(e[a].key, e[b].key, W) < 0; });
+        std::vector<std::pair<int64_t, int64_t>> tot;  // (summed |n|, entry holding the key)
+        for (int64_t x = 0; x < n; ++x) {
+            const int64_t i = ix[x];
+            const int64_t a = std::llabs((long long)e[i].pop);
+            if (!tot.empty() && key_cmp_host(e[tot.back().second].key, e[i].key, W) == 0)
+                tot.back().first += a;
+            else
+                tot.push_back({a, i});
+        }
+        if ((int64_t)tot.size() < D)
+            return fail(c, FQ_ESTATE, "fewer occupied determinants than the deterministic space size");
+        std::sort(tot.begin(), tot.end(), [&](const std::pair<int64_t, int64_t> &a, const std::pair<int64_t, int64_t> &b) {
+            if (a.first != b.first) return a.first > b.first;
+            return key_cmp_host(e[a.second].key, e[b.second].key, W) < 0;
         });
-        c->dkeys[r].resize((size_t)D * W);
-        for (int d = 0; d < D; ++d) {
-            const int64_t i = ix[d];
-            e[i].dslot = d;
-            pos[(size_t)r * D + d] = (int32_t)i;
-            h64[(size_t)r * D + d] = host_hash(e[i].key, W);
-            for (int q = 0; q < W; ++q) {
-                dk[(size_t)q * nd + (size_t)r * D + d] = e[i].key[q];
-                c->dkeys[r][(size_t)d * W + q] = e[i].key[q];
+        for (int r = 0; r < R; ++r)
+            for (int d = 0; d < D; ++d)
+                for (int q = 0; q < W; ++q) c->dkeys[r][(size_t)d * W + q] = e[tot[d].second].key[q];
+        // every replica holds every member: the missing ones enter with n = 0
+        std::vector<HostEntry> add;
+        for (int r = 0; r < R; ++r)
+            for (int d = 0; d < D; ++d) {
+                HostEntry x;
+                std::memset(&x, 0, sizeof(x));
+                for (int q = 0; q < W; ++q) x.key[q] = c->dkeys[r][(size_t)d * W + q];
+                x.skey = host_skey(host_hash(x.key, W), (uint32_t)r, c->rb);
+                x.dslot = -1;
+                auto it = std::lower_bound(e.begin(), e.end(), x,
+                                           [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, W); });
+                if (it == e.end() || it->skey != x.skey || key_cmp_host(it->key, x.key, W) != 0) add.push_back(x);
             }
+        if (!add.empty()) {
+            if (n + (int64_t)add.size() > c->main_cap) return fail(c, FQ_ECAPACITY, "main list capacity exceeded");
+            e.insert(e.end(), add.begin(), add.end());
+            std::sort(e.begin(), e.end(), [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, W); });
+            n = (int64_t)e.size();
         }
     }
+    // slots and positions of the members in the (sorted) list
+    for (auto &x : e) x.dslot = -1;
+    for (int r = 0; r < R; ++r)
+        for (int d = 0; d < D; ++d) {
+            HostEntry x;
+            std::memset(&x, 0, sizeof(x));
+            for (int q = 0; q < W; ++q) x.key[q] = c->dkeys[r][(size_t)d * W + q];
+            x.skey = host_skey(host_hash(x.key, W), (uint32_t)r, c->rb);
+            auto it = std::lower_bound(e.begin(), e.end(), x,
+                                       [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, W); });
+            const int64_t i = it - e.begin();
+            e[i].dslot = d;
+            pos[(size_t)r * D + d] = (int32_t)i;
+            h64[(size_t)r * D + d] = host_hash(x.key, W);
+            for (int q = 0; q < W; ++q) dk[(size_t)q * nd + (size_t)r * D + d] = x.key[q];
+        }
     // sorted copy for membership tests
     std::vector<size_t> order(nd);
     std::iota(order.begin(), order.end(), 0);
@@ -600,11 +665,16 @@ fq_status select_detspace(fq_ctx *c)
         ssk[x] = sks[order[x]];
         for (int q = 0; q < W; ++q) skk[(size_t)q * nd + x] = dk[(size_t)q * nd + order[x]];
     }
-    // dslot of the current list
-    std::vector<int32_t> ds(n);
-    for (int64_t i = 0; i < n; ++i) ds[i] = e[i].dslot;
+    // dslot of the current list (with the members added to it, the whole list)
     const MainList &m = c->buf[c->cur];
-    if (n) HIPCHK(c, h2d(c->stream, m.dslot, ds.data(), 4 * n));
+    if (c->ss.shared) {
+        fq_status su = upload_main(c, e);
+        if (su) return su;
+    } else {
+        std::vector<int32_t> ds(n);
+        for (int64_t i = 0; i < n; ++i) ds[i] = e[i].dslot;
+        if (n) HIPCHK(c, h2d(c->stream, m.dslot, ds.data(), 4 * n));
+    }
     HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[3], pos.data(), 4 * nd));
     HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[4], h64.data(), 8 * nd));
     HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[8], ssk.data(), 8 * nd));
@@ -640,7 +710,8 @@ size_t fq_workspace_bytes(const fq_system *sys, const fq_qmc *qmc, const fq_semi
         W = std::max(W, round_w(s.n_so));
     }
     const int D = ss ? std::max(0, ss[0].size) : 0;
-    return make_layout(n_instances, W, main_capacity, spawn_capacity, tables, D).total + 256;
+    const int nk = ss && ss[0].shared ? 1 : n_instances;
+    return make_layout(n_instances, W, main_capacity, spawn_capacity, tables, D, nk).total + 256;
 }
 
 fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss,
@@ -689,9 +760,17 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         c->D = ss[0].size;
         if (ss[0].precision != FQ_SS_FP64 && ss[0].precision != FQ_SS_SPLIT_BF16) { delete c; return FQ_EINVAL; }
         for (int r = 1; r < c->R; ++r)
-            if (ss[r].size != ss[0].size || ss[r].start_iteration != ss[0].start_iteration) { delete c; return FQ_EINVAL; }
+            if (ss[r].size != ss[0].size || ss[r].start_iteration != ss[0].start_iteration ||
+                ss[r].shared != ss[0].shared)
+                { delete c; return FQ_EINVAL; }
+        if (ss[0].shared != 0 && ss[0].shared != 1) { delete c; return FQ_EINVAL; }
+        // one deterministic space for all instances needs one Hamiltonian
+        if (ss[0].shared)
+            for (int r = 1; r < c->R; ++r)
+                if (!same_system(sys[0], sys[r])) { delete c; return FQ_EINVAL; }
     }
-    c->L = make_layout(c->R, c->W, main_capacity, spawn_capacity, tables, c->D);
+    const int nk = c->has_ss && c->ss.shared ? 1 : c->R;
+    c->L = make_layout(c->R, c->W, main_capacity, spawn_capacity, tables, c->D, nk);
     if (ws_bytes < c->L.total || ((uintptr_t)d_workspace & 255)) { delete c; return FQ_EINVAL; }
     c->ws = (char *)d_workspace;
     Work &w = c->w;
@@ -726,6 +805,8 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.ds.K = (const double *)(c->ws + c->L.ds[0]);
     w.ds.npad = ((c->D + 15) / 16) * 16;
     w.ds.check_period = c->has_ss ? c->ss.check_period : 0;
+    w.ds.shared = c->has_ss ? c->ss.shared : 0;
+    w.ds.nk = nk;
     w.ds.Khi = (uint16_t *)(c->ws + c->L.ds[1]);
     w.ds.Klo = (uint16_t *)(c->ws + c->L.ds[2]);
     w.ds.Chi = (uint16_t *)(c->ws + c->L.ds[10]);

@@ -105,8 +105,10 @@ struct DetSpace {
     int32_t precision;
     int32_t npad;         // D rounded up to 16 (MFMA tiles)
     int32_t check_period; // split mode: FP64 check every check_period iterations
-    const double *K;      // [R][n][n] FP64 K_DD (replica-major)
-    uint16_t *Khi;        // bf16 planes [R][npad][npad], zero padded
+    int32_t shared;       // one D (and one K_DD) for all replicas
+    int32_t nk;           // number of K_DD matrices: 1 if shared, else R
+    const double *K;      // [nk][n][n] FP64 K_DD (replica-major)
+    uint16_t *Khi;        // bf16 planes [nk][npad][npad], zero padded
     uint16_t *Klo;
     uint16_t *Chi;        // bf16 planes of the amplitudes [R][npad]
     uint16_t *Clo;

@@ -1485,10 +1485,14 @@ __global__ __launch_bounds__(256) void k_det_project_fp64(Work w, int mode)
     const int n = w.ds.n;
     const int lane = lane_id();
     const long long rows = (long long)n * w.R;
-    for (long long row = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); row < rows;
-         row += (long long)gridDim.x * (blockDim.x >> 6)) {
-        const int rep = (int)(row / n), d = (int)(row % n);
-        const double *K = w.ds.K + ((size_t)rep * n + d) * n;
+    for (long long job = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); job < rows;
+         job += (long long)gridDim.x * (blockDim.x >> 6)) {
+        // shared space: the replicas of one row of K_DD are consecutive jobs
+        // (the row is read once from memory); the sum of every row is the same
+        const int rep = w.ds.shared ? (int)(job % w.R) : (int)(job / n);
+        const int d = w.ds.shared ? (int)(job / w.R) : (int)(job % n);
+        const long long row = (long long)rep * n + d;
+        const double *K = w.ds.K + ((size_t)(w.ds.shared ? 0 : rep) * n + d) * n;
         const double *cv = w.ds.c + (size_t)rep * n;
         double part = 0.0, pabs = 0.0;
         for (int j = lane; j < n; j += 64) {
@@ -1530,6 +1534,49 @@ __global__ __launch_bounds__(256) void k_det_project_split(Work w)
     const int n = w.ds.n, np = w.ds.npad;
     const int lane = lane_id();
     const int tiles = np / 16;
+    if (w.ds.shared) {
+        // one K_DD for every replica: Y = K C with the replicas as the 16
+        // columns of the B tile, so each A tile serves 16 replicas
+        const int cblocks = (w.R + 15) / 16;
+        const long long jobs = (long long)tiles * cblocks;
+        for (long long job = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); job < jobs;
+             job += (long long)gridDim.x * (blockDim.x >> 6)) {
+            const int rt = (int)(job / cblocks), cb = (int)(job % cblocks);
+            const int arow = rt * 16 + (lane & 15);
+            const int kq = 4 * (lane >> 4);
+            const int rep = cb * 16 + (lane & 15);  // this lane's column of B and D
+            const bool bval = rep < w.R;
+            const uint16_t *kh = w.ds.Khi + (size_t)arow * np + kq;
+            const uint16_t *kl = w.ds.Klo + (size_t)arow * np + kq;
+            const uint16_t *ch = w.ds.Chi + (size_t)(bval ? rep : 0) * np + kq;
+            const uint16_t *cl = w.ds.Clo + (size_t)(bval ? rep : 0) * np + kq;
+            f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+            for (int kk = 0; kk < np; kk += 16) {
+                const bf16x4_t ah = *(const bf16x4_t *)(kh + kk);
+                const bf16x4_t al = *(const bf16x4_t *)(kl + kk);
+                bf16x4_t bh = {0, 0, 0, 0}, bl = {0, 0, 0, 0};
+                if (bval) {
+                    bh = *(const bf16x4_t *)(ch + kk);
+                    bl = *(const bf16x4_t *)(cl + kk);
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+            }
+            // lane holds rows 4 (lane / 16) + i of column lane % 16
+            if (bval) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int d = rt * 16 + 4 * (lane >> 4) + i;
+                    if (d < n) {
+                        const long long row = (long long)rep * n + d;
+                        det_update(w, c, rep, row, (double)acc[i], w.ds.c[row]);
+                    }
+                }
+            }
+        }
+        return;
+    }
     const long long jobs = (long long)tiles * w.R;
     for (long long job = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); job < jobs;
          job += (long long)gridDim.x * (blockDim.x >> 6)) {
@@ -1572,7 +1619,7 @@ __global__ __launch_bounds__(256) void k_det_project_split(Work w)
 __global__ void k_split_planes(Work w)
 {
     const int n = w.ds.n, np = w.ds.npad;
-    const long long tot = (long long)w.R * np * np;
+    const long long tot = (long long)w.ds.nk * np * np;
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < tot; x += (long long)gridDim.x * blockDim.x) {
         const int r = (int)(x / ((long long)np * np));
         const int i = (int)((x / np) % np), j = (int)(x % np);
@@ -1653,7 +1700,7 @@ __global__ void k_build_kdd(Work w, const uint64_t *dkeys /* [W][R*n] */, double
 {
     const int n = w.ds.n;
     const int nd = n * w.R;
-    const long long tot = (long long)w.R * n * n;
+    const long long tot = (long long)w.ds.nk * n * n;  // shared space: replica 0's keys (the same for all)
     for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < tot; x += (long long)gridDim.x * blockDim.x) {
         const int rep = (int)(x / ((long long)n * n));
         const int d = (int)((x / n) % n), e = (int)(x % n);

@@ -56,7 +56,7 @@ class Qmc(C.Structure):
 
 class SemiStoch(C.Structure):
     _fields_ = [("size", C.c_int32), ("start_iteration", C.c_int32), ("precision", C.c_int32),
-                ("check_period", C.c_int32)]
+                ("check_period", C.c_int32), ("shared", C.c_int32)]
 
 
 class Estimators(C.Structure):

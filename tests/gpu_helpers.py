@@ -28,7 +28,8 @@ def oracle_qmc(sysd, q, replica=0, ss=None):
                       excit_gen=k, p_single=q.get("p_single", 0.1), initiator=q.get("initiator", 0),
                       initiator_threshold=q.get("initiator_threshold", 3.0),
                       fixed_point_bits=q.get("fixed_point_bits", 0), spawn_cutoff=q.get("spawn_cutoff", 0.0),
-                      ss_size=ss["size"] if ss else 0, ss_start_iteration=ss["start_iteration"] if ss else 0)
+                      ss_size=ss["size"] if ss else 0, ss_start_iteration=ss["start_iteration"] if ss else 0,
+                      ss_shared=ss.get("shared", 0) if ss else 0)
 
 
 def gpu_context(sysds, qs, ints=None, ss=None, main_capacity=1 << 21, spawn_capacity=1 << 21,
@@ -48,7 +49,8 @@ def gpu_context(sysds, qs, ints=None, ss=None, main_capacity=1 << 21, spawn_capa
     sso = None
     if ss:
         sso = F.SemiStoch(size=ss["size"], start_iteration=ss["start_iteration"],
-                          precision=ss.get("precision", F.SS_FP64), check_period=ss.get("check_period", 0))
+                          precision=ss.get("precision", F.SS_FP64), check_period=ss.get("check_period", 0),
+                          shared=ss.get("shared", 0))
     return F.Context(systems, qmcs, sso, main_capacity=main_capacity, spawn_capacity=spawn_capacity)
 
 
@@ -77,3 +79,23 @@ def assert_same_estimators(eg, eo, where=""):
         assert eg[f] == eo[f], f"{where}: estimator {f}: gpu {eg[f]} vs oracle {eo[f]}"
     pe, po = eg["proj_energy"], eo["proj_energy"]
     assert (np.isnan(pe) and np.isnan(po)) or pe == po, f"{where}: proj_energy {pe} vs {po}"
+
+
+def split_bound_check(system, dkeys, start_state, y_split, y_fp64, bound):
+    """Per row: |y_i - y_i(FP64)| <= bound * sum_j |K_ij| |c_j|, with K_DD from the
+    oracle's matrix elements and c the populations the projection read."""
+    keys, pops = start_state
+    cur = {tuple(int(x) for x in k): int(p) for k, p in zip(keys, pops)}
+    dl = [tuple(int(x) for x in k) for k in dkeys]
+    c = np.array([cur.get(k, 0) for k in dl], float)
+    h00 = system.H00
+    K = np.array([[system.diag(np.array(a, np.uint64)) - h00 if i == j else
+                   system.hij(np.array(a, np.uint64), np.array(b, np.uint64))
+                   for j, b in enumerate(dl)] for i, a in enumerate(dl)])
+    scale = np.abs(K) @ np.abs(c)
+    err = np.abs(y_split - y_fp64)
+    ok = scale > 0
+    ratio = np.max(err[ok] / scale[ok])
+    assert ratio <= bound, (ratio, bound)
+    assert np.all(err[~ok] == 0)
+    return ratio

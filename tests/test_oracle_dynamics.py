@@ -243,3 +243,67 @@ def test_export_import_resumes_chain(oracle_mod):
     kb, pb = b.export()
     assert np.array_equal(ka, kb) and np.array_equal(pa, pb)
     assert a.estimators()["shift"] == b.estimators()["shift"]
+
+
+def test_shared_deterministic_space_ranks_summed_population(oracle_mod):
+    """One D for several runs: the ss_size determinants of largest summed |n|
+    over the runs (key ascending on ties), present in every run afterwards;
+    checked by brute force on the lists exported just before the selection."""
+    O = oracle_mod
+    s = O.System.hubbard(n_sites=8, periodic=True, t=1.0, U=4.0, n_alpha=4, n_beta=4)
+    size, start = 500, 25
+    runs = [O.Run(s, O.make_qmc(tau=0.01, excit_gen=O.EXGEN_HUB, replica_id=r, init_pop=100.0 * (r + 1),
+                                initial_shift=-4.0, target_population=1e9, ss_size=size,
+                                ss_start_iteration=start, ss_shared=1)) for r in range(3)]
+    O.step_shared(runs, start - 1)
+    before = [dict(zip(map(lambda k: brute.words_int(k), r.export()[0]), r.export()[1])) for r in runs]
+    O.step_shared(runs, 1)
+    # the lists at the end of iteration `start` (the selection happens after it)
+    after = [{brute.words_int(k): int(p) for k, p in zip(*r.export())} for r in runs]
+    tot = {}
+    for lst in after:
+        for k, p in lst.items():
+            if p != 0:
+                tot[k] = tot.get(k, 0) + abs(p)
+    want = sorted(tot, key=lambda k: (-tot[k], k))[:size]
+    for r, lst in zip(runs, after):
+        got = [brute.words_int(k) for k in r.detspace()]
+        assert got == want
+        assert set(want) <= set(lst)  # members a run did not hold are present with n = 0
+    assert any(0 in [lst[k] for k in want] for lst in after)  # the case of an unoccupied member occurred
+    assert before  # lists existed before the selection
+    # the runs continue with the shared space; D entries stay in every list
+    O.step_shared(runs, 20)
+    for r in runs:
+        kd, _ = r.export()
+        assert set(want) <= {brute.words_int(k) for k in kd}
+
+
+def test_shared_full_space_reaches_exact_energy(oracle_mod):
+    """A shared D covering the whole space makes the projection of every run
+    exact: started from the ground state, the projected energy of each run
+    stays at E_0 of exact diagonalisation."""
+    O = oracle_mod
+    dets, Hb = brute.hubbard_matrix(6, 3, 3, 1.0, 2.0)
+    w, v = np.linalg.eigh(Hb)
+    e0, psi = w[0], v[:, 0]
+    s = O.System.hubbard(n_sites=6, periodic=True, t=1.0, U=2.0, n_alpha=3, n_beta=3)
+    psi = psi * np.sign(psi[dets.index(brute.words_int(s.ref))])
+    keys = np.stack([brute.key_words(d, 1) for d in dets])
+    runs = []
+    for r in range(2):
+        pops = np.round(psi / np.abs(psi).sum() * 2e5 * (r + 1)).astype(np.int32)
+        run = O.Run(s, O.make_qmc(tau=0.01, excit_gen=O.EXGEN_HUB, replica_id=r, initial_shift=e0 - s.H00,
+                                  target_population=1e12, ss_size=len(dets), ss_start_iteration=10, ss_shared=1))
+        run.import_walkers(keys, pops, shift=e0 - s.H00, iteration=10)
+        runs.append(run)
+    O.select_shared(runs)
+    assert all(len(r.detspace()) == len(dets) for r in runs)
+    ests = [[], []]
+    for _ in range(100):
+        O.step_shared(runs, 1)
+        for r, e in zip(runs, ests):
+            e.append(r.estimators())
+    for e in ests:
+        ep = np.mean([x["proj_numerator"] for x in e]) / np.mean([x["ref_pop_units"] for x in e])
+        assert abs(ep - (e0 - s.H00)) < 2e-3, (ep, e0 - s.H00)
