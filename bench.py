@@ -205,6 +205,96 @@ def run_batch64(args):
     print(json.dumps(out))
 
 
+def run_mol30(args):
+    """Semi-stochastic FCIQMC on the seeded molecular-like Hamiltonian (30
+    orbitals, 8 + 8 electrons, heat-bath doubles): D = 2000 most highly
+    weighted determinants (one space shared by the replicas when there are
+    several), total target 1e7 walkers split evenly over the replicas, the
+    projection in FP64 and in split BF16 x3 / FP32 on MFMA, each run from the
+    same start with the same keys."""
+    from paper_1811_11679_amd import fciqmc as F
+    from paper_1811_11679_amd import synth, workloads
+
+    R = args.replicas
+    w = workloads.MOL30
+    h1, eri = synth.molecular_integrals()
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
+    start = max(args.warmup - 300, 1)
+    tgt = 1e7 / R
+    results = {}
+    for prec in (F.SS_FP64, F.SS_SPLIT_BF16):
+        name = "fp64" if prec == F.SS_FP64 else "split_bf16x3"
+        sysd = F.make_system(F.MOLECULAR, n_orb=30, n_alpha=8, n_beta=8, h1=h1, eri=eri)
+        qs = [F.make_qmc(excit_gen=F.MOLECULAR, **dict(w["qmc"], target_population=tgt, init_pop=tgt / 20,
+                                                       replica_id=r)) for r in range(R)]
+        ss = F.SemiStoch(size=2000, start_iteration=start, precision=prec, check_period=10, shared=1 if R > 1 else 0)
+        ctx = F.Context([sysd] * R, qs, ss, main_capacity=args.main_capacity, spawn_capacity=args.spawn_capacity)
+        t0 = time.perf_counter()
+        done = 0
+        while done < args.warmup:
+            k = min(250, args.warmup - done)
+            ctx.step(k)
+            done += k
+            nw = sum(ctx.estimators(r)["n_walkers_units"] for r in range(R)) / 256.0
+            log(f"{name} warmup {done}: N_w {nw:.4g}, {time.perf_counter() - t0:.1f} s")
+        e0 = [ctx.estimators(r) for r in range(R)]
+        ctx.set_timing(True)
+        t1 = time.perf_counter()
+        ctx.step(args.steps)
+        ctx.stream.synchronize()
+        dt = time.perf_counter() - t1
+        kt, niter = ctx.kernel_times()
+        it_ms = sorted(ctx.iteration_times())
+        ctx.set_timing(False)
+        hists = [ctx.history(r) for r in range(R)]
+        upd = sum((e0[r]["n_walkers_units"] + sum(h["n_walkers_units"] for h in hists[r][:-1])) / 256.0
+                  for r in range(R))
+        errs = [h["ss_error"] for hh in hists for h in hh if h["ss_error"] > 0]
+        num = sum(h["proj_numerator"] for hh in hists for h in hh)
+        den = sum(h["ref_pop_units"] for hh in hists for h in hh) / 256.0
+        results[name] = {
+            "walker_updates_per_s": upd / dt,
+            "ms_per_iteration": dt * 1e3 / args.steps,
+            "iteration_ms_device_median": it_ms[len(it_ms) // 2],
+            "projection_ms_per_iteration": kt["det_project"] / max(niter, 1),
+            "gather_ms_per_iteration": kt["det_gather"] / max(niter, 1),
+            "fp64_check_ms_per_iteration": kt["det_check"] / max(niter, 1),
+            "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in kt.items() if v / max(niter, 1) > 0.005},
+            "projected_energy_window": num / den if den else None,
+            "ss_error_max": max(errs) if errs else None,
+            "ss_error_bound": hists[0][-1]["ss_error_bound"],
+            "walkers_end": sum(hh[-1]["n_walkers_units"] for hh in hists) / 256.0,
+            "determinants_end": sum(hh[-1]["n_occupied"] for hh in hists),
+        }
+        log(f"{name}: {results[name]['walker_updates_per_s']:.4g} walker updates/s, projection "
+            f"{results[name]['projection_ms_per_iteration']:.4f} ms/iteration")
+        ctx.close()
+    split, fp = results["split_bf16x3"], results["fp64"]
+    out = {
+        "metric": METRIC,
+        "value": split["walker_updates_per_s"],
+        "unit": "walker updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": split["ms_per_iteration"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (projection bf16x3/fp32 on MFMA)",
+        "data": "synthetic",
+        "config": {"workload": f"mol30_semistochastic_D2000_R{R}_target1e7", "replicas": R,
+                   "deterministic_space": 2000, "shared_space": R > 1, "selection_iteration": start,
+                   "timed_iterations": f"{args.warmup + 1}..{args.warmup + args.steps}",
+                   "parallelism": "single GPU"},
+        "fp64": fp,
+        "split_bf16x3": split,
+        "split_over_fp64_walker_updates": split["walker_updates_per_s"] / fp["walker_updates_per_s"],
+        "split_over_fp64_projection_speed": fp["projection_ms_per_iteration"] / split["projection_ms_per_iteration"],
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,8 +303,10 @@ def main():
     ap.add_argument("--main-capacity", type=int, default=1 << 28)
     ap.add_argument("--spawn-capacity", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64"],
-                    help="ueg14: the plain single-instance path; batch64: 64 batched instances vs plain runs")
+    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64", "mol30"],
+                    help="ueg14: the plain single-instance path; batch64: 64 batched instances vs plain runs; "
+                         "mol30: semi-stochastic molecular runs, FP64 vs split-precision projection")
+    ap.add_argument("--replicas", type=int, default=1, help="mol30: replicas sharing one deterministic space")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (4 times) for counter calibration")
     args = ap.parse_args()
@@ -225,6 +317,8 @@ def main():
 
     if args.workload == "batch64":
         return run_batch64(args)
+    if args.workload == "mol30":
+        return run_mol30(args)
 
     import torch
     from paper_1811_11679_amd import fciqmc as F

@@ -555,8 +555,14 @@ __device__ bool gen_ueg(const UegTables &s, const uint64_t (&D)[W], uint32_t w0,
 template <int W>
 __device__ bool gen_heatbath(const DevSys &s, double p_single, const uint64_t (&D)[W], const U4 &r0,
                              uint32_t attempt, uint32_t t, uint64_t hsh, uint32_t k0, uint32_t k1,
-                             uint64_t (&child)[W], double &pgen, double &h)
+                             uint64_t (&child)[W], double &pgen, double &h, const double *stri = nullptr)
 {
+    // pair weights S_PQ: the full table, or (stri) its strict upper triangle
+    // row by row, P*(2n-P-1)/2 + Q-P-1, as staged in LDS by the spawn kernel
+    const int nso = s.n_so;
+    auto spq = [&](int P, int Q) -> double {
+        return stri ? stri[P * (2 * nso - P - 1) / 2 + (Q - P - 1)] : s.hb_S[P * nso + Q];
+    };
     const int N = s.nel;
     const int n = s.n_so;
     const double d = u53(r0.x, r0.y);
@@ -582,7 +588,7 @@ __device__ bool gen_heatbath(const DevSys &s, double p_single, const uint64_t (&
         return true;
     }
     double T = 0.0;
-    for_pairs<W>(D, [&](int P, int Q) { T = T + s.hb_S[P * n + Q]; });
+    for_pairs<W>(D, [&](int P, int Q) { T = T + spq(P, Q); });
     if (!(T > 0.0)) return false;
     const U4 r1 = draw(TAG_SELECT2, attempt, t, hsh, k0, k1);
     const double x = u53(r1.x, r1.y) * T;
@@ -590,7 +596,7 @@ __device__ bool gen_heatbath(const DevSys &s, double p_single, const uint64_t (&
     int Ps = -1, Qs = -1;
     for_pairs<W>(D, [&](int P, int Q) {
         if (Ps < 0) {
-            cum = cum + s.hb_S[P * n + Q];
+            cum = cum + spq(P, Q);
             if (x < cum) {
                 Ps = P;
                 Qs = Q;

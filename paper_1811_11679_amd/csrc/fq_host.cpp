@@ -923,6 +923,15 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         const size_t bytes = c->kind == FQ_UEG ? 8 * (m + m * m) : 8 * (m + 2 * m * m);
         if (bytes <= 65536) w.lds_diag = (int32_t)bytes;
     }
+    // heat-bath pair weights (upper triangle) staged in LDS by the single-replica spawn kernel
+    if (c->R == 1 && c->kind == FQ_MOLECULAR) {
+        const size_t nso = (size_t)c->sys[0].n_so;
+        const size_t bytes = 8 * (nso * (nso - 1) / 2);
+        if (bytes <= 32768) {
+            c->grids.spawn_lds = (int)bytes;
+            w.lds_tables = (int32_t)bytes;
+        }
+    }
     // UEG generator tables staged in LDS by the single-replica spawn kernel
     if (c->R == 1 && c->kind == FQ_UEG) {
         const HostSys &s0 = c->sys[0];

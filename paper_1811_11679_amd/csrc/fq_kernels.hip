@@ -354,7 +354,23 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
     const int lane = lane_id(), wid = threadIdx.x >> 6;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     UegTables lu = w.sys[w.rep[0].sys].u;
-    if constexpr (LT) {
+    const double *hb_tri = nullptr;  // heat-bath pair weights staged in LDS (LT, molecular)
+    if constexpr (LT && KIND == K_MOLECULAR) {
+        const DevSys &sy0 = w.sys[w.rep[0].sys];
+        const int nso = sy0.n_so, ntri = nso * (nso - 1) / 2;
+        double *tt = (double *)dyn_lds;
+        for (int x = threadIdx.x; x < ntri; x += SP_T) {
+            // x -> (P, Q), P < Q, row by row
+            int P = 0, rem = x;
+            while (rem >= nso - 1 - P) {
+                rem -= nso - 1 - P;
+                ++P;
+            }
+            tt[x] = sy0.hb_S[P * nso + P + 1 + rem];
+        }
+        hb_tri = tt;
+    }
+    if constexpr (LT && KIND == K_UEG) {
         const int M = lu.M, nv = w.sys[w.rep[0].sys].vlen, ng = lu.gdim * lu.gdim * lu.gdim;
         int32_t *tn = (int32_t *)dyn_lds;
         double *tv = (double *)(dyn_lds + ((4 * M + 15) & ~15));
@@ -479,7 +495,8 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 else if constexpr (KIND == K_UEG)
                     ok = gen_ueg<W>(LT ? lu : sy.u, key, r0.x, r0.y, child[it], pgen, hv);
                 else
-                    ok = gen_heatbath<W>(sy, rp.p_single, key, r0, (uint32_t)k, t, h, rp.k0, rp.k1, child[it], pgen, hv);
+                    ok = gen_heatbath<W>(sy, rp.p_single, key, r0, (uint32_t)k, t, h, rp.k0, rp.k1, child[it], pgen, hv,
+                                         hb_tri);
                 if (ok && hv != 0.0) {
                     bool skip = false;
                     if (pin_d) {
@@ -1527,73 +1544,41 @@ __global__ __launch_bounds__(256) void k_det_project_fp64(Work w, int mode)
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_det_project_split(Work w)
+constexpr int DP_WAVES = 8;  // waves per block of the split projection (split over k)
+
+__global__ __launch_bounds__(64 * DP_WAVES) void k_det_project_split(Work w)
 {
+    // One block per job (16 rows x up to 16 columns of Y = K C); its waves
+    // take interleaved 16-wide steps of the k range and their FP32 partial
+    // tiles are summed in LDS in wave order. Shared space: the columns are 16
+    // replicas, one K_DD for all. Otherwise: one replica per job, in column 0.
     const Ctl *c = w.ctl;
     if (c->err || !c->ss_active || w.ds.precision != 1) return;
+    __shared__ float s_part[DP_WAVES][64][4];
     const int n = w.ds.n, np = w.ds.npad;
-    const int lane = lane_id();
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
     const int tiles = np / 16;
-    if (w.ds.shared) {
-        // one K_DD for every replica: Y = K C with the replicas as the 16
-        // columns of the B tile, so each A tile serves 16 replicas
-        const int cblocks = (w.R + 15) / 16;
-        const long long jobs = (long long)tiles * cblocks;
-        for (long long job = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); job < jobs;
-             job += (long long)gridDim.x * (blockDim.x >> 6)) {
-            const int rt = (int)(job / cblocks), cb = (int)(job % cblocks);
-            const int arow = rt * 16 + (lane & 15);
-            const int kq = 4 * (lane >> 4);
-            const int rep = cb * 16 + (lane & 15);  // this lane's column of B and D
-            const bool bval = rep < w.R;
-            const uint16_t *kh = w.ds.Khi + (size_t)arow * np + kq;
-            const uint16_t *kl = w.ds.Klo + (size_t)arow * np + kq;
-            const uint16_t *ch = w.ds.Chi + (size_t)(bval ? rep : 0) * np + kq;
-            const uint16_t *cl = w.ds.Clo + (size_t)(bval ? rep : 0) * np + kq;
-            f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-            for (int kk = 0; kk < np; kk += 16) {
-                const bf16x4_t ah = *(const bf16x4_t *)(kh + kk);
-                const bf16x4_t al = *(const bf16x4_t *)(kl + kk);
-                bf16x4_t bh = {0, 0, 0, 0}, bl = {0, 0, 0, 0};
-                if (bval) {
-                    bh = *(const bf16x4_t *)(ch + kk);
-                    bl = *(const bf16x4_t *)(cl + kk);
-                }
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
-            }
-            // lane holds rows 4 (lane / 16) + i of column lane % 16
-            if (bval) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int d = rt * 16 + 4 * (lane >> 4) + i;
-                    if (d < n) {
-                        const long long row = (long long)rep * n + d;
-                        det_update(w, c, rep, row, (double)acc[i], w.ds.c[row]);
-                    }
-                }
-            }
-        }
-        return;
-    }
-    const long long jobs = (long long)tiles * w.R;
-    for (long long job = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); job < jobs;
-         job += (long long)gridDim.x * (blockDim.x >> 6)) {
-        const int rep = (int)(job / tiles), rt = (int)(job % tiles);
+    const bool shared = w.ds.shared != 0;
+    const int cblocks = shared ? (w.R + 15) / 16 : w.R;
+    const long long jobs = (long long)tiles * cblocks;
+    for (long long job = blockIdx.x; job < jobs; job += gridDim.x) {
+        const int rt = (int)(job / cblocks), cb = (int)(job % cblocks);
         const int arow = rt * 16 + (lane & 15);
         const int kq = 4 * (lane >> 4);
-        const uint16_t *kh = w.ds.Khi + ((size_t)rep * np + arow) * np + kq;
-        const uint16_t *kl = w.ds.Klo + ((size_t)rep * np + arow) * np + kq;
-        const uint16_t *ch = w.ds.Chi + (size_t)rep * np + kq;
-        const uint16_t *cl = w.ds.Clo + (size_t)rep * np + kq;
-        const bool bcol = (lane & 15) == 0;
+        // this lane's column of B (and of the result): a replica
+        const int rep = shared ? cb * 16 + (lane & 15) : cb;
+        const bool bval = shared ? rep < w.R : (lane & 15) == 0;
+        const size_t kmat = shared ? 0 : (size_t)cb;
+        const uint16_t *kh = w.ds.Khi + (kmat * np + arow) * np + kq;
+        const uint16_t *kl = w.ds.Klo + (kmat * np + arow) * np + kq;
+        const uint16_t *ch = w.ds.Chi + (size_t)(bval ? rep : 0) * np + kq;
+        const uint16_t *cl = w.ds.Clo + (size_t)(bval ? rep : 0) * np + kq;
         f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-        for (int kk = 0; kk < np; kk += 16) {
+        for (int kk = 16 * wv; kk < np; kk += 16 * DP_WAVES) {
             const bf16x4_t ah = *(const bf16x4_t *)(kh + kk);
             const bf16x4_t al = *(const bf16x4_t *)(kl + kk);
             bf16x4_t bh = {0, 0, 0, 0}, bl = {0, 0, 0, 0};
-            if (bcol) {
+            if (bval) {
                 bh = *(const bf16x4_t *)(ch + kk);
                 bl = *(const bf16x4_t *)(cl + kk);
             }
@@ -1601,17 +1586,23 @@ __global__ __launch_bounds__(256) void k_det_project_split(Work w)
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s_part[wv][lane][i] = acc[i];
+        __syncthreads();
         // lane holds rows 4 (lane / 16) + i of column lane % 16
-        if (bcol) {
+        if (wv == 0 && bval) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
+                float y = s_part[0][lane][i];
+                for (int q = 1; q < DP_WAVES; ++q) y = y + s_part[q][lane][i];
                 const int d = rt * 16 + 4 * (lane >> 4) + i;
                 if (d < n) {
                     const long long row = (long long)rep * n + d;
-                    det_update(w, c, rep, row, (double)acc[i], w.ds.c[row]);
+                    det_update(w, c, rep, row, (double)y, w.ds.c[row]);
                 }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -1647,6 +1638,8 @@ template __global__ void k_spawn<K_UEG, 1, false, true>(Work);
 template __global__ void k_spawn<K_UEG, 2, false, true>(Work);
 template __global__ void k_spawn<K_UEG, 4, false, true>(Work);
 template __global__ void k_spawn<K_UEG, 8, false, true>(Work);
+template __global__ void k_spawn<K_MOLECULAR, 1, false, true>(Work);
+template __global__ void k_spawn<K_MOLECULAR, 2, false, true>(Work);
 FQ_INST(K_MOLECULAR, 1)
 FQ_INST(K_MOLECULAR, 2)
 #define FQ_INSTW(W)                                        \
@@ -1751,8 +1744,8 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     rec();
     if (w.R > 1)
         k_spawn<KIND, W, true, false><<<g.spawn, SP_T, 0, s>>>(w);
-    else if (KIND == K_UEG && w.lds_tables > 0)
-        k_spawn<KIND, W, false, KIND == K_UEG><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
+    else if ((KIND == K_UEG || KIND == K_MOLECULAR) && w.lds_tables > 0)
+        k_spawn<KIND, W, false, KIND == K_UEG || KIND == K_MOLECULAR><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
     else
         k_spawn<KIND, W, false, false><<<g.spawn, SP_T, 0, s>>>(w);
     rec();
@@ -1775,7 +1768,7 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     k_det_gather<<<g.det, 256, 0, s>>>(w);
     rec();
     if (w.ds.precision == 1)
-        k_det_project_split<<<g.det, 256, 0, s>>>(w);
+        k_det_project_split<<<g.det, 64 * DP_WAVES, 0, s>>>(w);
     else
         k_det_project_fp64<<<g.det, 256, 0, s>>>(w, 0);
     rec();
