@@ -295,6 +295,96 @@ def run_mol30(args):
     print(json.dumps(out))
 
 
+def run_ueg54(args):
+    """Large single instance: 54-electron gas (27 + 27), rs = 1, 251 plane waves
+    (502 spin-orbitals, 8-word keys), initiator, 1/256 fixed point, dtau =
+    0.0005, population target set so that the list holds about 2e8
+    determinants, semi-stochastic with D = 8192 in split BF16 x3 precision
+    and the FP64 projection computed beside it every 10 iterations (its time
+    and the error of the split result)."""
+    from paper_1811_11679_amd import fciqmc as F
+    from paper_1811_11679_amd import workloads
+
+    w = workloads.UEG54
+    s, q = w["system"], dict(w["qmc"])
+    q["target_population"] = args.target
+    q["init_pop"] = args.init_pop
+    q["initial_shift"] = args.initial_shift
+    q["shift_damping"] = args.shift_damping
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
+    sysd = F.make_system(F.UEG, rs=s["rs"], ecut_n2=s["ecut_n2"], n_alpha=s["n_alpha"], n_beta=s["n_beta"])
+    ss = F.SemiStoch(size=8192, start_iteration=max(args.warmup - 100, 1), precision=F.SS_SPLIT_BF16,
+                     check_period=10)
+    ctx = F.Context([sysd], [F.make_qmc(excit_gen=F.UEG, **q)], ss, main_capacity=args.main_capacity,
+                    spawn_capacity=args.spawn_capacity)
+    log(f"workspace {ctx.workspace.numel() / 1e9:.1f} GB, key words {ctx.W}")
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.warmup:
+        k = min(20 if done < 400 else 100, args.warmup - done)
+        ctx.step(k)
+        done += k
+        e = ctx.estimators()
+        log(f"warmup {done}: N_w {e['n_walkers_units'] / 256:.4g}, {e['n_occupied']} determinants, "
+            f"{e['n_spawned']} spawned, shift {e['shift']:.5f}, {time.perf_counter() - t0:.1f} s")
+    e_start = ctx.estimators()
+    ctx.set_timing(True)
+    t1 = time.perf_counter()
+    done = 0
+    while done < args.steps:
+        k = min(100, args.steps - done)
+        ctx.step(k)
+        done += k
+        log(f"timed {done}: {time.perf_counter() - t1:.1f} s")
+    ctx.stream.synchronize()
+    dt = time.perf_counter() - t1
+    ctx.set_timing(False)
+    kt, niter = ctx.kernel_times()
+    it_ms = sorted(ctx.iteration_times())
+    hist = ctx.history()[-min(args.steps, 100):]
+    # the history of the last step call covers its iterations only
+    upd_note = "walker updates over the last timed step call"
+    upd = (sum(h["n_walkers_units"] for h in hist[:-1]) + hist[0]["n_walkers_units"]) / 256.0
+    errs = [h["ss_error"] for h in hist if h["ss_error"] > 0]
+    mean_ms = sum(it_ms) / len(it_ms) if it_ms else dt * 1e3 / args.steps
+    out = {
+        "metric": METRIC,
+        "value": (e_start["n_walkers_units"] / 256.0) / (dt / args.steps),
+        "unit": "walker updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (projection bf16x3/fp32 on MFMA)",
+        "data": "synthetic",
+        "config": {"workload": "ueg54_rs1_251pw_initiator_D8192", "electrons": 54, "plane_waves": 251,
+                   "key_words": ctx.W, "tau": q["tau"], "target_walkers": args.target,
+                   "timed_iterations": f"{e_start['iteration'] + 1}..{e_start['iteration'] + args.steps}",
+                   "parallelism": "single GPU"},
+        "walkers_start": e_start["n_walkers_units"] / 256.0,
+        "determinants_start": e_start["n_occupied"],
+        "determinants_end": hist[-1]["n_occupied"],
+        "spawned_per_iteration": sum(h["n_spawned"] for h in hist) / len(hist),
+        "walker_updates_per_s_window": upd / (sum(it_ms[-len(hist):]) * 1e-3) if it_ms else None,
+        "window_note": upd_note,
+        "iteration_ms_device": {"median": it_ms[len(it_ms) // 2], "p90": it_ms[(9 * len(it_ms)) // 10],
+                                "mean": mean_ms} if it_ms else None,
+        "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in kt.items() if v / max(niter, 1) > 0.005},
+        "projection_split_ms": kt["det_project"] / max(niter, 1),
+        "projection_fp64_ms_per_check": kt["det_check"] / max(1, niter // 10),
+        "ss_error_max": max(errs) if errs else None,
+        "ss_error_bound": hist[-1]["ss_error_bound"],
+        "shift_end": hist[-1]["shift"],
+        "proj_energy_end": hist[-1]["proj_energy"],
+        "warmup_s": time.perf_counter() - t0 - dt,
+    }
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,7 +393,12 @@ def main():
     ap.add_argument("--main-capacity", type=int, default=1 << 28)
     ap.add_argument("--spawn-capacity", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64", "mol30"],
+    ap.add_argument("--target", type=float, default=5e7, help="ueg54: target walkers")
+    ap.add_argument("--init-pop", type=float, default=1e4, help="ueg54: initial walkers on the reference")
+    ap.add_argument("--shift-damping", type=float, default=0.2, help="ueg54: shift damping (zeta)")
+    ap.add_argument("--initial-shift", type=float, default=0.0,
+                    help="ueg54: initial shift (Hartree, relative to H_00), damps the initial growth")
+    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64", "mol30", "ueg54"],
                     help="ueg14: the plain single-instance path; batch64: 64 batched instances vs plain runs; "
                          "mol30: semi-stochastic molecular runs, FP64 vs split-precision projection")
     ap.add_argument("--replicas", type=int, default=1, help="mol30: replicas sharing one deterministic space")
@@ -319,6 +414,8 @@ def main():
         return run_batch64(args)
     if args.workload == "mol30":
         return run_mol30(args)
+    if args.workload == "ueg54":
+        return run_ueg54(args)
 
     import torch
     from paper_1811_11679_amd import fciqmc as F

@@ -314,11 +314,19 @@ __device__ double diag_ueg(const UegTables &u, const uint64_t (&key)[W])
 {
     double e = 0.0;
     for_bits<W>(key, [&](int P) { e = e + u.eps[P >> 1]; });
-    for_pairs<W>(key, [&](int P, int Q) {
-        if ((P & 1) == (Q & 1)) {
-            const double v = u.vx ? u.vx[(P >> 1) * u.M + (Q >> 1)] : u.vtab[pk_dn2(u.npk[P >> 1], u.npk[Q >> 1])];
+    // exchange of the same-spin pairs P < Q, in the order of all pairs (P
+    // ascending, then Q ascending): opposite-spin pairs contribute nothing and
+    // are not visited
+    for_bits<W>(key, [&](int P) {
+        const uint64_t sm = (P & 1) ? 0xAAAAAAAAAAAAAAAAull : 0x5555555555555555ull;
+        uint64_t rest[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) rest[i] = key[i] & sm & ~range_mask(i, 0, P + 1);
+        const int p = P >> 1;
+        for_bits<W>(rest, [&](int Q) {
+            const double v = u.vx ? u.vx[p * u.M + (Q >> 1)] : u.vtab[pk_dn2(u.npk[p], u.npk[Q >> 1])];
             e = e - v;
-        }
+        });
     });
     return e;
 }

@@ -250,7 +250,7 @@ bool same_system(const fq_system &a, const fq_system &b)
 }
 
 // spans of 256 attempts the attempt partition can hold
-int64_t span_capacity(int64_t mcap, int64_t scap) { return tiles_of(std::max(mcap * 16, scap * 4), SPAN); }
+int64_t span_capacity(int64_t mcap, int64_t scap, int W) { return tiles_of(std::max(mcap * 16, scap * 4), span_of(W)); }
 
 Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D, int nk)
 {
@@ -269,13 +269,13 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.sys = take(sizeof(DevSys) * R);
     L.tables = take((size_t)tables);
     L.att = take(8 * (size_t)(mcap + 1));
-    L.span = take(8 * (size_t)(span_capacity(mcap, scap) + 2));
+    L.span = take(8 * (size_t)(span_capacity(mcap, scap, W) + 2));
     L.mpart = take(8 * (size_t)(tiles_of(mcap + scap, 512) + 2));
     L.st_scan = take(8 * (size_t)tiles_of(mcap, 2048));
     L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, 4096));
     L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
     L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 512));
-    L.st_spawn = take(8 * (size_t)(span_capacity(mcap, scap) + 2));
+    L.st_spawn = take(8 * (size_t)(span_capacity(mcap, scap, W) + 2));
     L.st_att = take(8 * (size_t)tiles_of(mcap + scap, 512));
     L.part_red = take(8 * (size_t)PART_MAX_BLOCKS * acc_rows(R) * EST_FIELDS);
     L.part_mrg = take(8 * (size_t)PART_MAX_BLOCKS * acc_rows(R) * EST_FIELDS);
@@ -574,7 +574,7 @@ fq_status select_detspace(fq_ctx *c)
                 if ((int)rep_of(e[i]) == r) ix.push_back(i);
             if ((int64_t)ix.size() < D)
                 return fail(c, FQ_ESTATE, "fewer occupied determinants than the deterministic space size");
-            std::sort(ix.begin(), ix.end(), [&](int64_t a, int64_t b) {
+            std::partial_sort(ix.begin(), ix.begin() + D, ix.end(), [&](int64_t a, int64_t b) {
                 const long long pa = std::llabs((long long)e[a].pop), pb = std::llabs((long long)e[b].pop);
                 if (pa != pb) return pa > pb;
                 return key_cmp_host(e[a].key, e[b].key, W) < 0;
@@ -821,7 +821,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.ds.key_sorted = (const uint64_t *)(c->ws + c->L.ds[9]);
     w.main_cap = main_capacity;
     w.spawn_cap = spawn_capacity;
-    w.span_cap = span_capacity(main_capacity, spawn_capacity);
+    w.span_cap = span_capacity(main_capacity, spawn_capacity, c->W);
     w.R = c->R;
     w.rb = c->rb;
     w.W = c->W;
@@ -920,8 +920,10 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     // diagonal tables staged in LDS by the single-replica new-determinant kernel
     if (c->R == 1 && (c->kind == FQ_UEG || c->kind == FQ_MOLECULAR)) {
         const size_t m = (size_t)c->sys[0].n_spatial;
-        const size_t bytes = c->kind == FQ_UEG ? 8 * (m + m * m) : 8 * (m + 2 * m * m);
-        if (bytes <= 65536) w.lds_diag = (int32_t)bytes;
+        size_t bytes = c->kind == FQ_UEG ? 8 * (m + m * m) : 8 * (m + 2 * m * m);
+        // electron gas on a large basis: kinetic energies, v by |dn|^2, packed momenta
+        if (c->kind == FQ_UEG && bytes > (size_t)ND_LDS_MAX) bytes = 8 * m + 8 * (size_t)c->sys[0].vlen + 4 * m;
+        if (bytes <= (size_t)ND_LDS_MAX) w.lds_diag = (int32_t)bytes;
     }
     // heat-bath pair weights (upper triangle) staged in LDS by the single-replica spawn kernel
     if (c->R == 1 && c->kind == FQ_MOLECULAR) {

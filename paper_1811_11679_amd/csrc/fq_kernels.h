@@ -68,12 +68,17 @@ constexpr int EST_FIELDS = 14;
 // to global memory directly), and the largest grid of the kernels that write
 // partials
 constexpr int ACC_LDS_R = 64;
-// spawn tiles: SP_T threads, SP_I attempts per thread, SPAN attempts per tile
+// spawn tiles: SP_T threads, sp_items(W) attempts per thread (fewer for long
+// keys, whose children take more registers), span_of(W) attempts per tile
 #ifndef FQ_SPAWN_ITEMS
 #define FQ_SPAWN_ITEMS 4
 #endif
-constexpr int SP_T = 256, SP_I = FQ_SPAWN_ITEMS, SPAN = SP_T * SP_I;
+constexpr int SP_T = 256;
+__host__ __device__ constexpr int sp_items(int W) { return W <= 2 ? FQ_SPAWN_ITEMS : 2; }
+__host__ __device__ constexpr int span_of(int W) { return SP_T * sp_items(W); }
 constexpr int PART_MAX_BLOCKS = 8192;
+// largest diagonal-table staging of the new-determinant kernel (bytes of LDS)
+constexpr int ND_LDS_MAX = 65536;
 __host__ __device__ inline int acc_rows(int R) { return R < ACC_LDS_R ? R : ACC_LDS_R; }
 
 struct MainList {

@@ -303,12 +303,12 @@ __device__ __forceinline__ long long upper_bound_ll(const long long *a, long lon
     return lo;
 }
 
-__global__ void k_spawn_partition(Work w)
+__global__ void k_spawn_partition(Work w, int span_len)
 {
     const Ctl *c = w.ctl;
     if (c->err) return;
     const long long total = c->n_att, n = c->n_main;
-    const long long nspans = (total + SPAN - 1) / SPAN;
+    const long long nspans = (total + span_len - 1) / span_len;
     if (nspans + 1 > w.span_cap) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&((Ctl *)c)->err, ERR_SPAWN_CAP);
         return;
@@ -318,7 +318,7 @@ __global__ void k_spawn_partition(Work w)
         if (s == nspans) {
             w.span_lo[s] = n > 0 ? n - 1 : 0;
         } else {
-            w.span_lo[s] = upper_bound_ll(w.att_off, 0, n + 1, s * SPAN) - 1;
+            w.span_lo[s] = upper_bound_ll(w.att_off, 0, n + 1, s * span_len) - 1;
         }
     }
 }
@@ -337,6 +337,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 {
     Ctl *c = w.ctl;
     if (c->err) return;
+    constexpr int SP_I = sp_items(W), SPAN = span_of(W);
     constexpr int LCAP = SPAN + 2;
     __shared__ long long s_off[LCAP];
     __shared__ uint32_t s_cnt[SP_I][SP_T / 64];
@@ -1384,11 +1385,26 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
         double *t0 = (double *)dyn_lds;
         const int m = s0.n_spatial;
         if (KIND == K_UEG) {
-            double *t1 = t0 + m;
-            for (int i = threadIdx.x; i < m; i += ND_T) t0[i] = lu.eps[i];
-            for (int i = threadIdx.x; i < m * m; i += ND_T) t1[i] = lu.vx[i];
-            lu.eps = t0;
-            lu.vx = t1;
+            if (8 * (m + m * m) <= ND_LDS_MAX) {
+                // kinetic energies and the exchange table v(|n_p - n_q|^2)
+                double *t1 = t0 + m;
+                for (int i = threadIdx.x; i < m; i += ND_T) t0[i] = lu.eps[i];
+                for (int i = threadIdx.x; i < m * m; i += ND_T) t1[i] = lu.vx[i];
+                lu.eps = t0;
+                lu.vx = t1;
+            } else {
+                // large bases: kinetic energies, v by |dn|^2 and the packed momenta
+                const int nv = s0.vlen;
+                double *t1 = t0 + m;
+                int32_t *t2 = (int32_t *)(t1 + nv);
+                for (int i = threadIdx.x; i < m; i += ND_T) t0[i] = lu.eps[i];
+                for (int i = threadIdx.x; i < nv; i += ND_T) t1[i] = lu.vtab[i];
+                for (int i = threadIdx.x; i < m; i += ND_T) t2[i] = lu.npk[i];
+                lu.eps = t0;
+                lu.vtab = t1;
+                lu.npk = t2;
+                lu.vx = nullptr;
+            }
         } else {
             double *t1 = t0 + m, *t2 = t1 + m * m;
             for (int i = threadIdx.x; i < m; i += ND_T) t0[i] = lhd[i];
@@ -1740,7 +1756,7 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     rec();
     k_begin<<<1, 256, 0, s>>>(w);
     rec();
-    k_spawn_partition<<<g.part, 256, 0, s>>>(w);
+    k_spawn_partition<<<g.part, 256, 0, s>>>(w, span_of(W));
     rec();
     if (w.R > 1)
         k_spawn<KIND, W, true, false><<<g.spawn, SP_T, 0, s>>>(w);
