@@ -918,7 +918,10 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     c->grids.part = ncu * 4;
     c->grids.spawn = ncu * occupancy_blocks(4);
     // diagonal tables staged in LDS by the single-replica new-determinant kernel
-    if (c->R == 1 && (c->kind == FQ_UEG || c->kind == FQ_MOLECULAR)) {
+    // tables staged in LDS serve every replica when all replicas share one system
+    bool one_system = true;
+    for (int r = 1; r < c->R; ++r) one_system = one_system && same_system(sys[0], sys[r]);
+    if (one_system && (c->kind == FQ_UEG || c->kind == FQ_MOLECULAR)) {
         const size_t m = (size_t)c->sys[0].n_spatial;
         size_t bytes = c->kind == FQ_UEG ? 8 * (m + m * m) : 8 * (m + 2 * m * m);
         // electron gas on a large basis: kinetic energies, v by |dn|^2, packed momenta
@@ -926,7 +929,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         if (bytes <= (size_t)ND_LDS_MAX) w.lds_diag = (int32_t)bytes;
     }
     // heat-bath pair weights (upper triangle) staged in LDS by the single-replica spawn kernel
-    if (c->R == 1 && c->kind == FQ_MOLECULAR) {
+    if (one_system && c->kind == FQ_MOLECULAR) {
         const size_t nso = (size_t)c->sys[0].n_so;
         const size_t bytes = 8 * (nso * (nso - 1) / 2);
         if (bytes <= 32768) {
@@ -935,7 +938,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         }
     }
     // UEG generator tables staged in LDS by the single-replica spawn kernel
-    if (c->R == 1 && c->kind == FQ_UEG) {
+    if (one_system && c->kind == FQ_UEG) {
         const HostSys &s0 = c->sys[0];
         const size_t bytes = ((4 * (size_t)s0.n_spatial + 15) & ~(size_t)15) + ((8 * (size_t)s0.vlen + 15) & ~(size_t)15) +
                              2 * s0.grid.size();

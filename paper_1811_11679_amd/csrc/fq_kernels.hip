@@ -1378,7 +1378,8 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
     __shared__ int s_n;
     const long long n = c->n_main_new;
     const DevSys &s0 = w.sys[w.rep[0].sys];
-    const bool local = w.R == 1 && w.lds_diag > 0 && (KIND == K_UEG || KIND == K_MOLECULAR);
+    // the host stages tables only when every replica has the same system
+    const bool local = w.lds_diag > 0 && (KIND == K_UEG || KIND == K_MOLECULAR);
     UegTables lu = s0.u;
     const double *lhd = s0.hd, *lJ = s0.Jt, *lK = s0.Kt;
     if (local) {
@@ -1656,6 +1657,12 @@ template __global__ void k_spawn<K_UEG, 4, false, true>(Work);
 template __global__ void k_spawn<K_UEG, 8, false, true>(Work);
 template __global__ void k_spawn<K_MOLECULAR, 1, false, true>(Work);
 template __global__ void k_spawn<K_MOLECULAR, 2, false, true>(Work);
+template __global__ void k_spawn<K_UEG, 1, true, true>(Work);
+template __global__ void k_spawn<K_UEG, 2, true, true>(Work);
+template __global__ void k_spawn<K_UEG, 4, true, true>(Work);
+template __global__ void k_spawn<K_UEG, 8, true, true>(Work);
+template __global__ void k_spawn<K_MOLECULAR, 1, true, true>(Work);
+template __global__ void k_spawn<K_MOLECULAR, 2, true, true>(Work);
 FQ_INST(K_MOLECULAR, 1)
 FQ_INST(K_MOLECULAR, 2)
 #define FQ_INSTW(W)                                        \
@@ -1758,7 +1765,10 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     rec();
     k_spawn_partition<<<g.part, 256, 0, s>>>(w, span_of(W));
     rec();
-    if (w.R > 1)
+    constexpr bool TAB = KIND == K_UEG || KIND == K_MOLECULAR;
+    if (w.R > 1 && TAB && w.lds_tables > 0)
+        k_spawn<KIND, W, true, TAB><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
+    else if (w.R > 1)
         k_spawn<KIND, W, true, false><<<g.spawn, SP_T, 0, s>>>(w);
     else if ((KIND == K_UEG || KIND == K_MOLECULAR) && w.lds_tables > 0)
         k_spawn<KIND, W, false, KIND == K_UEG || KIND == K_MOLECULAR><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
