@@ -393,9 +393,9 @@ def main():
     ap.add_argument("--main-capacity", type=int, default=1 << 28)
     ap.add_argument("--spawn-capacity", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--target", type=float, default=5e7, help="ueg54: target walkers")
+    ap.add_argument("--target", type=float, default=2e7, help="ueg54: target walkers")
     ap.add_argument("--init-pop", type=float, default=1e4, help="ueg54: initial walkers on the reference")
-    ap.add_argument("--shift-damping", type=float, default=0.2, help="ueg54: shift damping (zeta)")
+    ap.add_argument("--shift-damping", type=float, default=1.0, help="ueg54: shift damping (zeta)")
     ap.add_argument("--initial-shift", type=float, default=0.0,
                     help="ueg54: initial shift (Hartree, relative to H_00), damps the initial growth")
     ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64", "mol30", "ueg54"],
