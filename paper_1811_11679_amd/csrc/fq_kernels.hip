@@ -342,7 +342,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
     __shared__ long long s_off[LCAP];
     __shared__ uint32_t s_cnt[SP_I][SP_T / 64];
     __shared__ long long s_tile, s_base;
-    __shared__ uint64_t s_rk[SP_STAGE];
+    __shared__ uint32_t s_rrep[MULTI ? SP_STAGE : 1];  // replica of a staged record
     __shared__ uint64_t s_rkey[W][SP_STAGE];
     __shared__ int32_t s_ramp[SP_STAGE];
     __shared__ uint8_t s_rinit[SP_STAGE];
@@ -580,18 +580,17 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
             const long long lb_ = lookback(w.st_spawn, span, epoch, (long long)tot);
             if (threadIdx.x == 0) s_base = lb_;
         }
+        // staged records get their sort key (a hash of the child) in the dense
+        // output loop below, not in the divergent per-attempt code
         uint32_t rk[SP_I];
-        uint64_t csk[SP_I];
 #pragma unroll
         for (int it = 0; it < SP_I; ++it) {
             const uint64_t m = __ballot(has[it]);
             rk[it] = before[it] + (uint32_t)__popcll(m & lanemask_lt());
-            csk[it] = 0;
             if (has[it]) {
-                csk[it] = make_skey(hash64<W>(child[it]), rep[it], w.rb);
                 const uint32_t r = rk[it];
                 if (r < SP_STAGE) {
-                    s_rk[r] = csk[it];
+                    if constexpr (MULTI) s_rrep[r] = rep[it];
 #pragma unroll
                     for (int q = 0; q < W; ++q) s_rkey[q][r] = child[it][q];
                     s_ramp[r] = amp[it];
@@ -607,10 +606,13 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
             const uint32_t ns = tot < SP_STAGE ? tot : SP_STAGE;
             for (uint32_t p = threadIdx.x; p < ns; p += SP_T) {
                 const long long o = base + p;
-                w.sp.skey[o] = s_rk[p];
+                uint64_t key[W];
+#pragma unroll
+                for (int q = 0; q < W; ++q) key[q] = s_rkey[q][p];
+                w.sp.skey[o] = make_skey(hash64<W>(key), MULTI ? s_rrep[p] : 0u, w.rb);
                 uint64_t *rec = w.sp.rec + (size_t)o * (W + 1);
 #pragma unroll
-                for (int q = 0; q < W; ++q) rec[q] = s_rkey[q][p];
+                for (int q = 0; q < W; ++q) rec[q] = key[q];
                 rec[W] = (uint64_t)(uint32_t)s_ramp[p] | ((uint64_t)s_rinit[p] << 32);
                 w.u.sum[o] = 0;
                 w.u.flag[o] = 0;
@@ -619,7 +621,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
             for (int it = 0; it < SP_I; ++it)
                 if (has[it] && rk[it] >= SP_STAGE) {
                     const long long o = base + rk[it];
-                    w.sp.skey[o] = csk[it];
+                    w.sp.skey[o] = make_skey(hash64<W>(child[it]), rep[it], w.rb);
                     uint64_t *rec = w.sp.rec + (size_t)o * (W + 1);
 #pragma unroll
                     for (int q = 0; q < W; ++q) rec[q] = child[it][q];
