@@ -227,7 +227,7 @@ size_t table_bytes(const HostSys &s)
 struct Layout {
     size_t total = 0;
     size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge, st_spawn, st_att;
-    size_t part_red, part_mrg;
+    size_t part_red, part_mrg, newdet;
     size_t main[2][6];
     size_t sp[7];
     size_t u[4];
@@ -271,6 +271,7 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.att = take(8 * (size_t)(mcap + 1));
     L.span = take(8 * (size_t)(span_capacity(mcap, scap, W) + 2));
     L.mpart = take(8 * (size_t)(tiles_of(mcap + scap, 512) + 2));
+    L.newdet = take((size_t)mcap + 16);
     L.st_scan = take(8 * (size_t)tiles_of(mcap, 2048));
     L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, 4096));
     L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
@@ -783,6 +784,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.att_off = (long long *)(c->ws + c->L.att);
     w.span_lo = (long long *)(c->ws + c->L.span);
     w.mpart = (long long *)(c->ws + c->L.mpart);
+    w.newdet = (uint8_t *)(c->ws + c->L.newdet);
     w.st_scan = (unsigned long long *)(c->ws + c->L.st_scan);
     w.st_sort = (unsigned long long *)(c->ws + c->L.st_sort);
     w.st_red = (unsigned long long *)(c->ws + c->L.st_red);
@@ -909,8 +911,11 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
 
     // grids: persistent tile kernels sized to the resident capacity
     int dev = 0, ncu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) {
+        fq_destroy(c);
+        return FQ_EHIP;
+    }
     c->grids.scan = ncu * occupancy_blocks(3);
     c->grids.sort = ncu * occupancy_blocks(0);
     c->grids.merge = std::min(ncu * occupancy_blocks(1), PART_MAX_BLOCKS);
@@ -1444,9 +1449,9 @@ void fq_destroy(fq_ctx *c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    if (c->h_ctl) hipHostFree(c->h_ctl);
-    if (c->h_hist) hipHostFree(c->h_hist);
-    if (c->h_shift) hipHostFree(c->h_shift);
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    if (c->h_hist) (void)hipHostFree(c->h_hist);
+    if (c->h_shift) (void)hipHostFree(c->h_shift);
     delete c;
 }
 

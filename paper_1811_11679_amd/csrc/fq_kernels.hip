@@ -1330,6 +1330,7 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
                 }
                 w.nxt.pop[o] = p;
                 w.nxt.kdiag[o] = s_kd[slot];
+                w.newdet[o] = slot >= la ? 1 : 0;
                 w.nxt.dslot[o] = ds;
                 if (ds >= 0) w.ds.pos[(size_t)rep * w.ds.n + ds] = (int32_t)o;
                 const long long ap = p < 0 ? -(long long)p : (long long)p;
@@ -1369,6 +1370,7 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
 // and evaluates them one per thread, so no lane idles on unmarked entries;
 // for a single replica the diagonal's tables are read from LDS.
 constexpr int ND_T = 256, ND_CHUNK = 4096;
+static_assert(ND_CHUNK == ND_T * 16, "each thread scans 16 new-determinant flags");
 
 template <int KIND, int W>
 __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
@@ -1423,11 +1425,19 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
     for (long long base = (long long)blockIdx.x * ND_CHUNK; base < n; base += (long long)gridDim.x * ND_CHUNK) {
         if (threadIdx.x == 0) s_n = 0;
         __syncthreads();
-        for (int q = threadIdx.x; q < ND_CHUNK; q += ND_T) {
-            const long long i = base + q;
-            if (i < n) {
-                const double kd = w.nxt.kdiag[i];
-                if (kd != kd) s_q[atomicAdd(&s_n, 1)] = (uint32_t)q;
+        // the merge's new-determinant flags, 16 per thread
+        {
+            const int q0 = threadIdx.x * 16;
+            const long long i0 = base + q0;
+            if (i0 + 16 <= n) {
+                const uint4 f = *(const uint4 *)(w.newdet + i0);
+                const uint32_t fw[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    if ((fw[b >> 2] >> (8 * (b & 3))) & 0xFFu) s_q[atomicAdd(&s_n, 1)] = (uint32_t)(q0 + b);
+            } else {
+                for (int b = 0; b < 16 && i0 + b < n; ++b)
+                    if (w.newdet[i0 + b]) s_q[atomicAdd(&s_n, 1)] = (uint32_t)(q0 + b);
             }
         }
         __syncthreads();
@@ -1760,7 +1770,7 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     // one after every launch of the iteration
     int e = 0;
     auto rec = [&]() {
-        if (ev) hipEventRecord(ev[e++], s);
+        if (ev) (void)hipEventRecord(ev[e++], s);
     };
     rec();
     k_begin<<<1, 256, 0, s>>>(w);
@@ -1866,14 +1876,16 @@ hipError_t enqueue_setup(int what, int kind, const Work &w, DevSys *sys, int n_s
 int occupancy_blocks(int which)
 {
     int nb = 1;
+    hipError_t e = hipSuccess;
     switch (which) {
-    case 0: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass, OS_T, 0); break;
-    case 1: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false>, MG_T, 0); break;
-    case 2: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce<2>, RD_T, 0); break;
-    case 3: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan_attempts, SCAN_T, 0); break;
-    case 4: hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false, true>, SP_T, 8192); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass, OS_T, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false>, MG_T, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce<2>, RD_T, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan_attempts, SCAN_T, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false, true>, SP_T, 8192); break;
     default: break;
     }
+    if (e != hipSuccess) nb = 1;  // a persistent grid of one block per CU still covers every tile
     return nb < 1 ? 1 : nb;
 }
 
