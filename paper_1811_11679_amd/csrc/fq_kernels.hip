@@ -108,6 +108,42 @@ __device__ T block_excl_scan(T v, T &total, T *lds /* 8 entries */)
     return base + x - v;
 }
 
+// two exclusive block scans at once (one pair of barriers)
+__device__ void block_excl_scan2(long long v, long long u, long long &ex_v, long long &ex_u, long long &tot_v,
+                                 long long &tot_u, long long *lds /* 16 entries */)
+{
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    long long x = v, y = u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long a = __shfl_up(x, o, 64), b = __shfl_up(y, o, 64);
+        if (lane >= o) {
+            x += a;
+            y += b;
+        }
+    }
+    if (lane == 63) {
+        lds[wid] = x;
+        lds[8 + wid] = y;
+    }
+    __syncthreads();
+    long long bv = 0, bu = 0, tv = 0, tu = 0;
+    const int nw = blockDim.x >> 6;
+    for (int w = 0; w < nw; ++w) {
+        if (w < wid) {
+            bv += lds[w];
+            bu += lds[8 + w];
+        }
+        tv += lds[w];
+        tu += lds[8 + w];
+    }
+    tot_v = tv;
+    tot_u = tu;
+    ex_v = bv + x - v;
+    ex_u = bu + y - u;
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // estimator accumulation. A thread sums its values in registers for one
 // replica at a time; when it moves on to another replica (and at the end of
@@ -1100,7 +1136,7 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
     __shared__ long long s_nb_sum;
     __shared__ int s_pa_ok, s_nb_ok;
     __shared__ long long s_tile, s_base, s_abase;
-    __shared__ long long s_red[8];
+    __shared__ long long s_red[16];
     const long long na = c->n_main, nb = c->n_uniq;
     const long long ntiles = (na + nb + TILE - 1) / TILE;
     const uint32_t t = c->t;
@@ -1280,9 +1316,8 @@ __global__ __launch_bounds__(MG_T) void k_merge(Work w)
             const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
             asum += attempts_of(s_val[slot], w.rep[rep].bits, c);
         }
-        long long tot, atot;
-        const long long ex = block_excl_scan<long long>((long long)cnt, tot, s_red);
-        const long long aex = block_excl_scan<long long>(asum, atot, s_red);
+        long long tot, atot, ex, aex;
+        block_excl_scan2((long long)cnt, asum, ex, aex, tot, atot, s_red);
         if (threadIdx.x < 64) {
             const long long lb_ = lookback(w.st_merge, tile, epoch, tot);
             if (threadIdx.x == 0) s_base = lb_;
