@@ -1029,13 +1029,16 @@ __global__ void k_fixup(Work w)
 // merges its run of positions from LDS, writes each result into the source
 // slot, and the kept entries leave in merge order with coalesced stores.
 // ---------------------------------------------------------------------------
-constexpr int MG_T = 256;
+// 512 threads of two positions each: a tile's dependent phases (ticket,
+// partition, staging, look-back) are shorter than with 256 threads of four,
+// and two such blocks fit a compute unit's registers and LDS
+constexpr int MG_T = 512;
 #ifndef FQ_MERGE_ITEMS
-#define FQ_MERGE_ITEMS 4  // merge positions per thread and tile, keys of up to two words
+#define FQ_MERGE_ITEMS 2  // merge positions per thread and tile, keys of up to two words
 #endif
 template <int W>
 struct MergeCfg {
-    static constexpr int I = W <= 2 ? FQ_MERGE_ITEMS : 2;
+    static constexpr int I = W <= 2 ? FQ_MERGE_ITEMS : 1;
     static constexpr int TILE = MG_T * I;
 };
 
