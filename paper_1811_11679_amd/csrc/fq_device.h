@@ -154,41 +154,43 @@ __device__ __forceinline__ double parity_between(const uint64_t (&k)[W], int P, 
     return (c & 1) ? -1.0 : 1.0;
 }
 
-// position of the r-th (0-based) set bit of a word
+// position of the r-th (0-based) set bit of a word: choose the 32-bit half,
+// then halve the window with 32-bit popcounts
 __device__ __forceinline__ int select_in_word(uint64_t x, int r)
 {
-    int pos = 0;
+    const uint32_t lo = (uint32_t)x;
+    const int c0 = __popc(lo);
+    const bool up = r >= c0;
+    uint32_t v = up ? (uint32_t)(x >> 32) : lo;
+    int pos = up ? 32 : 0;
+    r = up ? r - c0 : r;
 #pragma unroll
-    for (int s = 32; s > 0; s >>= 1) {
-        const uint64_t low = x & ((1ull << s) - 1);
-        const int c = __popcll(low);
-        if (r >= c) {
-            r -= c;
-            x >>= s;
-            pos += s;
-        }
+    for (int s = 16; s > 0; s >>= 1) {
+        const int c = __popc(v & ((1u << s) - 1u));
+        const bool hi = r >= c;
+        r = hi ? r - c : r;
+        v = hi ? v >> s : v;
+        pos = hi ? pos + s : pos;
     }
     return pos;
 }
 
+// position of the r-th set bit of a key, -1 if it has fewer: the word is
+// chosen first (selects, no divergence), then searched once
 template <int W>
 __device__ __forceinline__ int select_bit(const uint64_t (&k)[W], int r)
 {
-    int res = -1;
-    bool done = false;
+    int wsel = -1;
+    uint64_t x = 0;
 #pragma unroll
     for (int i = 0; i < W; ++i) {
         const int c = __popcll(k[i]);
-        if (!done) {
-            if (r < c) {
-                res = 64 * i + select_in_word(k[i], r);
-                done = true;
-            } else {
-                r -= c;
-            }
-        }
+        const bool here = wsel < 0 && r < c;
+        x = here ? k[i] : x;
+        r = (wsel < 0 && !here) ? r - c : r;
+        wsel = here ? i : wsel;
     }
-    return res;
+    return wsel < 0 ? -1 : 64 * wsel + select_in_word(x, r);
 }
 
 template <int W>
