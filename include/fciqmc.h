@@ -248,6 +248,20 @@ fq_status fq_iteration_times(const fq_ctx *ctx, double *ms, int64_t cap, int64_t
  * kernels one by one and takes precedence. */
 fq_status fq_set_graph(fq_ctx *ctx, int32_t on);
 
+/* Sort-key truncation, for tests of the hash-collision path (the annihilation
+ * of Sec. 2.4 must combine walkers on one determinant however the list is
+ * ordered). Only the top `bits` (1..64) bits of each determinant's 64-bit hash
+ * then enter its sort key, so that many determinants share a sort key and
+ * ties are broken by the determinant itself, in the main list and in the
+ * spawned list (collision fix-up and repeated reduction every iteration).
+ * Results are unchanged: the random streams are keyed by the full hash.
+ * Needs two or more instances (FQ_EINVAL otherwise: a single instance's
+ * kernels use the sort key as the hash) and must precede the deterministic
+ * space (FQ_ESTATE). The current list is re-sorted on the host. A run of
+ * equal sort keys holding more than 64 determinants fails the iteration
+ * with FQ_ESTATE. */
+fq_status fq_set_sort_key_bits(fq_ctx *ctx, int32_t bits);
+
 /* Launch geometry of the persistent kernels, in blocks: [0] spawn, [1] merge,
  * [2] radix-sort pass, [3] segmented reduction, [4] new-determinant
  * diagonals. A value <= 0 keeps the current one. Results do not depend on

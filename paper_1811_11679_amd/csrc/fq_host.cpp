@@ -323,6 +323,7 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
 
 struct fq_ctx {
     int R = 0, W = 0, kind = 0, rb = 0;
+    uint64_t hmask = ~0ull;  // hash bits that enter a sort key
     hipStream_t stream = nullptr;
     std::vector<HostSys> sys;
     std::vector<fq_qmc> qmc;
@@ -614,7 +615,7 @@ fq_status select_detspace(fq_ctx *c)
                 HostEntry x;
                 std::memset(&x, 0, sizeof(x));
                 for (int q = 0; q < W; ++q) x.key[q] = c->dkeys[r][(size_t)d * W + q];
-                x.skey = host_skey(host_hash(x.key, W), (uint32_t)r, c->rb);
+                x.skey = host_skey(host_hash(x.key, W) & c->hmask, (uint32_t)r, c->rb);
                 x.dslot = -1;
                 auto it = std::lower_bound(e.begin(), e.end(), x,
                                            [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, W); });
@@ -634,7 +635,7 @@ fq_status select_detspace(fq_ctx *c)
             HostEntry x;
             std::memset(&x, 0, sizeof(x));
             for (int q = 0; q < W; ++q) x.key[q] = c->dkeys[r][(size_t)d * W + q];
-            x.skey = host_skey(host_hash(x.key, W), (uint32_t)r, c->rb);
+            x.skey = host_skey(host_hash(x.key, W) & c->hmask, (uint32_t)r, c->rb);
             auto it = std::lower_bound(e.begin(), e.end(), x,
                                        [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, W); });
             const int64_t i = it - e.begin();
@@ -650,7 +651,7 @@ fq_status select_detspace(fq_ctx *c)
     for (size_t x = 0; x < nd; ++x) {
         uint64_t k[MAXW] = {0};
         for (int q = 0; q < W; ++q) k[q] = dk[(size_t)q * nd + x];
-        sks[x] = host_skey(host_hash(k, W), (uint32_t)(x / D), c->rb);
+        sks[x] = host_skey(host_hash(k, W) & c->hmask, (uint32_t)(x / D), c->rb);
     }
     std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
         if (sks[a] != sks[b]) return sks[a] < sks[b];
@@ -826,6 +827,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.span_cap = span_capacity(main_capacity, spawn_capacity, c->W);
     w.R = c->R;
     w.rb = c->rb;
+    w.hmask = c->hmask;
     w.W = c->W;
     w.hist_len = HIST_LEN;
     c->cur = 0;
@@ -968,7 +970,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         HostEntry &e = init[r];
         std::memset(&e, 0, sizeof(e));
         std::memcpy(e.key, c->sys[r].ref, sizeof(e.key));
-        e.skey = host_skey(host_hash(e.key, c->W), (uint32_t)r, c->rb);
+        e.skey = host_skey(host_hash(e.key, c->W) & c->hmask, (uint32_t)r, c->rb);
         const double scale = std::ldexp(1.0, qmc[r].fixed_point_bits);
         const double u = std::floor(qmc[r].init_pop * scale + 0.5);
         if (u > 2147483647.0) { fq_destroy(c); return FQ_EOVERFLOW; }
@@ -1080,6 +1082,9 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             return fail(c, FQ_ESTATE, "device iteration counter " + std::to_string(ctl.t) + " after a block ending at " +
                                           std::to_string(stop));
         if (ctl.err) {
+            // ctl is the pinned host copy of the device counters, which the
+            // restore below overwrites: keep the error bits
+            const uint32_t err = ctl.err;
             const int64_t tf = ctl.t;  // failing iteration
             c->cur = cur0 ^ (int)((tf - 1 - t0) & 1);
             set_main_views(c);
@@ -1118,9 +1123,10 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                     c->last[r] = e;
                 }
             c->t = tf - 1;
-            if (ctl.err & (ERR_OVERFLOW | ERR_ATTEMPTS)) return fail(c, FQ_EOVERFLOW, "population or spawn exceeds the fixed-point range");
-            if (ctl.err & ERR_COLLISION) return fail(c, FQ_ESTATE, "spawned list holds an implausibly long run of equal sort keys");
-            return fail(c, FQ_ECAPACITY, (ctl.err & ERR_SPAWN_CAP) ? "spawn capacity exceeded" : "main list capacity exceeded");
+            if (err & (ERR_OVERFLOW | ERR_ATTEMPTS)) return fail(c, FQ_EOVERFLOW, "population or spawn exceeds the fixed-point range");
+            if (err & ERR_COLLISION) return fail(c, FQ_ESTATE, "more than 64 spawned determinants share one sort key (not a hash collision)");
+            if (err & ERR_SPAWN_CAP) return fail(c, FQ_ECAPACITY, "spawn capacity exceeded");
+            return fail(c, FQ_ECAPACITY, "main list capacity exceeded");
         }
         for (int64_t it = t0 + 1; it <= stop; ++it) {
             for (int r = 0; r < c->R; ++r) {
@@ -1267,7 +1273,7 @@ fq_status fq_import_walkers(fq_ctx *c, int32_t instance, const uint64_t *keys, c
         HostEntry x;
         std::memset(&x, 0, sizeof(x));
         for (int q = 0; q < c->W; ++q) x.key[q] = keys[(size_t)i * c->W + q];
-        x.skey = host_skey(host_hash(x.key, c->W), (uint32_t)instance, c->rb);
+        x.skey = host_skey(host_hash(x.key, c->W) & c->hmask, (uint32_t)instance, c->rb);
         x.pop = pops[i];
         x.dslot = -1;
         add.push_back(x);
@@ -1409,6 +1415,30 @@ fq_status fq_set_graph(fq_ctx *c, int32_t on)
     c->graph = on != 0;
     if (!c->graph) drop_graphs(c);
     return FQ_OK;
+}
+
+fq_status fq_set_sort_key_bits(fq_ctx *c, int32_t bits)
+{
+    if (!c) return FQ_EINVAL;
+    if (bits < 1 || bits > 64) return fail(c, FQ_EINVAL, "sort-key hash bits must lie in 1..64");
+    if (c->R < 2)
+        return fail(c, FQ_EINVAL, "sort-key truncation needs two or more instances (a single instance's kernels use the "
+                                  "sort key as the determinant's hash)");
+    if (c->ss_active) return fail(c, FQ_ESTATE, "sort-key truncation must precede the deterministic space");
+    c->hmask = bits == 64 ? ~0ull : ~((1ull << (64 - bits)) - 1);
+    c->w.hmask = c->hmask;
+    // the current list in the order of the new sort keys (upload_main drops
+    // the captured graphs, whose kernel arguments hold the old mask)
+    std::vector<HostEntry> e;
+    int64_t n = 0;
+    fq_status st = download_main(c, e, n);
+    if (st != FQ_OK) return st;
+    for (auto &x : e) {
+        const uint32_t rep = c->rb ? (uint32_t)(x.skey >> (64 - c->rb)) : 0u;
+        x.skey = host_skey(host_hash(x.key, c->W) & c->hmask, rep, c->rb);
+    }
+    std::sort(e.begin(), e.end(), [&](const HostEntry &a, const HostEntry &b) { return entry_less(a, b, c->W); });
+    return upload_main(c, e);
 }
 
 fq_status fq_set_launch(fq_ctx *c, const int32_t *blocks, int32_t n)

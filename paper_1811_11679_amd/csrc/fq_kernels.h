@@ -148,6 +148,7 @@ struct Work {
     DetSpace ds;
     long long main_cap, spawn_cap, span_cap;
     int32_t R, rb, W, hist_len;
+    uint64_t hmask;  // hash bits that enter a sort key (all but in collision tests)
     int32_t lds_tables;  // bytes of UEG tables the spawn kernel stages in LDS (0: read from global)
     int32_t lds_diag;    // bytes of diagonal tables the new-determinant kernel stages in LDS
 };

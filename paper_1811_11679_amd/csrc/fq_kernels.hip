@@ -538,7 +538,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                     bool skip = false;
                     if (pin_d) {
                         // discard spawns that stay inside the deterministic space
-                        const uint64_t cs = make_skey(hash64<W>(child[it]), rep[it], w.rb);
+                        const uint64_t cs = make_skey(hash64<W>(child[it]) & w.hmask, rep[it], w.rb);
                         const int nd = w.ds.n * w.R;
                         int l = 0, hh = nd;
                         while (l < hh) {
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 uint64_t key[W];
 #pragma unroll
                 for (int q = 0; q < W; ++q) key[q] = s_rkey[q][p];
-                w.sp.skey[o] = make_skey(hash64<W>(key), MULTI ? s_rrep[p] : 0u, w.rb);
+                w.sp.skey[o] = make_skey(hash64<W>(key) & w.hmask, MULTI ? s_rrep[p] : 0u, w.rb);
                 uint64_t *rec = w.sp.rec + (size_t)o * (W + 1);
 #pragma unroll
                 for (int q = 0; q < W; ++q) rec[q] = key[q];
@@ -657,7 +657,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
             for (int it = 0; it < SP_I; ++it)
                 if (has[it] && rk[it] >= SP_STAGE) {
                     const long long o = base + rk[it];
-                    w.sp.skey[o] = make_skey(hash64<W>(child[it]), rep[it], w.rb);
+                    w.sp.skey[o] = make_skey(hash64<W>(child[it]) & w.hmask, rep[it], w.rb);
                     uint64_t *rec = w.sp.rec + (size_t)o * (W + 1);
 #pragma unroll
                     for (int q = 0; q < W; ++q) rec[q] = child[it][q];
@@ -964,18 +964,31 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
     acc_finish(acc, any && acc.rep >= 0, tab, rl, w.acc, w.part_red);
 }
 
-// Rare path: equal sort keys holding different determinants are put in key
-// order (insertion sort of the run), and the reduction is redone. Runs are
-// bounded: such a run only arises from 64-bit hash collisions.
-constexpr long long FIXUP_MAX_RUN = 4096;
+// Rare path: equal sort keys holding different determinants (hash
+// collisions) are put in key order and the reduction is redone. A run of
+// equal sort keys can be long, since a determinant may receive many spawns:
+// it is only reordered when it holds more than one determinant, by moving the
+// entries of its smallest remaining determinant to the front, one determinant
+// at a time (stable; run length x distinct determinants gathers, through the
+// radix sort's ping-pong index buffer, which is free at this point).
+constexpr int FIXUP_MAX_KEYS = 64;
+
+template <int W>
+__device__ __forceinline__ void rec_key(const Work &w, uint32_t j, uint64_t (&k)[W])
+{
+#pragma unroll
+    for (int q = 0; q < W; ++q) k[q] = w.sp.rec[(size_t)j * (W + 1) + q];
+}
+
 template <int W>
 __global__ void k_fixup(Work w)
 {
     Ctl *c = w.ctl;
     if (c->err || !c->collision) return;
     const long long n = (long long)min(c->n_spawn, (unsigned long long)w.spawn_cap);
-    uint64_t *skey = w.sp.skey;
+    const uint64_t *skey = w.sp.skey;
     uint32_t *idx = w.sp.idx;
+    uint32_t *tmp = w.sp.idx2;
     const long long gs = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) {
         w.u.sum[i] = 0;
@@ -988,30 +1001,49 @@ __global__ void k_fixup(Work w)
         }
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) {
         if (i > 0 && skey[i - 1] == skey[i]) continue;
+        uint64_t k0[W];
+        rec_key<W>(w, idx[i], k0);
         long long e = i + 1;
-        while (e < n && e - i <= FIXUP_MAX_RUN && skey[e] == skey[i]) ++e;
-        if (e - i < 2) continue;
-        if (e - i > FIXUP_MAX_RUN) {
-            // equal sort keys this long cannot come from hash collisions: refuse
-            atomicOr(&c->err, ERR_COLLISION);
-            continue;
-        }
-        for (long long a = i + 1; a < e; ++a) {
-            const uint32_t ja = idx[a];
-            uint64_t ka[W];
-#pragma unroll
-            for (int q = 0; q < W; ++q) ka[q] = w.sp.rec[(size_t)ja * (W + 1) + q];
-            long long b = a - 1;
-            while (b >= i) {
-                uint64_t kb[W];
-                const uint32_t jb = idx[b];
-#pragma unroll
-                for (int q = 0; q < W; ++q) kb[q] = w.sp.rec[(size_t)jb * (W + 1) + q];
-                if (key_cmp<W>(kb, ka) <= 0) break;
-                idx[b + 1] = jb;
-                --b;
+        bool mixed = false;
+        while (e < n && skey[e] == skey[i]) {
+            if (!mixed) {
+                uint64_t ke[W];
+                rec_key<W>(w, idx[e], ke);
+                mixed = !key_eq<W>(ke, k0);
             }
-            idx[b + 1] = ja;
+            ++e;
+        }
+        if (!mixed) continue;
+        for (long long a = i; a < e; ++a) tmp[a] = idx[a];
+        long long pos = i;
+        uint64_t prev[W];
+        for (int d = 0;; ++d) {
+            // the smallest determinant of the run above the last one placed
+            bool found = false;
+            uint64_t best[W];
+            for (long long a = i; a < e; ++a) {
+                uint64_t ka[W];
+                rec_key<W>(w, tmp[a], ka);
+                if (d > 0 && key_cmp<W>(ka, prev) <= 0) continue;
+                if (!found || key_cmp<W>(ka, best) < 0) {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) best[q] = ka[q];
+                    found = true;
+                }
+            }
+            if (!found) break;
+            if (d == FIXUP_MAX_KEYS) {
+                // this many determinants on one sort key cannot come from hash collisions
+                atomicOr(&c->err, ERR_COLLISION);
+                break;
+            }
+            for (long long a = i; a < e; ++a) {
+                uint64_t ka[W];
+                rec_key<W>(w, tmp[a], ka);
+                if (key_eq<W>(ka, best)) idx[pos++] = tmp[a];
+            }
+#pragma unroll
+            for (int q = 0; q < W; ++q) prev[q] = best[q];
         }
     }
 }

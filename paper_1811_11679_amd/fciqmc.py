@@ -24,7 +24,7 @@ SS_FP64, SS_SPLIT_BF16 = 0, 1
 C_API = ["fq_workspace_bytes", "fq_init_system", "fq_step", "fq_estimators", "fq_estimator_history",
          "fq_export_walkers", "fq_import_walkers", "fq_shift_state", "fq_export_spawns", "fq_detspace", "fq_info",
          "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_iteration_times", "fq_set_graph",
-         "fq_set_launch", "fq_get_launch", "fq_last_error", "fq_destroy"]
+         "fq_set_sort_key_bits", "fq_set_launch", "fq_get_launch", "fq_last_error", "fq_destroy"]
 LAUNCH_KERNELS = ["spawn", "merge", "sort", "reduce", "new_diag"]
 
 KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "sort_hist"] + \
@@ -123,6 +123,8 @@ def load_library():
     L.fq_shift_state.restype = C.c_int32
     L.fq_set_graph.argtypes = [P, C.c_int32]
     L.fq_set_graph.restype = C.c_int32
+    L.fq_set_sort_key_bits.argtypes = [P, C.c_int32]
+    L.fq_set_sort_key_bits.restype = C.c_int32
     L.fq_set_launch.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
     L.fq_set_launch.restype = C.c_int32
     L.fq_get_launch.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
@@ -286,6 +288,10 @@ class Context:
 
     def set_graph(self, on=True):
         self._check(self.lib.fq_set_graph(self.ctx, int(on)))
+
+    def set_sort_key_bits(self, bits):
+        """Only the top `bits` hash bits enter the sort keys (hash-collision tests)."""
+        self._check(self.lib.fq_set_sort_key_bits(self.ctx, int(bits)))
 
     def set_launch(self, blocks):
         """blocks: {kernel name: blocks} for names in LAUNCH_KERNELS"""

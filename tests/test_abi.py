@@ -46,3 +46,4 @@ def test_workspace_size_and_argument_checks():
     # invalid arguments are rejected before any device call
     assert L.fq_init_system(ctypes.byref(ctx), arr, qa, None, 1, 0, 100, None, 0, None) == F.FQ_EINVAL
     assert L.fq_step(None, 1) == F.FQ_EINVAL
+    assert L.fq_set_sort_key_bits(None, 8) == F.FQ_EINVAL

@@ -170,7 +170,7 @@ def test_capacity_overflow_rolls_back_to_iteration_start():
     orun = O.Run(oracle_system(w["system"]), oracle_qmc(w["system"], q))
     with pytest.raises(F.FqError) as ei:
         ctx.step(200)
-    assert ei.value.code == F.FQ_ECAPACITY
+    assert ei.value.code == F.FQ_ECAPACITY and "spawn capacity exceeded" in str(ei.value)
     t = ctx.estimators()["iteration"]
     orun.step(int(t))
     assert_same_lists(ctx, orun, where="state at the start of the failing iteration")
