@@ -100,6 +100,17 @@ def cpu_baseline(state, budget_s=20.0, max_iter=50, max_dets=4_000_000):
                       f"single thread"}
 
 
+def batch_capacity(inst):
+    """Determinant and spawn capacities for a group of instances. Death and
+    cloning shrink populations continuously, so an instance can hold tens of
+    determinants per walker (up to about 30 measured at 123 plane waves): the
+    main list gets 40 entries per target walker, the spawn list 4 spawns."""
+    def cap(members, n_now=0):
+        tot = sum(inst[i][1]["target_population"] for i in members)
+        return int(max(40 * tot, 2 * n_now)), int(4 * tot)
+    return cap
+
+
 HIST_FIELDS = ("iteration", "n_walkers_units", "n_occupied", "ref_pop_units", "n_spawned", "n_spawn_events",
                "death_sum", "spawn_sum", "rejected_sum", "n_rejected_units", "n_sign_flips", "num_limbs", "shift")
 
