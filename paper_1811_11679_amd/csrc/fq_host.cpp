@@ -920,7 +920,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     }
     c->grids.scan = ncu * occupancy_blocks(3);
     c->grids.sort = ncu * occupancy_blocks(0);
-    c->grids.merge = std::min(ncu * occupancy_blocks(1), PART_MAX_BLOCKS);
+    c->grids.merge = std::min(ncu * occupancy_blocks(c->W <= 2 ? 1 : 5), PART_MAX_BLOCKS);
     c->grids.reduce = std::min(ncu * occupancy_blocks(2), PART_MAX_BLOCKS);
     c->grids.part = ncu * 4;
     c->grids.spawn = ncu * occupancy_blocks(4);

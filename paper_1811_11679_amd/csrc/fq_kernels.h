@@ -169,6 +169,9 @@ hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_
 // deterministic space
 hipError_t enqueue_setup(int what, int kind, const Work &w, DevSys *sys, int n_sys, MainList L, long long n,
                          const uint64_t *dk, double *K, hipStream_t s);
+// resident blocks per compute unit of a persistent kernel: 0 sort pass,
+// 1 merge (keys of up to two words), 2 reduce, 3 attempt scan, 4 spawn,
+// 5 merge (longer keys)
 int occupancy_blocks(int which);
 
 }  // namespace fq

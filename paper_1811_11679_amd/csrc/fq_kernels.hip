@@ -1061,17 +1061,19 @@ __global__ void k_fixup(Work w)
 // merges its run of positions from LDS, writes each result into the source
 // slot, and the kept entries leave in merge order with coalesced stores.
 // ---------------------------------------------------------------------------
-// 512 threads of two positions each: a tile's dependent phases (ticket,
-// partition, staging, look-back) are shorter than with 256 threads of four,
-// and two such blocks fit a compute unit's registers and LDS
-constexpr int MG_T = 512;
+// Keys of up to two words: 512 threads of two positions each, whose tile's
+// dependent phases (ticket, partition, staging, look-back) are shorter than
+// with 256 threads of four; two such blocks fit a compute unit's registers
+// and LDS. Longer keys: 256 threads of two positions (their LDS slice is
+// larger, and three such blocks per compute unit measured faster).
 #ifndef FQ_MERGE_ITEMS
 #define FQ_MERGE_ITEMS 2  // merge positions per thread and tile, keys of up to two words
 #endif
 template <int W>
 struct MergeCfg {
-    static constexpr int I = W <= 2 ? FQ_MERGE_ITEMS : 1;
-    static constexpr int TILE = MG_T * I;
+    static constexpr int T = W <= 2 ? 512 : 256;
+    static constexpr int I = W <= 2 ? FQ_MERGE_ITEMS : 2;
+    static constexpr int TILE = T * I;
 };
 
 template <int W>
@@ -1153,11 +1155,11 @@ __device__ __forceinline__ long long attempts_of(long long p, int bits, Ctl *c)
 }
 
 template <int KIND, int W, bool MULTI>
-__global__ __launch_bounds__(MG_T) void k_merge(Work w)
+__global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
 {
     Ctl *c = w.ctl;
     if (c->err) return;
-    constexpr int MI = MergeCfg<W>::I, TILE = MergeCfg<W>::TILE;
+    constexpr int MG_T = MergeCfg<W>::T, MI = MergeCfg<W>::I, TILE = MergeCfg<W>::TILE;
     __shared__ uint64_t s_sk[TILE];
     __shared__ uint64_t s_key[W][TILE];
     __shared__ long long s_val[TILE];   // main: population, then the new one; spawned: sum
@@ -1885,9 +1887,9 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     k_merge_partition<W><<<g.part, 256, 0, s>>>(w);
     rec();
     if (w.R > 1)
-        k_merge<KIND, W, true><<<g.merge, MG_T, accb, s>>>(w);
+        k_merge<KIND, W, true><<<g.merge, MergeCfg<W>::T, accb, s>>>(w);
     else
-        k_merge<KIND, W, false><<<g.merge, MG_T, accb, s>>>(w);
+        k_merge<KIND, W, false><<<g.merge, MergeCfg<W>::T, accb, s>>>(w);
     rec();
     k_new_diag<KIND, W><<<g.newdiag, ND_T, w.lds_diag, s>>>(w);
     rec();
@@ -1949,7 +1951,8 @@ int occupancy_blocks(int which)
     hipError_t e = hipSuccess;
     switch (which) {
     case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass, OS_T, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false>, MG_T, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false>, MergeCfg<2>::T, 0); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 8, false>, MergeCfg<8>::T, 0); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce<2>, RD_T, 0); break;
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan_attempts, SCAN_T, 0); break;
     case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false, true>, SP_T, 8192); break;
