@@ -484,7 +484,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 #pragma unroll
                 for (int q = 0; q < W; ++q) pkey[it][q] = w.cur.key[(size_t)q * w.main_cap + i];
                 pn0[it] = w.cur.pop[i];
-                pdsl[it] = w.cur.dslot[i];
+                pdsl[it] = ss ? w.cur.dslot[i] : -1;  // read only with the deterministic space active
                 ppsk[it] = w.cur.skey[i];
             }
         }
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 #pragma unroll
                     for (int q = 0; q < W; ++q) key[q] = w.cur.key[(size_t)q * w.main_cap + i];
                     n0 = w.cur.pop[i];
-                    dsl = w.cur.dslot[i];
+                    dsl = ss ? w.cur.dslot[i] : -1;
                     psk = w.cur.skey[i];
                 }
                 rep[it] = MULTI ? skey_rep(psk, w.rb) : 0u;
@@ -1203,7 +1203,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
             for (int x = 0; x < W; ++x) s_key[x][q] = w.cur.key[(size_t)x * w.main_cap + g];
             s_val[q] = w.cur.pop[g];
             s_kd[q] = w.cur.kdiag[g];
-            s_meta[q] = w.cur.dslot[g];
+            s_meta[q] = ss ? w.cur.dslot[g] : -1;
         }
         for (int q = threadIdx.x; q < lb; q += MG_T) {
             const long long g = j0 + q;
@@ -1403,7 +1403,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
                 w.nxt.pop[o] = p;
                 w.nxt.kdiag[o] = s_kd[slot];
                 w.newdet[o] = slot >= la ? 1 : 0;
-                w.nxt.dslot[o] = ds;
+                if (ss) w.nxt.dslot[o] = ds;
                 if (ds >= 0) w.ds.pos[(size_t)rep * w.ds.n + ds] = (int32_t)o;
                 const long long ap = p < 0 ? -(long long)p : (long long)p;
                 acc_switch(acc, rep, tab, rl, w.acc);
