@@ -26,23 +26,26 @@ METRIC = "walker updates/s per FCIQMC iteration, plain vs batched; annihilation 
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(hist_prev, hist, W, ds_active=False):
+def algorithmic_bytes(hist_prev, hist, W, ds_active=False, instances=1):
     """Bytes each kernel must move per iteration (reads + writes of the data it
     owns). The deterministic slot of a main entry (4 bytes) is read and written
-    only while a deterministic space is active."""
+    only while a deterministic space is active; its sort key (8 bytes) is
+    stored only when several instances share the list (for one it is the
+    key's hash, recomputed)."""
     out = {}
     nm, nm2 = hist_prev["n_occupied"], hist["n_occupied"]
     ns, nu = hist["n_spawned"], hist["n_spawn_events"]
     kb = 8 * W
     ds = 4 if ds_active else 0
-    out["spawn"] = nm * (kb + 8 + 4 + ds + 8) + ns * (8 + kb + 8 + 8 + 4)
+    sk = 8 if instances > 1 else 0
+    out["spawn"] = nm * (kb + sk + 4 + ds + 8) + ns * (8 + kb + 8 + 8 + 4)
     out["sort_pass0"] = ns * (8 + 8 + 4)
     for p in range(1, 8):
         out[f"sort_pass{p}"] = ns * (8 + 4) * 2
     out["sort_hist"] = ns * 8
     out["reduce"] = ns * (8 + 4 + kb + 8) + nu * (8 + kb + 8 + 4)
     # output: skey, key, pop, kdiag, slot, attempt offset and the new-determinant flag
-    out["merge"] = nm * (8 + kb + 4 + 8 + ds) + nu * (8 + kb + 8 + 4) + nm2 * (8 + kb + 4 + 8 + ds + 8 + 1)
+    out["merge"] = nm * (sk + kb + 4 + 8 + ds) + nu * (8 + kb + 8 + 4) + nm2 * (sk + kb + 4 + 8 + ds + 8 + 1)
     out["new_diag"] = nm2 * 8
     return out
 

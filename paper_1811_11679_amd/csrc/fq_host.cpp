@@ -464,8 +464,10 @@ fq_status download_main(fq_ctx *c, std::vector<HostEntry> &out, int64_t &n)
     const MainList &m = c->buf[c->cur];
     std::vector<uint64_t> sk(n), kk((size_t)n * c->W);
     std::vector<int32_t> pp(n), ds(n);
+    // a single instance's kernels keep no sort keys (they are the keys' hashes)
+    const bool stored = c->R > 1;
     if (n) {
-        HIPCHK(c, d2h(c->stream, sk.data(), m.skey, 8 * n));
+        if (stored) HIPCHK(c, d2h(c->stream, sk.data(), m.skey, 8 * n));
         for (int q = 0; q < c->W; ++q)
             HIPCHK(c, d2h(c->stream, kk.data() + (size_t)q * n, m.key + (size_t)q * c->main_cap, 8 * n));
         HIPCHK(c, d2h(c->stream, pp.data(), m.pop, 4 * n));
@@ -473,8 +475,8 @@ fq_status download_main(fq_ctx *c, std::vector<HostEntry> &out, int64_t &n)
     }
     out.resize(n);
     for (int64_t i = 0; i < n; ++i) {
-        out[i].skey = sk[i];
         for (int q = 0; q < MAXW; ++q) out[i].key[q] = q < c->W ? kk[(size_t)q * n + i] : 0;
+        out[i].skey = stored ? sk[i] : host_skey(host_hash(out[i].key, c->W) & c->hmask, 0u, c->rb);
         out[i].pop = pp[i];
         out[i].dslot = ds[i];
     }

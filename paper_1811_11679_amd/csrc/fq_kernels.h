@@ -82,11 +82,11 @@ constexpr int ND_LDS_MAX = 65536;
 __host__ __device__ inline int acc_rows(int R) { return R < ACC_LDS_R ? R : ACC_LDS_R; }
 
 struct MainList {
-    uint64_t *skey;
+    uint64_t *skey;  // sort key; kept for several instances only (one: the key's hash, recomputed)
     uint64_t *key;   // word-major: key[w * cap + i]
     int32_t *pop;
     double *kdiag;   // H_ii - H_00
-    int32_t *dslot;  // index in the deterministic space, -1 if not in it
+    int32_t *dslot;  // index in the deterministic space, -1 if not in it (kept while the space is active)
     int32_t *natt;   // spawning attempts for the next iteration
 };
 

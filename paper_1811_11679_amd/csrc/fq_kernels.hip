@@ -485,7 +485,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 for (int q = 0; q < W; ++q) pkey[it][q] = w.cur.key[(size_t)q * w.main_cap + i];
                 pn0[it] = w.cur.pop[i];
                 pdsl[it] = ss ? w.cur.dslot[i] : -1;  // read only with the deterministic space active
-                ppsk[it] = w.cur.skey[i];
+                ppsk[it] = MULTI ? w.cur.skey[i] : 0;  // one instance: the sort key is the key's hash
             }
         }
         // phase 3: excitation, matrix element, amplitude
@@ -515,12 +515,12 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                     for (int q = 0; q < W; ++q) key[q] = w.cur.key[(size_t)q * w.main_cap + i];
                     n0 = w.cur.pop[i];
                     dsl = ss ? w.cur.dslot[i] : -1;
-                    psk = w.cur.skey[i];
+                    psk = MULTI ? w.cur.skey[i] : 0;
                 }
                 rep[it] = MULTI ? skey_rep(psk, w.rb) : 0u;
                 const RepParams &rp = w.rep[MULTI ? rep[it] : 0u];
                 const DevSys &sy = w.sys[rp.sys];
-                const uint64_t h = MULTI ? hash64<W>(key) : psk;
+                const uint64_t h = hash64<W>(key);
                 const long long an = n0 < 0 ? -(long long)n0 : (long long)n0;
                 const bool pin_d = ss && dsl >= 0;
                 init[it] = (uint8_t)(an > rp.thr || key_eq<W>(key, *(const uint64_t(*)[W])sy.ref) || pin_d);
@@ -1083,6 +1083,17 @@ __device__ __forceinline__ void load_key(const uint64_t *base, long long cap, lo
     for (int q = 0; q < W; ++q) k[q] = base[(size_t)q * cap + i];
 }
 
+// sort key of main entry i: stored for several instances; for one it is the
+// hash of the key, recomputed rather than moved through HBM
+template <int W>
+__device__ __forceinline__ uint64_t main_skey(const Work &w, long long i)
+{
+    if (w.rb) return w.cur.skey[i];
+    uint64_t k[W];
+    load_key<W>(w.cur.key, w.main_cap, i, k);
+    return hash64<W>(k);
+}
+
 // main[i] <= uniq[j] in (sort key, key) order (global memory)
 template <int W>
 __device__ __forceinline__ bool le_ab(const Work &w, long long i, uint64_t si, long long j, uint64_t sj)
@@ -1109,7 +1120,7 @@ __global__ void k_merge_partition(Work w)
         while (lo < hi) {
             const long long mid = (lo + hi) >> 1;
             const long long j = d - 1 - mid;
-            if (le_ab<W>(w, mid, w.cur.skey[mid], j, w.u.skey[j])) lo = mid + 1; else hi = mid;
+            if (le_ab<W>(w, mid, main_skey<W>(w, mid), j, w.u.skey[j])) lo = mid + 1; else hi = mid;
         }
         w.mpart[tile] = lo;
     }
@@ -1198,9 +1209,14 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
         const int la = (int)(i1 - i0), lb = (int)(j1 - j0);
         for (int q = threadIdx.x; q < la; q += MG_T) {
             const long long g = i0 + q;
-            s_sk[q] = w.cur.skey[g];
+            uint64_t k[W];
 #pragma unroll
-            for (int x = 0; x < W; ++x) s_key[x][q] = w.cur.key[(size_t)x * w.main_cap + g];
+            for (int x = 0; x < W; ++x) {
+                k[x] = w.cur.key[(size_t)x * w.main_cap + g];
+                s_key[x][q] = k[x];
+            }
+            // one instance: the sort key is the key's hash, not stored
+            s_sk[q] = MULTI ? w.cur.skey[g] : hash64<W>(k);
             s_val[q] = w.cur.pop[g];
             s_kd[q] = w.cur.kdiag[g];
             s_meta[q] = ss ? w.cur.dslot[g] : -1;
@@ -1216,9 +1232,9 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
         if (threadIdx.x == 0) {
             s_pa_ok = i0 > 0;
             if (i0 > 0) {
-                s_pa_sk = w.cur.skey[i0 - 1];
 #pragma unroll
                 for (int x = 0; x < W; ++x) s_pa_key[x] = w.cur.key[(size_t)x * w.main_cap + i0 - 1];
+                s_pa_sk = MULTI ? w.cur.skey[i0 - 1] : hash64<W>(s_pa_key);
             }
             s_nb_ok = j1 < nb;
             if (j1 < nb) {
@@ -1393,7 +1409,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
                 const DevSys &sy = w.sys[rp.sys];
                 const int32_t p = (int32_t)s_val[slot];
                 const int32_t ds = s_meta[slot];
-                w.nxt.skey[o] = sk;
+                if (MULTI) w.nxt.skey[o] = sk;
                 uint64_t key[W];
 #pragma unroll
                 for (int x = 0; x < W; ++x) {
@@ -1535,7 +1551,7 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
                 }
                 w.nxt.kdiag[i] = e - s0.H00;
             } else {
-                const int rep = (int)skey_rep(w.nxt.skey[i], w.rb);
+                const int rep = w.rb ? (int)skey_rep(w.nxt.skey[i], w.rb) : 0;
                 const DevSys &sy = w.sys[w.rep[rep].sys];
                 w.nxt.kdiag[i] = diag_element<KIND, W>(sy, key) - sy.H00;
             }
