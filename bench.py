@@ -30,14 +30,14 @@ def algorithmic_bytes(hist_prev, hist, W, ds_active=False, instances=1):
     """Bytes each kernel must move per iteration (reads + writes of the data it
     owns). The deterministic slot of a main entry (4 bytes) is read and written
     only while a deterministic space is active; its sort key (8 bytes) is
-    stored only when several instances share the list (for one it is the
-    key's hash, recomputed)."""
+    stored when several instances share the list or keys are longer than two
+    words (else it is the key's hash, recomputed)."""
     out = {}
     nm, nm2 = hist_prev["n_occupied"], hist["n_occupied"]
     ns, nu = hist["n_spawned"], hist["n_spawn_events"]
     kb = 8 * W
     ds = 4 if ds_active else 0
-    sk = 8 if instances > 1 else 0
+    sk = 8 if instances > 1 or W > 2 else 0
     out["spawn"] = nm * (kb + sk + 4 + ds + 8) + ns * (8 + kb + 8 + 8 + 4)
     out["sort_pass0"] = ns * (8 + 8 + 4)
     for p in range(1, 8):

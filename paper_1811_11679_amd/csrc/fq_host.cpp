@@ -464,8 +464,8 @@ fq_status download_main(fq_ctx *c, std::vector<HostEntry> &out, int64_t &n)
     const MainList &m = c->buf[c->cur];
     std::vector<uint64_t> sk(n), kk((size_t)n * c->W);
     std::vector<int32_t> pp(n), ds(n);
-    // a single instance's kernels keep no sort keys (they are the keys' hashes)
-    const bool stored = c->R > 1;
+    // sort keys not kept by the kernels are the keys' hashes
+    const bool stored = stored_skey(c->R > 1, c->W);
     if (n) {
         if (stored) HIPCHK(c, d2h(c->stream, sk.data(), m.skey, 8 * n));
         for (int q = 0; q < c->W; ++q)

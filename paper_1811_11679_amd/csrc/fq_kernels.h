@@ -81,8 +81,16 @@ constexpr int PART_MAX_BLOCKS = 8192;
 constexpr int ND_LDS_MAX = 65536;
 __host__ __device__ inline int acc_rows(int R) { return R < ACC_LDS_R ? R : ACC_LDS_R; }
 
+// Whether the main list keeps its sort keys. With one instance the sort key
+// is the key's hash: for keys of up to two words it is recomputed where it is
+// needed (cheaper than 8 bytes per entry moved twice per iteration); longer
+// keys would turn each random probe of the merge partition into W scattered
+// loads, so their sort keys stay stored. With several instances the sort key
+// also holds the replica id and is always stored.
+__host__ __device__ constexpr bool stored_skey(bool multi, int W) { return multi || W > 2; }
+
 struct MainList {
-    uint64_t *skey;  // sort key; kept for several instances only (one: the key's hash, recomputed)
+    uint64_t *skey;  // sort key, kept when stored_skey(R > 1, W)
     uint64_t *key;   // word-major: key[w * cap + i]
     int32_t *pop;
     double *kdiag;   // H_ii - H_00

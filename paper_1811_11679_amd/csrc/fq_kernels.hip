@@ -485,7 +485,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 for (int q = 0; q < W; ++q) pkey[it][q] = w.cur.key[(size_t)q * w.main_cap + i];
                 pn0[it] = w.cur.pop[i];
                 pdsl[it] = ss ? w.cur.dslot[i] : -1;  // read only with the deterministic space active
-                ppsk[it] = MULTI ? w.cur.skey[i] : 0;  // one instance: the sort key is the key's hash
+                ppsk[it] = stored_skey(MULTI, W) ? w.cur.skey[i] : 0;
             }
         }
         // phase 3: excitation, matrix element, amplitude
@@ -515,12 +515,12 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                     for (int q = 0; q < W; ++q) key[q] = w.cur.key[(size_t)q * w.main_cap + i];
                     n0 = w.cur.pop[i];
                     dsl = ss ? w.cur.dslot[i] : -1;
-                    psk = MULTI ? w.cur.skey[i] : 0;
+                    psk = stored_skey(MULTI, W) ? w.cur.skey[i] : 0;
                 }
                 rep[it] = MULTI ? skey_rep(psk, w.rb) : 0u;
                 const RepParams &rp = w.rep[MULTI ? rep[it] : 0u];
                 const DevSys &sy = w.sys[rp.sys];
-                const uint64_t h = hash64<W>(key);
+                const uint64_t h = (!MULTI && W > 2) ? psk : hash64<W>(key);
                 const long long an = n0 < 0 ? -(long long)n0 : (long long)n0;
                 const bool pin_d = ss && dsl >= 0;
                 init[it] = (uint8_t)(an > rp.thr || key_eq<W>(key, *(const uint64_t(*)[W])sy.ref) || pin_d);
@@ -1083,12 +1083,11 @@ __device__ __forceinline__ void load_key(const uint64_t *base, long long cap, lo
     for (int q = 0; q < W; ++q) k[q] = base[(size_t)q * cap + i];
 }
 
-// sort key of main entry i: stored for several instances; for one it is the
-// hash of the key, recomputed rather than moved through HBM
+// sort key of main entry i (see stored_skey)
 template <int W>
 __device__ __forceinline__ uint64_t main_skey(const Work &w, long long i)
 {
-    if (w.rb) return w.cur.skey[i];
+    if (stored_skey(w.rb != 0, W)) return w.cur.skey[i];
     uint64_t k[W];
     load_key<W>(w.cur.key, w.main_cap, i, k);
     return hash64<W>(k);
@@ -1215,8 +1214,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
                 k[x] = w.cur.key[(size_t)x * w.main_cap + g];
                 s_key[x][q] = k[x];
             }
-            // one instance: the sort key is the key's hash, not stored
-            s_sk[q] = MULTI ? w.cur.skey[g] : hash64<W>(k);
+            s_sk[q] = stored_skey(MULTI, W) ? w.cur.skey[g] : hash64<W>(k);
             s_val[q] = w.cur.pop[g];
             s_kd[q] = w.cur.kdiag[g];
             s_meta[q] = ss ? w.cur.dslot[g] : -1;
@@ -1234,7 +1232,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
             if (i0 > 0) {
 #pragma unroll
                 for (int x = 0; x < W; ++x) s_pa_key[x] = w.cur.key[(size_t)x * w.main_cap + i0 - 1];
-                s_pa_sk = MULTI ? w.cur.skey[i0 - 1] : hash64<W>(s_pa_key);
+                s_pa_sk = stored_skey(MULTI, W) ? w.cur.skey[i0 - 1] : hash64<W>(s_pa_key);
             }
             s_nb_ok = j1 < nb;
             if (j1 < nb) {
@@ -1409,7 +1407,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
                 const DevSys &sy = w.sys[rp.sys];
                 const int32_t p = (int32_t)s_val[slot];
                 const int32_t ds = s_meta[slot];
-                if (MULTI) w.nxt.skey[o] = sk;
+                if (stored_skey(MULTI, W)) w.nxt.skey[o] = sk;
                 uint64_t key[W];
 #pragma unroll
                 for (int x = 0; x < W; ++x) {
