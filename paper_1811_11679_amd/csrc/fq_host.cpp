@@ -273,7 +273,7 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.mpart = take(8 * (size_t)(tiles_of(mcap + scap, 512) + 2));
     L.newdet = take((size_t)mcap + 16);
     L.st_scan = take(8 * (size_t)tiles_of(mcap, 2048));
-    L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, 4096));
+    L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, SORT_TILE));
     L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
     L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 512));
     L.st_spawn = take(8 * (size_t)(span_capacity(mcap, scap, W) + 2));

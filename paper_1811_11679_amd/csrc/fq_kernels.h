@@ -68,6 +68,9 @@ constexpr int EST_FIELDS = 14;
 // to global memory directly), and the largest grid of the kernels that write
 // partials
 constexpr int ACC_LDS_R = 64;
+// keys per radix-sort tile (the host sizes the per-tile digit status words by it)
+constexpr int SORT_TILE = 3072;
+
 // spawn tiles: SP_T threads, sp_items(W) attempts per thread (fewer for long
 // keys, whose children take more registers), span_of(W) attempts per tile
 #ifndef FQ_SPAWN_ITEMS

@@ -674,7 +674,9 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 // ---------------------------------------------------------------------------
 // onesweep LSD radix sort of (sort key, index) pairs, 8 passes of 8 bits
 // ---------------------------------------------------------------------------
-constexpr int OS_T = 256, OS_I = 16, OS_TILE = OS_T * OS_I, OS_WAVES = OS_T / 64;
+// 3072-key tiles (12 per thread): three blocks fit a compute unit's LDS
+constexpr int OS_T = 256, OS_I = SORT_TILE / OS_T, OS_TILE = SORT_TILE, OS_WAVES = OS_T / 64;
+static_assert(OS_I * OS_T == SORT_TILE, "sort tiles are whole rows of 256 threads");
 
 __global__ __launch_bounds__(256) void k_sort_hist(Work w)
 {
@@ -780,17 +782,34 @@ __global__ __launch_bounds__(OS_T) void k_sort_pass(Work w, int pass, const uint
             } else {
                 st_store(st, st_pack(epoch, ST_AGG, cnt));
                 long long j = tile - 1;
+                int width = 1;  // the immediate predecessor first, then four per round trip
                 for (;;) {
-                    const unsigned long long s = st_load(w.st_sort + (size_t)j * 256 + d);
-                    const uint32_t e = (uint32_t)(s >> 40);
-                    const unsigned long long f = (s >> ST_VBITS) & 3ull;
-                    if (e != epoch || f == 0) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
+                    unsigned long long s4[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        s4[u] = (u < width && j - u >= 0) ? st_load(w.st_sort + (size_t)(j - u) * 256 + d) : 0ull;
+                    bool done = false, stop = false;
+                    int used = 0;
+                    long long add = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (done || stop || u >= width) continue;
+                        const unsigned long long s = s4[u];
+                        const uint32_t e = (uint32_t)(s >> 40);
+                        const unsigned long long f = (s >> ST_VBITS) & 3ull;
+                        if (j - u < 0 || e != epoch || f == 0) {
+                            stop = true;
+                            continue;
+                        }
+                        add += (long long)(s & ST_VMASK);
+                        ++used;
+                        if (f == ST_INC) done = true;
                     }
-                    excl += (long long)(s & ST_VMASK);
-                    if (f == ST_INC) break;
-                    --j;
+                    excl += add;
+                    j -= used;
+                    if (done) break;
+                    if (used == 0) __builtin_amdgcn_s_sleep(1);
+                    width = 4;
                 }
                 st_store(st, st_pack(epoch, ST_INC, excl + cnt));
             }
