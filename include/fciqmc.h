@@ -269,6 +269,41 @@ fq_status fq_set_sort_key_bits(fq_ctx *ctx, int32_t bits);
 fq_status fq_set_launch(fq_ctx *ctx, const int32_t *blocks, int32_t n);
 fq_status fq_get_launch(const fq_ctx *ctx, int32_t *blocks, int32_t n);
 
+/* On-the-fly blocking analysis (Sec. 3.1: the reblocking of Flyvbjerg and
+ * Petersen, accumulated as the data arrive, so that a run can stop once a
+ * requested statistical error is reached). Host-only: no device call, no
+ * context needed. An accumulator holds n_series (1..64) series observed
+ * together and n_levels (1..62) blocking levels: level k holds the means of
+ * consecutive blocks of 2^k observations (pairwise averages of level k - 1;
+ * an incomplete last block is left out, as in the post-hoc analysis). Memory
+ * is O(n_levels * n_series^2), independent of the number of observations.
+ *
+ * fq_reblock_create: *out receives the accumulator (owned by the caller,
+ *   released by fq_reblock_destroy); FQ_EINVAL for sizes out of range.
+ * fq_reblock_add: x[n_series], one observation of every series; FQ_EINVAL for
+ *   a non-finite value (nothing is recorded).
+ * fq_reblock_level: *n_blocks receives the number of complete blocks at the
+ *   level; mean[n_series] (optional) their means; cov[n_series * n_series]
+ *   (optional, row-major) the sample covariance of the block values (divided
+ *   by n_blocks - 1; NaN below two blocks). The variance of the mean of
+ *   series s at that level is cov[s * n_series + s] / n_blocks.
+ * fq_reblock_optimal: *level receives the smallest level whose block length
+ *   B = 2^k satisfies B^3 > 2 n (e_k / e_0)^4 (n observations, e_k the
+ *   standard error of the mean from level k; Lee, Needs and Towler's
+ *   criterion), or -1 when no level satisfies it yet (not enough data).
+ * fq_reblock_ratio: mean(num) / mean(den) at a level and its first-order
+ *   standard error from the block covariances (the projected energy:
+ *   numerator and reference population averaged separately, then divided);
+ *   *err is NaN below two blocks or for a zero denominator. */
+typedef struct fq_reblock fq_reblock;
+fq_status fq_reblock_create(fq_reblock **out, int32_t n_series, int32_t n_levels);
+fq_status fq_reblock_add(fq_reblock *rb, const double *x);
+fq_status fq_reblock_level(const fq_reblock *rb, int32_t level, int64_t *n_blocks, double *mean, double *cov);
+fq_status fq_reblock_optimal(const fq_reblock *rb, int32_t series, int32_t *level);
+fq_status fq_reblock_ratio(const fq_reblock *rb, int32_t level, int32_t num, int32_t den, double *ratio,
+                           double *err);
+void fq_reblock_destroy(fq_reblock *rb);
+
 const char *fq_last_error(const fq_ctx *ctx);
 void fq_destroy(fq_ctx *ctx);
 

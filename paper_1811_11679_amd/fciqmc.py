@@ -24,7 +24,9 @@ SS_FP64, SS_SPLIT_BF16 = 0, 1
 C_API = ["fq_workspace_bytes", "fq_init_system", "fq_step", "fq_estimators", "fq_estimator_history",
          "fq_export_walkers", "fq_import_walkers", "fq_shift_state", "fq_export_spawns", "fq_detspace", "fq_info",
          "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_iteration_times", "fq_set_graph",
-         "fq_set_sort_key_bits", "fq_set_launch", "fq_get_launch", "fq_last_error", "fq_destroy"]
+         "fq_set_sort_key_bits", "fq_set_launch", "fq_get_launch", "fq_reblock_create", "fq_reblock_add",
+         "fq_reblock_level", "fq_reblock_optimal", "fq_reblock_ratio", "fq_reblock_destroy", "fq_last_error",
+         "fq_destroy"]
 LAUNCH_KERNELS = ["spawn", "merge", "sort", "reduce", "new_diag"]
 
 KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "sort_hist"] + \
@@ -125,6 +127,19 @@ def load_library():
     L.fq_set_graph.restype = C.c_int32
     L.fq_set_sort_key_bits.argtypes = [P, C.c_int32]
     L.fq_set_sort_key_bits.restype = C.c_int32
+    D = C.POINTER(C.c_double)
+    L.fq_reblock_create.argtypes = [C.POINTER(P), C.c_int32, C.c_int32]
+    L.fq_reblock_create.restype = C.c_int32
+    L.fq_reblock_add.argtypes = [P, D]
+    L.fq_reblock_add.restype = C.c_int32
+    L.fq_reblock_level.argtypes = [P, C.c_int32, C.POINTER(C.c_int64), D, D]
+    L.fq_reblock_level.restype = C.c_int32
+    L.fq_reblock_optimal.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
+    L.fq_reblock_optimal.restype = C.c_int32
+    L.fq_reblock_ratio.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, D, D]
+    L.fq_reblock_ratio.restype = C.c_int32
+    L.fq_reblock_destroy.argtypes = [P]
+    L.fq_reblock_destroy.restype = None
     L.fq_set_launch.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
     L.fq_set_launch.restype = C.c_int32
     L.fq_get_launch.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
