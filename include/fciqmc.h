@@ -102,6 +102,12 @@ typedef struct {
     double initiator_threshold; /* n_add, walkers (strict >) */
     int32_t fixed_point_bits;   /* b; 0 = integer walkers */
     double spawn_cutoff;        /* walkers; real mode only */
+    int32_t tau_search;         /* 1: the tutorial's tau_search, one instance per context
+                                   (FQ_EINVAL otherwise). After each shift update tau only
+                                   decreases, to min(tau, 1 / max |H_ji| / p_gen over every
+                                   attempt so far, 1 / (max K_ii - S) over the entries of the
+                                   last death step), each bound applying when positive.
+                                   Export/import keep tau and the running maximum. */
 } fq_qmc;
 
 /* Semi-stochastic block (tutorial appendix, semi_stoch = {size,
@@ -146,6 +152,9 @@ typedef struct {
     double ss_error;          /* split projection: max_i |y_i - y_i(FP64)| / sum_j |K_ij||c_j|
                                  of the last checked iteration (0 if none) */
     double ss_error_bound;    /* a priori bound of that ratio for the BF16 x3 / FP32 scheme */
+    double tau;               /* time step of the next iteration (tau_search may lower it) */
+    double spawn_ratio_max;   /* tau_search: largest |H_ji| / p_gen of any attempt so far, as of
+                                 the end of the fq_step call (0 without tau_search) */
 } fq_estimators_t;
 
 typedef struct fq_ctx fq_ctx;

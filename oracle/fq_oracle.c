@@ -655,6 +655,10 @@ struct or_run {
     uint64_t *dsorted;   /* sorted copy of the keys */
     int32_t *dsorted_ix; /* D index of each sorted key */
     double *last_y;
+    /* time-step search (tutorial appendix: tau_search) */
+    double rs_max;  /* largest |H_ji| / p_gen over the attempts so far */
+    double kd_max;  /* largest K_ii over the entries of the last death step */
+    int kd_any;
 };
 
 static void draw(const or_run *r, uint32_t tag, uint32_t attempt, uint32_t t, uint64_t h,
@@ -799,6 +803,7 @@ or_run *or_run_new(const or_sys *s, const or_qmc *q)
     r->n = 1;
     r->S = q->initial_shift;
     compute_estimators(r);
+    r->est.tau = r->q.tau;
     return r;
 }
 
@@ -826,6 +831,10 @@ static int spawn_attempt(or_run *r, const uint64_t *key, uint64_t h, int32_t n0,
     if (hij == 0.0) return OR_OK;
     if (parent_in_d && dspace_find(r, child) >= 0) return OR_OK;
     double ah = fabs(hij);
+    if (r->q.tau_search) {
+        double ratio = ah / pgen;
+        if (ratio > r->rs_max) r->rs_max = ratio;
+    }
     double m;
     if (r->q.fixed_point_bits == 0) {
         m = (r->q.tau * ah) / pgen;
@@ -1070,6 +1079,7 @@ static int step_once(or_run *r)
     int64_t flips = 0;
     /* 1. spawning from the start-of-iteration populations */
     r->ns = 0;
+    r->kd_any = 0;
     for (int64_t i = 0; i < n; ++i) {
         int32_t n0 = r->pops[i];
         if (n0 == 0) continue;
@@ -1111,6 +1121,10 @@ static int step_once(or_run *r)
             continue;
         }
         if (n0 == 0) { newpop[i] = 0; continue; }
+        if (r->q.tau_search && (!r->kd_any || r->kdiag[i] > r->kd_max)) {
+            r->kd_max = r->kdiag[i];
+            r->kd_any = 1;
+        }
         double an = (double)(n0 < 0 ? -(int64_t)n0 : (int64_t)n0);
         double m = (r->q.tau * (r->kdiag[i] - r->S)) * an;
         draw(r, TAG_DEATH, 0, t, h, rnd);
@@ -1222,7 +1236,29 @@ static int step_once(or_run *r)
         }
         r->est.shift = r->S;
         r->est.vary_shift = r->vary;
+        /* time-step search (reading of the tutorial's tau_search): after the
+           shift update, tau only decreases, to the largest value at which no
+           attempt seen so far expects more than one walker per parent walker
+           (tau |H_ji| / p_gen <= 1) and the death step of the last iteration
+           removes at most every walker of a determinant (tau (K_ii - S) <= 1) */
+        if (r->q.tau_search) {
+            double tau = r->q.tau;
+            if (r->rs_max > 0.0) {
+                double b = 1.0 / r->rs_max;
+                if (b < tau) tau = b;
+            }
+            if (r->kd_any) {
+                double d = r->kd_max - r->S;
+                if (d > 0.0) {
+                    double b = 1.0 / d;
+                    if (b < tau) tau = b;
+                }
+            }
+            r->q.tau = tau;
+        }
     }
+    r->est.tau = r->q.tau;
+    r->est.spawn_ratio_max = r->rs_max;
     /* deterministic space chosen from the most highly weighted determinants */
     if (r->q.ss_size > 0 && !r->q.ss_shared && !r->ss_active && r->t >= r->q.ss_start_iteration) select_detspace(r);
     return OR_OK;

@@ -58,6 +58,7 @@ typedef struct {
     int32_t ss_size;            /* 0: no semi-stochastic */
     int32_t ss_start_iteration;
     int32_t ss_shared;          /* 1: D chosen jointly with other runs (or_runs_select_shared) */
+    int32_t tau_search;         /* 1: lower tau on the fly (see step_once) */
 } or_qmc;
 
 /* estimators of the last completed iteration */
@@ -68,6 +69,8 @@ typedef struct {
     int32_t vary_shift, status;
     double shift, proj_numerator, proj_energy, e_ref;
     int64_t num_limbs[4];
+    double tau;             /* time step in force for the next iteration */
+    double spawn_ratio_max; /* largest |H_ji| / p_gen of any attempt so far (tau search only) */
 } or_estimators;
 
 /* Philox4x32-10, Salmon et al. (SC'11) */

@@ -38,7 +38,7 @@ class Qmc(C.Structure):
                 ("p_single", C.c_double), ("initiator", C.c_int32),
                 ("initiator_threshold", C.c_double), ("fixed_point_bits", C.c_int32),
                 ("spawn_cutoff", C.c_double), ("ss_size", C.c_int32),
-                ("ss_start_iteration", C.c_int32), ("ss_shared", C.c_int32)]
+                ("ss_start_iteration", C.c_int32), ("ss_shared", C.c_int32), ("tau_search", C.c_int32)]
 
 
 class Estimators(C.Structure):
@@ -50,7 +50,7 @@ class Estimators(C.Structure):
                 ("vary_shift", C.c_int32), ("status", C.c_int32),
                 ("shift", C.c_double), ("proj_numerator", C.c_double),
                 ("proj_energy", C.c_double), ("e_ref", C.c_double),
-                ("num_limbs", C.c_int64 * 4)]
+                ("num_limbs", C.c_int64 * 4), ("tau", C.c_double), ("spawn_ratio_max", C.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "num_limbs"}
@@ -194,7 +194,7 @@ def make_qmc(**kw) -> Qmc:
     d = dict(tau=0.01, seed=7, replica_id=0, init_pop=500.0, target_population=1e4,
              shift_period=10, shift_damping=0.05, initial_shift=0.0, excit_gen=EXGEN_HUB,
              p_single=0.1, initiator=0, initiator_threshold=3.0, fixed_point_bits=0,
-             spawn_cutoff=0.0, ss_size=0, ss_start_iteration=0, ss_shared=0)
+             spawn_cutoff=0.0, ss_size=0, ss_start_iteration=0, ss_shared=0, tau_search=0)
     d.update(kw)
     return Qmc(**d)
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -349,6 +350,7 @@ struct fq_ctx {
     EstAcc *h_hist = nullptr;
     double *h_shift = nullptr;
     double h00[64] = {0};
+    double rs_max = 0.0;  // time-step search: largest |H_ji| / p_gen so far (device maximum)
     std::vector<double> h00v;
     bool timing = false;
     bool graph = false;
@@ -420,6 +422,8 @@ void estimators_from_acc(const fq_ctx *c, int r, const EstAcc &a, fq_estimators_
     e.proj_numerator = num * std::ldexp(1.0, -c->qmc[r].fixed_point_bits);
     e.proj_energy = a.n0 != 0 ? num / (double)a.n0 : NAN;
     e.e_ref = c->h00v[r];
+    e.tau = c->qmc[r].tau;
+    e.spawn_ratio_max = c->rs_max;
 }
 
 void set_main_views(fq_ctx *c)
@@ -726,6 +730,8 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         spawn_capacity < 1 || !d_workspace)
         return FQ_EINVAL;
     if (spawn_capacity >= (1ll << 32)) return FQ_EINVAL;
+    for (int r = 0; r < n_instances; ++r)
+        if (qmc[r].tau_search && n_instances > 1) return FQ_EINVAL;  // the search is per context
     *out = nullptr;
     fq_ctx *c = new fq_ctx();
     c->R = n_instances;
@@ -830,6 +836,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     w.R = c->R;
     w.rb = c->rb;
     w.hmask = c->hmask;
+    w.tau_search = c->qmc[0].tau_search;
     w.W = c->W;
     w.hist_len = HIST_LEN;
     c->cur = 0;
@@ -1130,6 +1137,11 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             if (err & ERR_SPAWN_CAP) return fail(c, FQ_ECAPACITY, "spawn capacity exceeded");
             return fail(c, FQ_ECAPACITY, "main list capacity exceeded");
         }
+        if (c->qmc[0].tau_search) {
+            const unsigned long long b = c->h_ctl->rs_max;
+            std::memcpy(&c->rs_max, &b, 8);
+        }
+        bool tau_changed = false;
         for (int64_t it = t0 + 1; it <= stop; ++it) {
             for (int r = 0; r < c->R; ++r) {
                 fq_estimators_t e;
@@ -1148,7 +1160,30 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                         c->shift[r] = c->shift[r] - cc * std::log(ratio);
                         c->nprev[r] = nw;
                     }
+                    // time-step search (the tutorial's tau_search), after the shift
+                    // update: tau only decreases, so that tau |H_ji| / p_gen <= 1 for
+                    // every attempt so far and tau (K_ii - S) <= 1 for the entries of
+                    // the last death step (the block's last iteration is this one)
+                    if (c->qmc[r].tau_search && it == stop) {
+                        double tau = c->qmc[r].tau;
+                        if (c->rs_max > 0.0) {
+                            const double bnd = 1.0 / c->rs_max;
+                            if (bnd < tau) tau = bnd;
+                        }
+                        if (c->h_ctl->kd_max != 0) {
+                            const double d = from_ordered_key(c->h_ctl->kd_max) - c->shift[r];
+                            if (d > 0.0) {
+                                const double bnd = 1.0 / d;
+                                if (bnd < tau) tau = bnd;
+                            }
+                        }
+                        if (tau != c->qmc[r].tau) {
+                            c->qmc[r].tau = tau;
+                            tau_changed = true;
+                        }
+                    }
                 }
+                e.tau = c->qmc[r].tau;
                 e.shift = c->shift[r];
                 e.vary_shift = c->vary[r];
                 c->hist[r].push_back(e);
@@ -1157,6 +1192,8 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         }
         c->t = stop;
         done += nb;
+        if (tau_changed)
+            HIPCHK(c, h2d(c->stream, (char *)c->w.rep + offsetof(RepParams, tau), &c->qmc[0].tau, sizeof(double)));
         for (int r = 0; r < c->R; ++r) c->h_shift[r] = c->shift[r];
         HIPCHK(c, hipMemcpyAsync(c->w.shift, c->h_shift, 8 * c->R, hipMemcpyHostToDevice, c->stream));
         if (c->has_ss && !c->ss_active && c->t >= c->ss.start_iteration) {

@@ -51,6 +51,11 @@ struct Ctl {
     uint32_t err;
     uint32_t collision;    // equal sort keys with different determinants seen
     uint32_t ss_active;
+    // time-step search (one instance): bits of the largest |H_ji| / p_gen of
+    // any attempt so far (a non-negative double orders as its bits), and the
+    // order-preserving key of the largest K_ii of the last death step (0: none)
+    unsigned long long rs_max;
+    unsigned long long kd_max;
     uint32_t tickets[TK_COUNT];
     uint32_t hist[8][256];  // radix-sort digit histogram of the spawned keys
 };
@@ -83,6 +88,21 @@ constexpr int PART_MAX_BLOCKS = 8192;
 // largest diagonal-table staging of the new-determinant kernel (bytes of LDS)
 constexpr int ND_LDS_MAX = 65536;
 __host__ __device__ inline int acc_rows(int R) { return R < ACC_LDS_R ? R : ACC_LDS_R; }
+
+// order-preserving unsigned key of a double (larger value, larger key)
+__host__ __device__ inline unsigned long long ordered_key(double x)
+{
+    unsigned long long b;
+    __builtin_memcpy(&b, &x, 8);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double from_ordered_key(unsigned long long k)
+{
+    const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    double x;
+    __builtin_memcpy(&x, &b, 8);
+    return x;
+}
 
 // Whether the main list keeps its sort keys. With one instance the sort key
 // is the key's hash: for keys of up to two words it is recomputed where it is
@@ -160,6 +180,7 @@ struct Work {
     long long main_cap, spawn_cap, span_cap;
     int32_t R, rb, W, hist_len;
     uint64_t hmask;  // hash bits that enter a sort key (all but in collision tests)
+    int32_t tau_search;  // track the maxima of the time-step search (one instance)
     int32_t lds_tables;  // bytes of UEG tables the spawn kernel stages in LDS (0: read from global)
     int32_t lds_diag;    // bytes of diagonal tables the new-determinant kernel stages in LDS
 };

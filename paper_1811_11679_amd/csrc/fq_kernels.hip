@@ -45,6 +45,13 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // Decoupled look-back, run by one whole wavefront: publishes this tile's
 // aggregate, then inspects the 64 preceding tiles at a time until it meets an
 // inclusive prefix, publishes its own inclusive prefix and returns the
@@ -236,6 +243,7 @@ __global__ void k_begin(Work w)
         c->n_uniq = 0;
         c->n_att = c->n_att_new;
         c->collision = 0;
+        c->kd_max = 0;
     }
     for (int i = threadIdx.x; i < TK_COUNT; i += blockDim.x) c->tickets[i] = 0;
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&c->hist[0][0])[i] = 0;
@@ -389,6 +397,9 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
     const bool ss = c->ss_active != 0;
     const uint32_t epoch = epoch_of(t, 12);
     const int lane = lane_id(), wid = threadIdx.x >> 6;
+    // time-step search: the largest |H_ji| / p_gen of this thread's attempts
+    const bool ts = !MULTI && w.tau_search != 0;
+    double rs_max = 0.0;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     UegTables lu = w.sys[w.rep[0].sys].u;
     const double *hb_tri = nullptr;  // heat-bath pair weights staged in LDS (LT, molecular)
@@ -562,6 +573,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                     }
                     if (!skip) {
                         const double ah = fabs(hv);
+                        if (ts) rs_max = fmax(rs_max, ah / pgen);
                         double m;
                         if (rp.bits == 0)
                             m = (rp.tau * ah) / pgen;
@@ -668,6 +680,10 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
         }
         if (span == nspans - 1 && threadIdx.x == 0) c->n_spawn = (unsigned long long)(base + tot);
         __syncthreads();
+    }
+    if (ts) {
+        rs_max = wave_max(rs_max);
+        if (lane == 0 && rs_max > 0.0) atomicMax(&c->rs_max, (unsigned long long)__double_as_longlong(rs_max));
     }
 }
 
@@ -1216,6 +1232,9 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
     acc.clear();
     acc.rep = -1;
     bool any = false;
+    // time-step search: the largest K_ii of the entries this thread's death steps act on
+    const bool ts = !MULTI && w.tau_search != 0;
+    double kd_max = -INFINITY;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[TK_MERGE], 1u);
         __syncthreads();
@@ -1314,6 +1333,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
                     v = (long long)n0 + w.ds.delta[(size_t)rep * w.ds.n + dsl];
                 } else if (n0 != 0) {
                     const RepParams &rp = w.rep[rep];
+                    if (ts) kd_max = fmax(kd_max, s_kd[a]);
                     const double an = (double)(n0 < 0 ? -(long long)n0 : (long long)n0);
                     const double mm = (rp.tau * (s_kd[a] - w.shift[rep])) * an;
                     uint64_t h = sk;
@@ -1463,6 +1483,10 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
         __syncthreads();
     }
     acc_finish(acc, any && acc.rep >= 0, tab, rl, w.acc, w.part_mrg);
+    if (ts) {
+        kd_max = wave_max(kd_max);
+        if (lane_id() == 0 && kd_max > -INFINITY) atomicMax(&c->kd_max, ordered_key(kd_max));
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0 && ntiles == 0) {
         c->n_main_new = 0;
         w.att_off[0] = 0;

@@ -53,7 +53,7 @@ class Qmc(C.Structure):
                 ("shift_period", C.c_int32), ("shift_damping", C.c_double), ("initial_shift", C.c_double),
                 ("excit_gen", C.c_int32), ("p_single", C.c_double), ("initiator", C.c_int32),
                 ("initiator_threshold", C.c_double), ("fixed_point_bits", C.c_int32),
-                ("spawn_cutoff", C.c_double)]
+                ("spawn_cutoff", C.c_double), ("tau_search", C.c_int32)]
 
 
 class SemiStoch(C.Structure):
@@ -68,7 +68,8 @@ class Estimators(C.Structure):
                 ("death_sum", C.c_int64), ("spawn_sum", C.c_int64), ("rejected_sum", C.c_int64),
                 ("vary_shift", C.c_int32), ("status", C.c_int32), ("shift", C.c_double),
                 ("proj_numerator", C.c_double), ("proj_energy", C.c_double), ("e_ref", C.c_double),
-                ("num_limbs", C.c_int64 * 4), ("ss_error", C.c_double), ("ss_error_bound", C.c_double)]
+                ("num_limbs", C.c_int64 * 4), ("ss_error", C.c_double), ("ss_error_bound", C.c_double),
+                ("tau", C.c_double), ("spawn_ratio_max", C.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "num_limbs"}
@@ -176,7 +177,7 @@ def make_system(kind, **kw):
 def make_qmc(**kw):
     d = dict(tau=0.01, rng_seed=7, replica_id=0, init_pop=500.0, target_population=1e4, shift_period=10,
              shift_damping=0.05, initial_shift=0.0, excit_gen=1, p_single=0.1, initiator=0,
-             initiator_threshold=3.0, fixed_point_bits=0, spawn_cutoff=0.0)
+             initiator_threshold=3.0, fixed_point_bits=0, spawn_cutoff=0.0, tau_search=0)
     d.update(kw)
     return Qmc(**d)
 

@@ -29,7 +29,7 @@ def oracle_qmc(sysd, q, replica=0, ss=None):
                       initiator_threshold=q.get("initiator_threshold", 3.0),
                       fixed_point_bits=q.get("fixed_point_bits", 0), spawn_cutoff=q.get("spawn_cutoff", 0.0),
                       ss_size=ss["size"] if ss else 0, ss_start_iteration=ss["start_iteration"] if ss else 0,
-                      ss_shared=ss.get("shared", 0) if ss else 0)
+                      ss_shared=ss.get("shared", 0) if ss else 0, tau_search=q.get("tau_search", 0))
 
 
 def gpu_context(sysds, qs, ints=None, ss=None, main_capacity=1 << 21, spawn_capacity=1 << 21,
@@ -71,7 +71,7 @@ def assert_same_lists(ctx, run, instance=0, where=""):
 
 FIELDS = ("iteration", "n_walkers_units", "n_occupied", "ref_pop_units", "n_spawned", "n_spawn_events",
           "death_sum", "spawn_sum", "rejected_sum", "n_rejected_units", "n_sign_flips", "vary_shift",
-          "num_limbs", "shift", "proj_numerator")
+          "num_limbs", "shift", "proj_numerator", "tau", "spawn_ratio_max")
 
 
 def assert_same_estimators(eg, eo, where=""):

@@ -238,3 +238,22 @@ def test_semistochastic_split_precision_error_within_bound():
     hist = ctx.history()
     assert all(h["ss_error"] <= h["ss_error_bound"] for h in hist)
     ctx.close()
+
+
+def test_tau_search_lowers_tau_identically():
+    # a time step twice too large for the 19-plane-wave gas: the search lowers
+    # it at the shift updates, on the GPU exactly as in the oracle
+    sysd = dict(kind="ueg", rs=1.0, ecut_n2=2, n_alpha=7, n_beta=7)
+    q = dict(tau=0.02, rng_seed=11, init_pop=3e3, target_population=2e4, initiator=1, initiator_threshold=3.0,
+             fixed_point_bits=8, spawn_cutoff=0.1, tau_search=1)
+    e = _compare_run(sysd, q, 120, 20, tag="tau search ueg19")
+    assert e["tau"] < 0.02 and e["spawn_ratio_max"] > 0.0
+    assert e["tau"] * e["spawn_ratio_max"] <= 1.0 + 1e-15
+
+
+def test_tau_search_needs_a_single_instance():
+    from paper_1811_11679_amd import fciqmc as F
+    sysd = dict(kind="hubbard", n_sites=8, periodic=1, t=1.0, U=4.0, n_alpha=4, n_beta=4)
+    with pytest.raises(F.FqError):
+        gpu_context([sysd, sysd], [dict(tau=0.01, init_pop=500.0, target_population=1e4, tau_search=1)] * 2,
+                    replicas=[0, 1])
