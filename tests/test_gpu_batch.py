@@ -119,3 +119,22 @@ def test_mixed_width_batch_matches_plain_runs_and_oracle():
     assert_same_estimators(plain.estimators(), bt.estimators(3), where="plain continuation of instance 3")
     plain.close()
     bt.close()
+
+
+def test_graph_replay_with_tau_search_matches_oracle():
+    # the lowered time step reaches the captured kernels through device memory
+    from paper_1811_11679_amd import fciqmc as F
+    sysd = dict(kind="ueg", rs=1.0, ecut_n2=2, n_alpha=7, n_beta=7)
+    q = dict(tau=0.02, rng_seed=11, init_pop=3e3, target_population=2e4, initiator=1, initiator_threshold=3.0,
+             fixed_point_bits=8, spawn_cutoff=0.1, tau_search=1)
+    say("[case] graph replay with tau search ueg19")
+    ctx = F.Context([F.make_system(F.UEG, rs=1.0, ecut_n2=2, n_alpha=7, n_beta=7)],
+                    [F.make_qmc(excit_gen=F.UEG, **q)], main_capacity=1 << 21, spawn_capacity=1 << 21, graph=True)
+    run = _oracle_run(sysd, q)
+    for k in (10, 10, 7, 3, 20, 30):
+        ctx.step(k)
+        run.step(k)
+        assert_same_lists(ctx, run, where="graph replay with tau search")
+        assert_same_estimators(ctx.estimators(), run.estimators(), where="graph replay with tau search")
+    assert ctx.estimators()["tau"] < 0.02
+    ctx.close()
