@@ -74,3 +74,19 @@ def test_without_the_search_tau_is_constant():
         r.step(10)
         e = r.estimators()
         assert e["tau"] == 0.01 and e["spawn_ratio_max"] == 0.0
+
+
+def test_death_bound_uses_the_largest_diagonal_of_the_last_death_step():
+    # Hubbard ring from tau = 0.05: at the first shift update the death bound
+    # 1 / (max K_ii - S) is the binding one (the spawn bound is 1/16). K_ii is
+    # recomputed here from the list the last death step acted on.
+    s = O.System.hubbard()
+    r = O.Run(s, O.make_qmc(tau=0.05, initial_shift=-4.0, tau_search=1))
+    r.step(9)
+    keys, pops = r.export()  # the list iteration 10 starts from
+    kii = max(s.diag(k) - s.H00 for k, p in zip(keys, pops) if p != 0)
+    r.step(1)
+    e = r.estimators()
+    expect = min(0.05, 1.0 / e["spawn_ratio_max"], 1.0 / (kii - e["shift"]))
+    assert 1.0 / (kii - e["shift"]) < 1.0 / e["spawn_ratio_max"]
+    assert e["tau"] == expect

@@ -142,3 +142,58 @@ def test_on_the_fly_edge_cases_and_argument_checks():
     with pytest.raises(F.FqError):
         acc.optimal(2)
     acc.close()
+
+
+class _FakeContext:
+    """Stands in for a library context: replays a precomputed estimator series."""
+
+    def __init__(self, rows):
+        self.rows = rows
+        self.t = 0
+        self.last = []
+
+    def step(self, k):
+        self.last = [dict(iteration=self.t + 1 + i, shift=float(self.rows[self.t + i][0]),
+                          proj_numerator=float(self.rows[self.t + i][1]), ref_pop_units=float(self.rows[self.t + i][2]))
+                     for i in range(k)]
+        self.t += k
+
+    def history(self, instance=0):
+        return self.last
+
+    def estimators(self, instance=0):
+        return {"iteration": self.t}
+
+
+def test_run_until_error_stops_at_the_first_qualifying_check():
+    _lib()
+    from paper_1811_11679_amd import reblock as RB
+    rng = np.random.default_rng(6)
+    n = 1 << 15
+    den = 100.0 + 5.0 * _ar1(n, 0.9, rng)
+    num = -0.5 * den + 2.0 * _ar1(n, 0.9, rng)
+    rows = np.stack([-0.5 + 0.1 * _ar1(n, 0.9, rng), num, den], axis=1)
+    ctx = _FakeContext(rows)
+    obs = []
+    start, block, target, min_blocks = 200, 256, 0.004, 16
+    res = RB.run_until_error(ctx, target, start, block=block, max_iterations=n, observations=obs, min_blocks=min_blocks)
+    assert res["converged"]
+    np.testing.assert_array_equal(np.array(obs), rows[start:res["iteration"]])
+
+    def decide(x):
+        lv = R.block_levels(x)
+        k1, k2 = R.optimal_level(lv, 1), R.optimal_level(lv, 2)
+        if min(k1, k2) < 0:
+            return False, None
+        k = max(k1, k2)
+        e, err = R.ratio(lv, k, 1, 2)
+        return lv[k][0] >= min_blocks and err <= target, (k, e, err)
+
+    ok, (k, e, err) = decide(rows[start:res["iteration"]])
+    assert ok and k == res["level"]
+    assert res["proj_energy"] == pytest.approx(e, rel=1e-12) and res["proj_energy_error"] == pytest.approx(err, rel=1e-8)
+    assert not decide(rows[start:res["iteration"] - block])[0]
+    # an unreachable target runs to the limit and reports no convergence
+    ctx2 = _FakeContext(rows)
+    res2 = RB.run_until_error(ctx2, 1e-9, start, block=block, max_iterations=4096)
+    assert ctx2.t == 4096 and (res2 is None or not res2["converged"])
