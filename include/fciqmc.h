@@ -54,7 +54,7 @@ typedef int32_t fq_status;
 #define FQ_EHIP (-4)
 #define FQ_ESTATE (-5)
 
-/* model systems (paper Sec. 4.2: Hubbard, uniform electron gas) and molecular
+/* model systems (paper Sec. 4.3: uniform electron gas, Hubbard) and molecular
  * integrals (Sec. 3.1 and the tutorial appendix: h_pq and (pq|rs)) */
 #define FQ_HUBBARD_REAL 1
 #define FQ_UEG 2
@@ -100,7 +100,9 @@ typedef struct {
     double p_single;            /* heat-bath generator: probability of a single */
     int32_t initiator;          /* 1: initiator approximation on */
     double initiator_threshold; /* n_add, walkers (strict >) */
-    int32_t fixed_point_bits;   /* b; 0 = integer walkers */
+    int32_t fixed_point_bits;   /* b; 0 = integer walkers, else 3..20 (FQ_EINVAL otherwise:
+                                   with b = 1, 2 an int32 population could need 2^28 or more
+                                   spawning attempts, the limit of the random-number counter) */
     double spawn_cutoff;        /* walkers; real mode only */
     int32_t tau_search;         /* 1: the tutorial's tau_search, one instance per context
                                    (FQ_EINVAL otherwise). After each shift update tau only
@@ -208,7 +210,7 @@ fq_status fq_import_walkers(fq_ctx *ctx, int32_t instance, const uint64_t *keys,
  * S (Hartree, relative to H_00), the population (units) at the last shift
  * update and whether S is being varied. With fq_export_walkers and
  * fq_estimators this is everything fq_import_walkers needs to continue the run
- * exactly (Section 4.1.2: S is updated every A iterations from the ratio of
+ * exactly (Sec. 2.1 and the tutorial appendix: S is updated every A iterations from the ratio of
  * populations). Any output pointer may be NULL. */
 fq_status fq_shift_state(const fq_ctx *ctx, int32_t instance, double *shift, int64_t *n_prev,
                          int32_t *vary_shift);

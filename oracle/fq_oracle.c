@@ -118,7 +118,7 @@ static double parity_between(const uint64_t *k, int P, int A)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Systems (paper Sec. 4.2: UEG and Hubbard model systems; Sec. 3.1 and the   */
+/* Systems (paper Sec. 4.3: UEG and Hubbard model systems; Sec. 3.1 and the   */
 /* tutorial appendix: molecular integrals h_pq, (pq|rs)).                     */
 /* ------------------------------------------------------------------------- */
 struct or_sys {
@@ -320,7 +320,7 @@ static int pw_cmp(const void *a, const void *b)
 
 /* Plane waves n in Z^3 with |n|^2 <= ecut in a simple-cubic box of side
  * L = rs * cbrt(4 pi N / 3); kinetic (2pi/L)^2 |n|^2 / 2; Coulomb
- * v(q) = 4 pi / (L^3 |k_q|^2), q = 0 excluded (paper Sec. 4.2, UEG). */
+ * v(q) = 4 pi / (L^3 |k_q|^2), q = 0 excluded (paper Sec. 4.3, UEG). */
 or_sys *or_ueg_new(double rs, int ecut_n2, int n_alpha, int n_beta)
 {
     int c = 0;
@@ -780,7 +780,10 @@ static void compute_estimators(or_run *r)
 
 or_run *or_run_new(const or_sys *s, const or_qmc *q)
 {
+    /* b = 1, 2 would allow more than 2^28 attempts per determinant (the
+       attempt index field of the random-number counter): refused */
     if (!s || !q || !(q->tau > 0.0) || q->fixed_point_bits < 0 || q->fixed_point_bits > 20 ||
+        (q->fixed_point_bits > 0 && q->fixed_point_bits < 3) ||
         q->shift_period <= 0)
         return NULL;
     if (q->excit_gen == OR_EXGEN_HUB && s->kind != OR_HUBBARD) return NULL;
@@ -879,16 +882,15 @@ static int idx_cmp(const void *a, const void *b)
 }
 
 /* Deterministic projection on D (Sec. 2.1 semi-stochastic propagation):
- * y_i = sum_j K_ij n_j with 64 interleaved partial sums (j = l mod 64) each
- * taken in increasing j, then combined by a fixed halving tree. */
+ * y_i = sum_j K_ij n_j. Reading: the sum is taken exactly and rounded once,
+ * as the projected-energy numerator is: every FP64 product K_ij n_j is
+ * truncated at 2^-64 and added in fixed point, so the value does not depend
+ * on the order of the terms. */
 static double det_row(const double *row, const double *c, int64_t nd)
 {
-    double part[64];
-    for (int l = 0; l < 64; ++l) part[l] = 0.0;
-    for (int64_t j = 0; j < nd; ++j) part[j & 63] = part[j & 63] + row[j] * c[j];
-    for (int step = 32; step >= 1; step >>= 1)
-        for (int l = 0; l < step; ++l) part[l] = part[l] + part[l + step];
-    return part[0];
+    int64_t limbs[4] = {0, 0, 0, 0};
+    for (int64_t j = 0; j < nd; ++j) acc_term(limbs, row[j] * c[j]);
+    return limbs_value(limbs);
 }
 
 static struct { const or_run *r; } g_top;

@@ -20,7 +20,7 @@ from . import fciqmc as F
 
 def n_plane_waves(ecut_n2: int) -> int:
     """Number of integer vectors n with |n|^2 <= ecut_n2 (the basis of the
-    simple-cubic electron gas, Section 6.2)."""
+    simple-cubic electron gas, Sec. 4.3)."""
     m = int(ecut_n2 ** 0.5) + 1
     return sum(1 for x in range(-m, m + 1) for y in range(-m, m + 1) for z in range(-m, m + 1)
                if x * x + y * y + z * z <= ecut_n2)

@@ -751,7 +751,11 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         const int need = c->kind == FQ_HUBBARD_REAL ? FQ_EXGEN_HUB_UNIFORM
                          : c->kind == FQ_UEG        ? FQ_EXGEN_UEG_UNIFORM
                                                     : FQ_EXGEN_HEATBATH_UNIFORM_SINGLES;
+        // fixed_point_bits 1 and 2 would allow 2^28 or more attempts on one
+        // determinant (int32 populations), beyond the attempt field of the
+        // random-number counter
         if (!(q.tau > 0) || q.excit_gen != need || q.fixed_point_bits < 0 || q.fixed_point_bits > 20 ||
+            (q.fixed_point_bits > 0 && q.fixed_point_bits < 3) ||
             q.shift_period <= 0 || q.shift_period > HIST_LEN / 2 || !(q.init_pop >= 0) ||
             (q.excit_gen == FQ_EXGEN_HEATBATH_UNIFORM_SINGLES && !(q.p_single >= 0 && q.p_single < 1))) {
             delete c;
@@ -1018,6 +1022,14 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         stop = std::min(stop, next_shift);
         if (c->has_ss && !c->ss_active && c->t < c->ss.start_iteration) stop = std::min<int64_t>(stop, c->ss.start_iteration);
         stop = std::min<int64_t>(stop, c->t + HIST_LEN / 2);
+        // The look-back status words carry the iteration counter modulo
+        // 2^20. A block never crosses a multiple of 2^20, and before the first
+        // iteration of each such period every status array is cleared, so no
+        // word written 2^20 iterations earlier can carry a matching epoch.
+        constexpr int64_t EPOCH_PERIOD = int64_t(1) << 20;
+        stop = std::min<int64_t>(stop, ((c->t + 1) / EPOCH_PERIOD + 1) * EPOCH_PERIOD - 1);
+        if ((c->t + 1) % EPOCH_PERIOD == 0)
+            HIPCHK(c, fill0(c->stream, c->ws + c->L.st_scan, c->L.part_red - c->L.st_scan));
         const int64_t t0 = c->t;
         const int cur0 = c->cur;
         const int nb = (int)(stop - t0);

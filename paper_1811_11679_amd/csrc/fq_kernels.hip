@@ -1160,7 +1160,10 @@ __global__ void k_merge_partition(Work w)
     }
 }
 
-__device__ __forceinline__ void add_limbs(long long (&v)[EST_FIELDS], double x)
+// Exact fixed-point accumulation of one FP64 term: |x| 2^64 truncated toward
+// zero, split into four 32-bit limbs added with the sign of x (int64 limb
+// sums are exact and order independent).
+__device__ __forceinline__ void add_limbs4(long long &a0, long long &a1, long long &a2, long long &a3, double x)
 {
     if (x == 0.0) return;
     const bool neg = x < 0.0;
@@ -1181,10 +1184,71 @@ __device__ __forceinline__ void add_limbs(long long (&v)[EST_FIELDS], double x)
     }
     const long long l0 = (long long)(lo & 0xFFFFFFFFull), l1 = (long long)(lo >> 32);
     const long long l2 = (long long)(hi & 0xFFFFFFFFull), l3 = (long long)(hi >> 32);
-    v[F_L0] += neg ? -l0 : l0;
-    v[F_L1] += neg ? -l1 : l1;
-    v[F_L2] += neg ? -l2 : l2;
-    v[F_L3] += neg ? -l3 : l3;
+    a0 += neg ? -l0 : l0;
+    a1 += neg ? -l1 : l1;
+    a2 += neg ? -l2 : l2;
+    a3 += neg ? -l3 : l3;
+}
+
+__device__ __forceinline__ void add_limbs(long long (&v)[EST_FIELDS], double x)
+{
+    add_limbs4(v[F_L0], v[F_L1], v[F_L2], v[F_L3], x);
+}
+
+// The value sum_k a_k 2^(32k - 64) of four limb sums, rounded once to the
+// nearest FP64 value (ties to even).
+__device__ double limbs_to_double(long long a0, long long a1, long long a2, long long a3)
+{
+    // signed 128-bit total as (hi, lo), two's complement
+    uint64_t lo = 0, hi = 0;
+    auto add_shifted = [&](long long v, int s) {
+        // v * 2^s, s in {0, 32, 64, 96}, sign-extended to 128 bits
+        const uint64_t ext = v < 0 ? ~0ull : 0ull;
+        uint64_t vlo, vhi;
+        if (s == 0) { vlo = (uint64_t)v; vhi = ext; }
+        else if (s < 64) { vlo = (uint64_t)v << s; vhi = (ext << s) | ((uint64_t)v >> (64 - s)); }
+        else if (s == 64) { vlo = 0; vhi = (uint64_t)v; }
+        else { vlo = 0; vhi = (uint64_t)v << (s - 64); }
+        const uint64_t nlo = lo + vlo;
+        hi = hi + vhi + (nlo < lo ? 1ull : 0ull);
+        lo = nlo;
+    };
+    add_shifted(a0, 0);
+    add_shifted(a1, 32);
+    add_shifted(a2, 64);
+    add_shifted(a3, 96);
+    if ((hi | lo) == 0) return 0.0;
+    const bool neg = (long long)hi < 0;
+    if (neg) {
+        lo = ~lo + 1ull;
+        hi = ~hi + (lo == 0 ? 1ull : 0ull);
+    }
+    // leading bit position of the magnitude
+    const int msb = hi ? 127 - __clzll(hi) : 63 - __clzll(lo);
+    double r;
+    if (msb < 53) {
+        r = (double)lo;  // exact
+    } else {
+        const int shift = msb - 52;  // bits below the 53-bit mantissa
+        uint64_t m, rem_hi_bit, rem_rest;
+        // m = magnitude >> shift; the dropped bits decide the rounding
+        if (shift >= 64) {
+            m = hi >> (shift - 64);
+            const int rs = shift - 64;  // dropped bits of hi below m, then all of lo
+            const uint64_t dh = rs ? (hi & ((1ull << rs) - 1)) : 0ull;
+            rem_hi_bit = rs ? (dh >> (rs - 1)) & 1ull : (lo >> 63);
+            rem_rest = rs ? ((dh & ((1ull << (rs - 1)) - 1)) | lo) : (lo & ~(1ull << 63));
+        } else {
+            m = (lo >> shift) | (shift ? hi << (64 - shift) : 0ull);
+            const uint64_t dl = lo & ((1ull << shift) - 1);  // shift >= 1 here
+            rem_hi_bit = (dl >> (shift - 1)) & 1ull;
+            rem_rest = dl & ((1ull << (shift - 1)) - 1);
+        }
+        if (rem_hi_bit && (rem_rest || (m & 1ull))) m += 1;
+        r = ldexp((double)m, shift);  // m <= 2^53: exact
+    }
+    r = r * 0x1p-64;
+    return neg ? -r : r;
 }
 
 // spawning attempts of a determinant holding p units: |p| for integer walkers,
@@ -1602,9 +1666,9 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
 }
 
 // ---------------------------------------------------------------------------
-// deterministic projection (Sec. 2.1 semi-stochastic): y = K_DD n_D with 64
-// interleaved partial sums (j = lane mod 64) taken in increasing j, combined
-// by a fixed halving tree; then n_D += SR(-dtau (y - S n_D))
+// deterministic projection (Sec. 2.1 semi-stochastic): y = K_DD n_D, summed
+// exactly in fixed point and rounded once (FP64 mode), or as BF16 x3 products
+// with FP32 accumulation (split mode); then n_D += SR(-dtau (y - S n_D))
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint16_t bf16_rn(float f)
 {
@@ -1663,27 +1727,27 @@ __global__ __launch_bounds__(256) void k_det_project_fp64(Work w, int mode)
     for (long long job = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); job < rows;
          job += (long long)gridDim.x * (blockDim.x >> 6)) {
         // shared space: the replicas of one row of K_DD are consecutive jobs
-        // (the row is read once from memory); the sum of every row is the same
+        // (the row is read once from memory)
         const int rep = w.ds.shared ? (int)(job % w.R) : (int)(job / n);
         const int d = w.ds.shared ? (int)(job / w.R) : (int)(job % n);
         const long long row = (long long)rep * n + d;
         const double *K = w.ds.K + ((size_t)(w.ds.shared ? 0 : rep) * n + d) * n;
         const double *cv = w.ds.c + (size_t)rep * n;
-        double part = 0.0, pabs = 0.0;
+        // y = sum_j K_ij n_j, exact in fixed point (2^-64), rounded once: the
+        // order of the terms over lanes and the wave reduction does not matter
+        long long a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        double pabs = 0.0;
         for (int j = lane; j < n; j += 64) {
-            part = part + K[j] * cv[j];
+            add_limbs4(a0, a1, a2, a3, K[j] * cv[j]);
             if (mode == 1) pabs = pabs + fabs(K[j]) * fabs(cv[j]);
         }
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-            const double o = __shfl_down(part, step, 64);
-            const double oa = __shfl_down(pabs, step, 64);
-            if (lane < step) {
-                part = part + o;
-                pabs = pabs + oa;
-            }
-        }
+        a0 = wave_sum<long long>(a0);
+        a1 = wave_sum<long long>(a1);
+        a2 = wave_sum<long long>(a2);
+        a3 = wave_sum<long long>(a3);
+        if (mode == 1) pabs = wave_sum<double>(pabs);
         if (lane == 0) {
+            const double part = limbs_to_double(a0, a1, a2, a3);
             if (mode == 0) {
                 det_update(w, c, rep, row, part, cv[d]);
             } else {
