@@ -1,14 +1,25 @@
 #!/usr/bin/env python
 """FCIQMC iteration throughput on one MI355X.
 
-Workload: initiator FCIQMC on the 3D uniform electron gas, 14 electrons
-(7 + 7), rs = 1, 57 plane waves (114 spin-orbitals, two-word keys), Coulomb
-4 pi / (L^3 k^2), real weights in 1/256 units, spawn cutoff 0.1, initiator
-threshold 3, dtau = 0.002, target 1e7 walkers, shift varied every 10
+Default workload: initiator FCIQMC on the 3D uniform electron gas, 14
+electrons (7 + 7), rs = 1, 57 plane waves (114 spin-orbitals, two-word keys),
+Coulomb 4 pi / (L^3 k^2), real weights in 1/256 units, spawn cutoff 0.1,
+initiator threshold 3, dtau = 0.002, target 1e7 walkers, shift varied every 10
 iterations with damping 0.05; synthetic (the system is defined by its
-parameters). One step = one whole projector iteration: attempt scan,
-spawning, radix sort, segmented reduction, merge with death/initiator,
-estimators and the host shift update.
+parameters). The workload runs 5000 iterations and times the last 1000: the
+first 4000 (equilibration, part of the workload) bring the population to its
+target and let the shift settle; --warmup adds iterations after them and
+--steps sets how many are timed.
+
+One step = one whole projector iteration: spawning, radix sort, segmented
+reduction, merge with death/initiator rule, estimators and the host shift
+update. The timed window is replayed from captured HIP graphs (one per block of
+iterations between shift updates) and bracketed by one pair of HIP events on
+the context's stream plus device synchronisation; per-kernel durations come
+from an equally long window right after it with an event around every launch
+(events inside a captured graph record no elapsed time), at the same steady
+state. A rocprofv3 run with --selected-regions profiles exactly those two
+windows (roctxProfilerResume / roctxProfilerPause around them).
 
 Prints one JSON line: walker updates/s = sum over the timed iterations of the
 walker population at the start of each iteration, divided by the wall time.
@@ -50,12 +61,12 @@ def algorithmic_bytes(hist_prev, hist, W, ds_active=False, instances=1):
     return out
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if the
-    kernel sources are the ones it was measured on (else None)."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of the
+    workload, if the kernel sources are the ones it was measured on (else None)."""
     import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_ueg14.json")
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -69,41 +80,80 @@ def measured_traffic(kernel):
     return None if k is None else k["bytes_per_launch"]
 
 
-def cpu_baseline(state, budget_s=20.0, max_iter=50, max_dets=4_000_000):
+class ProfilerRegion:
+    """roctxProfilerResume(0) / roctxProfilerPause(0): under `rocprofv3
+    --selected-regions` only what runs between them is traced or counted. No-op
+    without the profiler (or without the roctx library)."""
+
+    def __init__(self):
+        import ctypes
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so", "/opt/rocm/lib/librocprofiler-sdk-roctx.so"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(0)
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(0)
+
+
+def host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cores": os.cpu_count(),
+            "cores_available": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_baseline(state, spec, budget_s=20.0, max_iter=50, max_dets=4_000_000):
     """The oracle, single thread, continuing from a bounded sample of the GPU's
     state at the start of the timed window: every k-th determinant of the list
     in key order (at most max_dets), with the same shift and iteration, for as
-    many whole iterations as fit in about budget_s seconds. Work per walker
-    update is what is compared; the sample keeps the oracle's run short."""
+    many whole iterations as fit in about budget_s seconds (at least one). Work
+    per walker update is what is compared; the sample keeps the oracle's run
+    short."""
     from oracle import oracle as O
-    from paper_1811_11679_amd import workloads
     keys_all, pops_all, e, (sh, nprev, vary) = state
     k = max(1, -(-len(pops_all) // max_dets))
     keys, pops = keys_all[::k], pops_all[::k]
-    w = workloads.UEG14
-    s, q = w["system"], w["qmc"]
+    s, q = spec["system"], spec["qmc"]
     sysd = O.System.ueg(s["rs"], s["ecut_n2"], s["n_alpha"], s["n_beta"])
     run = O.Run(sysd, O.make_qmc(tau=q["tau"], seed=q["rng_seed"], init_pop=q["init_pop"],
                                  target_population=q["target_population"], shift_period=q["shift_period"],
                                  shift_damping=q["shift_damping"], excit_gen=O.EXGEN_UEG, initiator=1,
-                                 initiator_threshold=q["initiator_threshold"], fixed_point_bits=8,
+                                 initiator_threshold=q["initiator_threshold"], fixed_point_bits=q["fixed_point_bits"],
                                  spawn_cutoff=q["spawn_cutoff"]))
     run.import_walkers(keys, pops, shift=sh, iteration=int(e["iteration"]), vary=vary, n_prev=max(1, nprev // k))
+    scale = 2.0 ** q["fixed_point_bits"]
     nw_prev = run.estimators()["n_walkers_units"]
     upd, it = 0.0, 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and it < max_iter:
+    while (time.perf_counter() - t0 < budget_s or it == 0) and it < max_iter:
         run.step(1)
-        upd += nw_prev / 256.0
+        upd += nw_prev / scale
         nw_prev = run.estimators()["n_walkers_units"]
         it += 1
         print(f"# oracle iteration {it}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
-    return {"value": upd / dt, "unit": "walker updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{it} iterations ({e['iteration'] + 1}..{e['iteration'] + it}) from every {k}-th "
-                      f"determinant of the GPU list at the start of the timed window ({len(pops)} of "
-                      f"{len(pops_all)} determinants, {abs(pops.astype('int64')).sum() / 256:.4g} walkers), "
-                      f"single thread"}
+    out = {"value": upd / dt, "unit": "walker updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"{it} iterations ({e['iteration'] + 1}..{e['iteration'] + it}) from every {k}-th "
+                     f"determinant of the GPU list at the start of the timed window ({len(pops)} of "
+                     f"{len(pops_all)} determinants, {abs(pops.astype('int64')).sum() / scale:.4g} walkers), "
+                     f"single thread"}
+    out.update(host_cpu())
+    return out
 
 
 def batch_capacity(inst):
@@ -155,10 +205,13 @@ def run_batch64(args):
     # launch geometry is searched near the end of the equilibration, where the
     # populations are close to their targets, one context at a time; it does
     # not change the results
-    warm_to(int(args.warmup * 0.8))
+    # the workload runs 5000 iterations and times the last 1000: 4000 of
+    # equilibration, then --warmup more
+    equil = 4000 + args.warmup
+    warm_to(int(equil * 0.8))
     tuned = [autotune.tune(c, iters=3, log=lambda m, k=k: log(f"context {k}: {m}"))
              for k, c in enumerate(bt.contexts)]
-    warm_to(args.warmup)
+    warm_to(equil)
     t_start = int(bt.estimators(0)["iteration"])
     e_start = [bt.estimators(i) for i in range(n)]
     torch.cuda.synchronize()
@@ -236,7 +289,10 @@ def run_mol30(args):
     w = workloads.MOL30
     h1, eri = synth.molecular_integrals()
     log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
-    start = max(args.warmup - 300, 1)
+    # equilibration of 4000 iterations (part of the workload) plus --warmup;
+    # the deterministic space is chosen 300 iterations before the timed window
+    equil = 4000 + args.warmup
+    start = max(equil - 300, 1)
     tgt = 1e7 / R
     results = {}
     for prec in (F.SS_FP64, F.SS_SPLIT_BF16):
@@ -248,8 +304,8 @@ def run_mol30(args):
         ctx = F.Context([sysd] * R, qs, ss, main_capacity=args.main_capacity, spawn_capacity=args.spawn_capacity)
         t0 = time.perf_counter()
         done = 0
-        while done < args.warmup:
-            k = min(250, args.warmup - done)
+        while done < equil:
+            k = min(250, equil - done)
             ctx.step(k)
             done += k
             nw = sum(ctx.estimators(r)["n_walkers_units"] for r in range(R)) / 256.0
@@ -302,7 +358,7 @@ def run_mol30(args):
         "data": "synthetic",
         "config": {"workload": f"mol30_semistochastic_D2000_R{R}_target1e7", "replicas": R,
                    "deterministic_space": 2000, "shared_space": R > 1, "selection_iteration": start,
-                   "timed_iterations": f"{args.warmup + 1}..{args.warmup + args.steps}",
+                   "timed_iterations": f"{equil + 1}..{equil + args.steps}",
                    "parallelism": "single GPU"},
         "fp64": fp,
         "split_bf16x3": split,
@@ -312,182 +368,101 @@ def run_mol30(args):
     print(json.dumps(out))
 
 
-def run_ueg54(args):
-    """Large single instance: 54-electron gas (27 + 27), rs = 1, 251 plane waves
-    (502 spin-orbitals, 8-word keys), initiator, 1/256 fixed point, dtau =
-    0.0005, population target set so that the list holds about 2e8
-    determinants, semi-stochastic with D = 8192 in split BF16 x3 precision
-    and the FP64 projection computed beside it every 10 iterations (its time
-    and the error of the split result)."""
+def single_spec(args):
+    """The single-instance workloads: 14-electron gas (default) and the
+    54-electron gas with its split-precision deterministic space."""
     from paper_1811_11679_amd import fciqmc as F
     from paper_1811_11679_amd import workloads
-
+    if args.workload == "ueg14":
+        w = workloads.UEG14
+        return dict(name="ueg14", w=w, system=w["system"], qmc=dict(w["qmc"]), ss=None,
+                    equilibration=w["equilibration"],
+                    config={"workload": "ueg14_rs1_57pw_initiator_target1e7", "electrons": 14, "rs": 1.0,
+                            "plane_waves": 57, "fixed_point": "1/256", "initiator_threshold": 3.0})
     w = workloads.UEG54
-    s, q = w["system"], dict(w["qmc"])
-    q["target_population"] = args.target
-    q["init_pop"] = args.init_pop
-    q["initial_shift"] = args.initial_shift
-    q["shift_damping"] = args.shift_damping
-    log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
-    sysd = F.make_system(F.UEG, rs=s["rs"], ecut_n2=s["ecut_n2"], n_alpha=s["n_alpha"], n_beta=s["n_beta"])
-    ss = F.SemiStoch(size=8192, start_iteration=max(args.warmup - 100, 1), precision=F.SS_SPLIT_BF16,
-                     check_period=10)
-    ctx = F.Context([sysd], [F.make_qmc(excit_gen=F.UEG, **q)], ss, main_capacity=args.main_capacity,
-                    spawn_capacity=args.spawn_capacity)
-    log(f"workspace {ctx.workspace.numel() / 1e9:.1f} GB, key words {ctx.W}")
-    t0 = time.perf_counter()
-    done = 0
-    while done < args.warmup:
-        k = min(20 if done < 400 else 100, args.warmup - done)
-        ctx.step(k)
-        done += k
-        e = ctx.estimators()
-        log(f"warmup {done}: N_w {e['n_walkers_units'] / 256:.4g}, {e['n_occupied']} determinants, "
-            f"{e['n_spawned']} spawned, shift {e['shift']:.5f}, {time.perf_counter() - t0:.1f} s")
-    e_start = ctx.estimators()
-    ctx.set_timing(True)
-    t1 = time.perf_counter()
-    done = 0
-    while done < args.steps:
-        k = min(100, args.steps - done)
-        ctx.step(k)
-        done += k
-        log(f"timed {done}: {time.perf_counter() - t1:.1f} s")
-    ctx.stream.synchronize()
-    dt = time.perf_counter() - t1
-    ctx.set_timing(False)
-    kt, niter = ctx.kernel_times()
-    it_ms = sorted(ctx.iteration_times())
-    hist = ctx.history()[-min(args.steps, 100):]
-    # the history of the last step call covers its iterations only
-    upd_note = "walker updates over the last timed step call"
-    upd = (sum(h["n_walkers_units"] for h in hist[:-1]) + hist[0]["n_walkers_units"]) / 256.0
-    errs = [h["ss_error"] for h in hist if h["ss_error"] > 0]
-    mean_ms = sum(it_ms) / len(it_ms) if it_ms else dt * 1e3 / args.steps
-    out = {
-        "metric": METRIC,
-        "value": (e_start["n_walkers_units"] / 256.0) / (dt / args.steps),
-        "unit": "walker updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64 (projection bf16x3/fp32 on MFMA)",
-        "data": "synthetic",
-        "config": {"workload": "ueg54_rs1_251pw_initiator_D8192", "electrons": 54, "plane_waves": 251,
-                   "key_words": ctx.W, "tau": q["tau"], "target_walkers": args.target,
-                   "timed_iterations": f"{e_start['iteration'] + 1}..{e_start['iteration'] + args.steps}",
-                   "parallelism": "single GPU"},
-        "walkers_start": e_start["n_walkers_units"] / 256.0,
-        "determinants_start": e_start["n_occupied"],
-        "determinants_end": hist[-1]["n_occupied"],
-        "spawned_per_iteration": sum(h["n_spawned"] for h in hist) / len(hist),
-        "walker_updates_per_s_window": upd / (sum(it_ms[-len(hist):]) * 1e-3) if it_ms else None,
-        "window_note": upd_note,
-        "iteration_ms_device": {"median": it_ms[len(it_ms) // 2], "p90": it_ms[(9 * len(it_ms)) // 10],
-                                "mean": mean_ms} if it_ms else None,
-        "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in kt.items() if v / max(niter, 1) > 0.005},
-        "projection_split_ms": kt["det_project"] / max(niter, 1),
-        "projection_fp64_ms_per_check": kt["det_check"] / max(1, niter // 10),
-        "ss_error_max": max(errs) if errs else None,
-        "ss_error_bound": hist[-1]["ss_error_bound"],
-        "shift_end": hist[-1]["shift"],
-        "proj_energy_end": hist[-1]["proj_energy"],
-        "warmup_s": time.perf_counter() - t0 - dt,
-    }
-    ctx.close()
-    print(json.dumps(out))
+    q = dict(w["qmc"])
+    for k, a in (("target_population", "target"), ("init_pop", "init_pop"), ("initial_shift", "initial_shift"),
+                 ("shift_damping", "shift_damping"), ("tau", "tau")):
+        if getattr(args, a) is not None:
+            q[k] = getattr(args, a)
+    equil = w["equilibration"]
+    ss = F.SemiStoch(size=w["semistoch"]["size"], start_iteration=w["semistoch"]["start_iteration"],
+                     precision=F.SS_SPLIT_BF16, check_period=10)
+    return dict(name="ueg54", w=w, system=w["system"], qmc=q, ss=ss, equilibration=equil,
+                config={"workload": "ueg54_rs1_251pw_initiator_D8192_split", "electrons": 54, "rs": 1.0,
+                        "plane_waves": 251, "fixed_point": "1/256", "initiator_threshold": 3.0,
+                        "deterministic_space": w["semistoch"]["size"], "projection": "bf16x3/fp32 MFMA"})
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=4000)
-    ap.add_argument("--main-capacity", type=int, default=None,
-                    help="determinant capacity (default 2^28; ueg54: 3.2e8, its list peaks near 2.73e8)")
-    ap.add_argument("--spawn-capacity", type=int, default=None, help="spawn capacity (default 2^27; ueg54: 1.6e8)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--target", type=float, default=2e7, help="ueg54: target walkers")
-    ap.add_argument("--init-pop", type=float, default=1e4, help="ueg54: initial walkers on the reference")
-    ap.add_argument("--shift-damping", type=float, default=1.0, help="ueg54: shift damping (zeta)")
-    ap.add_argument("--initial-shift", type=float, default=0.0,
-                    help="ueg54: initial shift (Hartree, relative to H_00), damps the initial growth")
-    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64", "mol30", "ueg54"],
-                    help="ueg14: the plain single-instance path; batch64: 64 batched instances vs plain runs; "
-                         "mol30: semi-stochastic molecular runs, FP64 vs split-precision projection")
-    ap.add_argument("--replicas", type=int, default=1, help="mol30: replicas sharing one deterministic space")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain device copy of 1 GiB (4 times) for counter calibration")
-    args = ap.parse_args()
-    big = args.workload == "ueg54"
-    if args.main_capacity is None:
-        args.main_capacity = 320_000_000 if big else 1 << 28
-    if args.spawn_capacity is None:
-        args.spawn_capacity = 160_000_000 if big else 1 << 27
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs is "
-              "designed but not implemented", file=sys.stderr)
-        sys.exit(2)
-
-    if args.workload == "batch64":
-        return run_batch64(args)
-    if args.workload == "mol30":
-        return run_mol30(args)
-    if args.workload == "ueg54":
-        return run_ueg54(args)
-
+def run_single(args):
+    """One instance: equilibrate (part of the workload), --warmup more
+    iterations, then --steps timed iterations under graph replay, then as many
+    again with per-kernel events for the roofline."""
     import torch
     from paper_1811_11679_amd import fciqmc as F
-    from paper_1811_11679_amd import workloads
 
-    w = workloads.UEG14
-    s, q = w["system"], dict(w["qmc"])
+    spec = single_spec(args)
+    s, q = spec["system"], spec["qmc"]
+    log = lambda m: print("# " + m, file=sys.stderr, flush=True)  # noqa: E731
     sysd = F.make_system(F.UEG, rs=s["rs"], ecut_n2=s["ecut_n2"], n_alpha=s["n_alpha"], n_beta=s["n_beta"])
-    ctx = F.Context([sysd], [F.make_qmc(excit_gen=2, **q)], main_capacity=args.main_capacity,
-                    spawn_capacity=args.spawn_capacity)
+    ctx = F.Context([sysd], [F.make_qmc(excit_gen=F.UEG, **q)], spec["ss"], main_capacity=args.main_capacity,
+                    spawn_capacity=args.spawn_capacity, graph=True)
+    log(f"workspace {ctx.workspace.numel() / 1e9:.1f} GB, key words {ctx.W}")
+    scale = 2.0 ** q["fixed_point_bits"]
     t_w0 = time.perf_counter()
+    pre = spec["equilibration"] + args.warmup
     done = 0
-    while done < args.warmup:
-        k = min(250, args.warmup - done)
+    while done < pre:
+        k = min(250, pre - done)
         ctx.step(k)
         done += k
         e = ctx.estimators()
-        print(f"# warmup {done}: N_w {e['n_walkers_units'] / 256:.4g} walkers, "
-              f"{e['n_occupied']} determinants, shift {e['shift']:.5f}, "
-              f"{time.perf_counter() - t_w0:.1f} s", file=sys.stderr, flush=True)
+        log(f"equilibration {done}/{pre}: N_w {e['n_walkers_units'] / scale:.4g} walkers, "
+            f"{e['n_occupied']} determinants, N_0 {e['ref_pop_units'] / scale:.4g}, shift {e['shift']:.5f}, "
+            f"E_proj {e['proj_energy']:.5f}, {time.perf_counter() - t_w0:.1f} s")
     warm_s = time.perf_counter() - t_w0
     e_start = ctx.estimators()
     start_state = None
     if not args.no_cpu_baseline:
         keys, pops = ctx.export()
         start_state = (keys, pops, e_start, ctx.shift_state())
-    ctx.set_timing(True)
+    prof = ProfilerRegion()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    prof.resume()
     t0 = time.perf_counter()
+    ev0.record(ctx.stream)
     ctx.step(args.steps)
+    ev1.record(ctx.stream)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.set_timing(False)
+    dt = time.perf_counter() - t0
     hist = ctx.history()[-args.steps:]
     prev = [e_start] + hist[:-1]
-    upd = sum(h["n_walkers_units"] for h in prev) / 256.0
-    dt = t1 - t0
+    upd = sum(h["n_walkers_units"] for h in prev) / scale
+    dev_ms = ev0.elapsed_time(ev1)
+    # kernel window: same length (at most 200 iterations), an event around every launch
+    nk = min(args.steps, 200)
+    e_k0 = ctx.estimators()
+    ctx.set_timing(True)
+    ctx.step(nk)
+    torch.cuda.synchronize()
+    prof.pause()
+    ctx.set_timing(False)
+    hk = ctx.history()[-nk:]
+    prevk = [e_k0] + hk[:-1]
     ktimes, niter = ctx.kernel_times()
     stages = ctx.stage_times()
     it_ms = sorted(ctx.iteration_times())
     dets = sum(h["n_occupied"] for h in prev)
     spawned = sum(h["n_spawned"] for h in hist)
-    # algorithmic bytes per kernel summed over the timed iterations
+    ds_active = spec["ss"] is not None
     tot_bytes = {}
-    for a, b in zip(prev, hist):
-        for k, v in algorithmic_bytes(a, b, ctx.W).items():
+    for a, b in zip(prevk, hk):
+        for k, v in algorithmic_bytes(a, b, ctx.W, ds_active=ds_active).items():
             tot_bytes[k] = tot_bytes.get(k, 0) + v
-    groups = {"sort_pass": [f"sort_pass{p}" for p in range(8)]}
-    cand = {"spawn": ["spawn"], "merge": ["merge"], "reduce": ["reduce"], "new_diag": ["new_diag"], **groups}
+    cand = {"spawn": ["spawn"], "merge": ["merge"], "reduce": ["reduce"], "new_diag": ["new_diag"],
+            "sort_pass": [f"sort_pass{p}" for p in range(8)]}
     best = max(cand, key=lambda g: sum(ktimes[k] for k in cand[g]))
     launches = niter * len(cand[best])
     avg_ms = sum(ktimes[k] for k in cand[best]) / max(launches, 1)
@@ -495,6 +470,15 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     ann_ms = stages["sort"] + stages["reduce"] + stages["merge"]
     ann_bytes = sum(tot_bytes[k] for k in tot_bytes if k.startswith("sort") or k in ("reduce", "merge"))
+    hwin = hist + hk
+    errs = [h["ss_error"] for h in hwin if h.get("ss_error", 0) > 0]
+    cfg = dict(spec["config"])
+    cfg.update({"key_words": ctx.W, "tau": q["tau"], "target_walkers": q["target_population"],
+                "init_pop": q["init_pop"], "shift_damping": q["shift_damping"],
+                "equilibration_iterations": spec["equilibration"],
+                "timed_iterations": f"{e_start['iteration'] + 1}..{hist[-1]['iteration']}",
+                "kernel_timing_iterations": f"{e_k0['iteration'] + 1}..{hk[-1]['iteration']}",
+                "graph_replay": True, "parallelism": "single GPU"})
     out = {
         "metric": METRIC,
         "value": upd / dt,
@@ -506,44 +490,94 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if spec["ss"] is None else "f64 (deterministic projection bf16x3/fp32 on MFMA)",
         "data": "synthetic",
-        "config": {"workload": "ueg14_rs1_57pw_initiator_target1e7", "electrons": 14, "rs": 1.0,
-                   "plane_waves": 57, "key_words": ctx.W, "tau": q["tau"], "fixed_point": "1/256",
-                   "initiator_threshold": 3.0, "target_walkers": q["target_population"],
-                   "timed_iterations": f"{e_start['iteration'] + 1}..{hist[-1]['iteration']}",
-                   "parallelism": "single GPU"},
+        "config": cfg,
         "roofline": {"bound": "hbm", "kernel": best, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(best),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(best, spec["name"]),
                      "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch},
+        "device_ms_per_step": dev_ms / args.steps,
         "annihilation_gbps_algorithmic": ann_bytes / (ann_ms * 1e-3) / 1e9 if ann_ms > 0 else None,
-        "iteration_ms_device": {"median": it_ms[len(it_ms) // 2], "p90": it_ms[(9 * len(it_ms)) // 10],
-                                "min": it_ms[0], "max": it_ms[-1]} if it_ms else None,
+        "iteration_ms_device_kernel_window": {"median": it_ms[len(it_ms) // 2], "p90": it_ms[(9 * len(it_ms)) // 10],
+                                              "min": it_ms[0], "max": it_ms[-1]} if it_ms else None,
         "determinant_updates_per_s": dets / dt,
         "spawns_per_s": spawned / dt,
         "stage_ms_per_iteration": {k: v / max(niter, 1) for k, v in stages.items()},
-        "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in ktimes.items()},
-        "walkers_start": e_start["n_walkers_units"] / 256.0,
-        "walkers_end": hist[-1]["n_walkers_units"] / 256.0,
+        "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in ktimes.items() if v > 0},
+        "walkers_start": e_start["n_walkers_units"] / scale,
+        "walkers_end": hist[-1]["n_walkers_units"] / scale,
+        "determinants_start": e_start["n_occupied"],
         "determinants_end": hist[-1]["n_occupied"],
-        "spawned_per_iteration": sum(h["n_spawned"] for h in hist) / len(hist),
-        "shift_end": hist[-1]["shift"],
-        "proj_energy_end": hist[-1]["proj_energy"],
+        "spawned_per_iteration": spawned / len(hist),
+        "ref_pop_start": e_start["ref_pop_units"] / scale,
+        "ref_pop_end": hist[-1]["ref_pop_units"] / scale,
+        "shift_mean_window": sum(h["shift"] for h in hist) / len(hist),
+        "proj_energy_window": (sum(h["proj_numerator"] for h in hist) / sum(h["ref_pop_units"] for h in hist) * scale)
+        if sum(h["ref_pop_units"] for h in hist) else None,
         "warmup_s": warm_s,
     }
+    if ds_active:
+        out["ss_error_max"] = max(errs) if errs else None
+        out["ss_error_bound"] = hwin[-1]["ss_error_bound"]
+        out["projection_ms_per_iteration"] = ktimes["det_project"] / max(niter, 1)
     ctx.close()
     if args.calibrate_copy:
         # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE per
         # dispatch scale the counters of the FCIQMC kernels to bytes
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
+        prof.resume()
         for _ in range(4):
             dst.copy_(src)
         torch.cuda.synchronize()
+        prof.pause()
         out["copy_calibration_bytes"] = 1 << 30
     if start_state is not None:
-        out["cpu_baseline"] = cpu_baseline(start_state)
+        out["cpu_baseline"] = cpu_baseline(start_state, spec)
     print(json.dumps(out))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000, help="timed iterations")
+    ap.add_argument("--warmup", type=int, default=0,
+                    help="untimed iterations after the workload's own equilibration (never shortens it)")
+    ap.add_argument("--main-capacity", type=int, default=None,
+                    help="determinant capacity (default 2^28; ueg54: 3.3e8)")
+    ap.add_argument("--spawn-capacity", type=int, default=None, help="spawn capacity (default 2^27; ueg54: 2e8)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--target", type=float, default=None, help="ueg54: target walkers")
+    ap.add_argument("--init-pop", type=float, default=None, help="ueg54: initial walkers on the reference")
+    ap.add_argument("--shift-damping", type=float, default=None, help="ueg54: shift damping (zeta)")
+    ap.add_argument("--initial-shift", type=float, default=None, help="ueg54: initial shift (Hartree, relative to H_00)")
+    ap.add_argument("--tau", type=float, default=None, help="ueg54: time step")
+    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64", "mol30", "ueg54"],
+                    help="ueg14: the plain single-instance path; ueg54: the large single instance; batch64: 64 "
+                         "batched instances vs plain runs; mol30: semi-stochastic molecular runs, FP64 vs split")
+    ap.add_argument("--replicas", type=int, default=1, help="mol30: replicas sharing one deterministic space")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain device copy of 1 GiB (4 times) for counter calibration")
+    args = ap.parse_args()
+    big = args.workload == "ueg54"
+    if args.main_capacity is None:
+        args.main_capacity = 330_000_000 if big else 1 << 28
+    if args.spawn_capacity is None:
+        args.spawn_capacity = 200_000_000 if big else 1 << 27
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs is "
+              "designed but not implemented", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1:
+        print("--steps must be at least 1", file=sys.stderr)
+        sys.exit(2)
+
+    if args.workload == "batch64":
+        return run_batch64(args)
+    if args.workload == "mol30":
+        return run_mol30(args)
+    return run_single(args)
 
 
 if __name__ == "__main__":
