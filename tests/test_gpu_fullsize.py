@@ -9,6 +9,12 @@ list on the CPU:
   parents (an oracle run holding only that parent draws the same keyed random
   numbers) must all appear in the GPU's spawned list, and the new population
   of sampled parents that receive no spawns must equal the oracle's death step;
+* merged populations of sampled spawned-to determinants: the oracle's death
+  step of the determinant's own entry plus every spawn the GPU sent to it, and
+  for determinants that were unoccupied the initiator rule (accepted iff some
+  contribution came from an initiator); one iteration later the death step of
+  sampled new determinants, which uses the diagonal element the GPU computed
+  for them when they were created;
 * properties that hold at any size: the signed population balance of the
   annihilation, the walker count, the spawned amplitude sum, distinct and
   well-formed keys.
@@ -39,21 +45,50 @@ def _find(sorted_keys, key):
     return int(j) if j < b and int(sorted_keys[j, 0]) == key[0] else -1
 
 
-def test_ueg14_full_size_iteration_sampled_against_oracle():
+def _oracle_qmc(q):
+    return O.make_qmc(tau=q["tau"], seed=q["rng_seed"], init_pop=q["init_pop"], target_population=q["target_population"],
+                      shift_period=q["shift_period"], shift_damping=q["shift_damping"], excit_gen=O.EXGEN_UEG,
+                      initiator=1, initiator_threshold=q["initiator_threshold"], fixed_point_bits=8,
+                      spawn_cutoff=q["spawn_cutoff"])
+
+
+def _own_after_step(osys, oq, key, pop, shift, it, vary, nprev):
+    """The oracle's population of a lone determinant after one iteration: its
+    death step (a lone entry receives no spawns)."""
+    run = O.Run(osys, oq)
+    run.import_walkers(key[None, :], np.array([pop], np.int32), shift=shift, iteration=it, vary=vary, n_prev=nprev)
+    run.step(1)
+    kd, pd = run.export()
+    return dict(zip(_words_to_tuples(kd), pd.tolist())).get(tuple(int(x) for x in key), 0), run
+
+
+def _spawn_groups(sk, sa, si):
+    """Spawned records sorted by key, with [lo, hi) ranges per distinct key."""
+    so = np.lexsort(sk.T)
+    sk, sa, si = sk[so], sa[so], si[so]
+    new = np.ones(len(sk), bool)
+    new[1:] = np.any(sk[1:] != sk[:-1], axis=1)
+    starts = np.flatnonzero(new)
+    ends = np.append(starts[1:], len(sk))
+    return sk, sa, si, starts, ends
+
+
+def _full_size_iteration(pre_iterations, min_dets):
     from paper_1811_11679_amd import fciqmc as F
     w = workloads.UEG14
     s, q = w["system"], w["qmc"]
-    say("[case] UEG14 full size: 200 iterations, then one iteration checked")
+    say(f"[case] UEG14 full size, graph replay: {pre_iterations} iterations, then two iterations checked")
     ctx = F.Context([F.make_system(F.UEG, rs=s["rs"], ecut_n2=s["ecut_n2"], n_alpha=s["n_alpha"], n_beta=s["n_beta"])],
-                    [F.make_qmc(excit_gen=F.UEG, **q)], main_capacity=1 << 28, spawn_capacity=1 << 27)
-    ctx.step(200)
+                    [F.make_qmc(excit_gen=F.UEG, **q)], main_capacity=1 << 28, spawn_capacity=1 << 27, graph=True)
+    ctx.step(pre_iterations)
     e0 = ctx.estimators()
     shift, nprev, vary = ctx.shift_state()
     k0, p0 = ctx.export()
-    say(f"[case] {len(p0)} determinants, {e0['n_walkers_units'] / 256:.4g} walkers")
-    assert len(p0) > 10_000_000
+    say(f"[case] {len(p0)} determinants, {e0['n_walkers_units'] / 256:.4g} walkers, shift {shift:.5f}")
+    assert len(p0) > min_dets
     ctx.step(1)
     e1 = ctx.estimators()
+    shift1, nprev1, vary1 = ctx.shift_state()
     k1, p1 = ctx.export()
     sk, sa, si = ctx.spawns()
     say(f"[case] {len(sa)} spawns, {len(p1)} determinants after")
@@ -76,31 +111,24 @@ def test_ueg14_full_size_iteration_sampled_against_oracle():
         b = bin(int(k1[i, 0] & beta)).count("1") + bin(int(k1[i, 1] & beta)).count("1")
         assert a == 7 and b == 7 and int(k1[i, 1]) >> (114 - 64) == 0
 
-    # sampled parents against oracle runs that hold only that parent
     osys = O.System.ueg(s["rs"], s["ecut_n2"], s["n_alpha"], s["n_beta"])
-    oq = O.make_qmc(tau=q["tau"], seed=q["rng_seed"], init_pop=q["init_pop"], target_population=q["target_population"],
-                    shift_period=q["shift_period"], shift_damping=q["shift_damping"], excit_gen=O.EXGEN_UEG,
-                    initiator=1, initiator_threshold=q["initiator_threshold"], fixed_point_bits=8,
-                    spawn_cutoff=q["spawn_cutoff"])
-    so = np.lexsort(sk.T)
-    sk_sorted = sk[so]
+    oq = _oracle_qmc(q)
+    it0 = int(e0["iteration"])
+    gk, ga, gi, g_lo, g_hi = _spawn_groups(sk, sa, si)
+
+    # 1. sampled parents against oracle runs that hold only that parent
     idx = rng.choice(len(p0), N_SAMPLE, replace=False)
     # the parent with the largest population (the reference) as well
     idx = np.concatenate([idx, [int(np.argmax(np.abs(p0)))]])
     wanted = {}
     deaths_checked = 0
     for i in idx:
-        run = O.Run(osys, oq)
-        run.import_walkers(k0[i:i + 1], p0[i:i + 1], shift=shift, iteration=int(e0["iteration"]), vary=vary,
-                           n_prev=nprev)
-        run.step(1)
+        own, run = _own_after_step(osys, oq, k0[i], int(p0[i]), shift, it0, vary, nprev)
         ok_, oa, oi = run.spawns()
         for kk, a, f in zip(_words_to_tuples(ok_), oa.tolist(), oi.tolist()):
             wanted.setdefault(kk, []).append((a, f))
         parent = (int(k0[i, 0]), int(k0[i, 1]))
-        if _find(sk_sorted, parent) < 0:
-            kd, pd = run.export()
-            own = dict(zip(_words_to_tuples(kd), pd.tolist())).get(parent, 0)
+        if _find(gk, parent) < 0:
             j = _find(k1, parent)
             gpu = int(p1[j]) if j >= 0 else 0
             assert gpu == own, (parent, gpu, own)
@@ -120,4 +148,72 @@ def test_ueg14_full_size_iteration_sampled_against_oracle():
             n_checked += 1
     say(f"[case] {n_checked} sampled spawns and {deaths_checked} death steps identical to the oracle")
     assert n_checked > 1000
+
+    # 2. merged populations of sampled spawned-to determinants
+    groups = rng.choice(len(g_lo), N_SAMPLE, replace=False)
+    n_occ = n_new = n_rej = 0
+    new_children = []
+    for g in groups:
+        key = gk[g_lo[g]]
+        amps = ga[g_lo[g]:g_hi[g]].astype(np.int64)
+        inits = gi[g_lo[g]:g_hi[g]]
+        i0 = _find(k0, key)
+        if i0 >= 0:
+            own, _ = _own_after_step(osys, oq, key, int(p0[i0]), shift, it0, vary, nprev)
+            want = own + int(amps.sum())
+            n_occ += 1
+        else:
+            accepted = bool(inits.any()) and int(amps.sum()) != 0
+            want = int(amps.sum()) if accepted else 0
+            n_new += int(accepted)
+            n_rej += int(not accepted and int(amps.sum()) != 0)
+        j = _find(k1, key)
+        gpu = int(p1[j]) if j >= 0 else 0
+        assert gpu == want, (tuple(int(x) for x in key), gpu, want)
+        if i0 < 0 and j >= 0:
+            new_children.append(j)
+    say(f"[case] merged populations of {len(groups)} spawned-to determinants identical: {n_occ} occupied, "
+        f"{n_new} created, {n_rej} refused by the initiator rule")
+    assert n_occ > 0 and n_new > 0
+
+    # 3. one more iteration: the death step of sampled new determinants (their
+    # K_jj was computed on the GPU when they were created)
+    extra = []
+    for g in rng.choice(len(g_lo), 4 * N_SAMPLE, replace=False):
+        key = gk[g_lo[g]]
+        if _find(k0, key) < 0:
+            j = _find(k1, key)
+            if j >= 0:
+                extra.append(j)
+    new_children = sorted(set(new_children + extra))
+    ctx.step(1)
+    k2, p2 = ctx.export()
+    sk2, sa2, si2 = ctx.spawns()
+    hk, ha, hi_, h_lo, h_hi = _spawn_groups(sk2, sa2, si2)
+    it1 = int(e1["iteration"])
+    checked = 0
+    for j in new_children:
+        key = k1[j]
+        own, _ = _own_after_step(osys, oq, key, int(p1[j]), shift1, it1, vary1, nprev1)
+        g = _find(hk, key)  # first record of the key: the start of its group
+        inc = 0
+        if g >= 0:
+            grp = int(np.searchsorted(h_lo, g))
+            inc = int(ha[h_lo[grp]:h_hi[grp]].astype(np.int64).sum())
+        jj = _find(k2, key)
+        gpu = int(p2[jj]) if jj >= 0 else 0
+        assert gpu == own + inc, (tuple(int(x) for x in key), gpu, own, inc)
+        checked += 1
+    say(f"[case] death steps of {checked} new determinants identical to the oracle")
+    assert checked > 50
     ctx.close()
+
+
+def test_ueg14_full_size_iteration_sampled_against_oracle():
+    """Growth phase: the list still grows (shift not yet varied)."""
+    _full_size_iteration(200, 10_000_000)
+
+
+def test_ueg14_full_size_steady_state_sampled_against_oracle():
+    """Steady state of the benchmark workload: population at target, shift settled."""
+    _full_size_iteration(1500, 50_000_000)
