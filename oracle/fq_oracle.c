@@ -725,6 +725,27 @@ static int64_t n_attempts(const or_run *r, int32_t pop)
 
 static int is_reference(const or_run *r, const uint64_t *key) { return key_cmp(key, r->s->ref, r->W) == 0; }
 
+/* Words of one determinant (s->W) in a key: the key itself for FCIQMC; for
+ * the density-matrix methods the bra is the first half, the ket the second. */
+static int det_words(const or_run *r) { return r->s->W; }
+
+/* The diagonal element of an entry, relative to H_00, as death uses it.
+ * FCIQMC: K_ii = H_ii - H_00.
+ * DMQMC: the symmetrised Bloch equation (Sec. 2.3, eq. dmqmc) gives the pair
+ *   (i, j) the diagonal (H_ii + H_jj) / 2: here (K_ii + K_jj) / 2.
+ * IP-DMQMC (eq. ipdmqmc, H^0 the diagonal part of H): df/dtau = H^0 f - f H
+ *   gives the pair (i, j) the diagonal H_jj - H^0_ii = K_jj - K_ii. */
+static double entry_kdiag(const or_run *r, const uint64_t *key)
+{
+    const or_sys *s = r->s;
+    if (r->q.method == OR_FCIQMC) return or_diag(s, key) - s->H00;
+    int w = det_words(r);
+    double ki = or_diag(s, key) - s->H00;
+    double kj = or_diag(s, key + w) - s->H00;
+    if (r->q.method == OR_DMQMC) return (ki + kj) * 0.5;
+    return kj - ki;
+}
+
 /* Fixed-point accumulation of one FP64 term at resolution 2^-64, split into
  * four 32-bit limbs; the limb sums are exact and order independent. */
 static void acc_term(int64_t limbs[4], double x)
@@ -747,19 +768,35 @@ static double limbs_value(const int64_t limbs[4])
 }
 
 /* Projected energy (tutorial appendix): numerator sum_{j != 0} H_0j N_j
- * over the determinants at most doubly excited from D_0; N_0 as denominator. */
+ * over the determinants at most doubly excited from D_0; N_0 as denominator.
+ * Density-matrix methods (Sec. 2.3): the thermal energy Tr(rho H) / Tr(rho),
+ * numerator sum over pairs of rho_ij H_ji (pairs at most doubly excited from
+ * each other; H_ii on the diagonal), denominator the trace sum_i rho_ii. */
 static void compute_estimators(or_run *r)
 {
     or_estimators *e = &r->est;
     int64_t nw = 0, n0 = 0;
     int64_t limbs[4] = {0, 0, 0, 0};
+    int dm = r->q.method != OR_FCIQMC;
+    int w = det_words(r);
     for (int64_t i = 0; i < r->n; ++i) {
         const uint64_t *k = r->keys + (size_t)i * r->W;
         int32_t p = r->pops[i];
         nw += p < 0 ? -(int64_t)p : p;
+        if (dm) {
+            int nd = 0;
+            for (int x = 0; x < w; ++x) nd += __builtin_popcountll(k[x] ^ k[w + x]);
+            if (nd == 0) {
+                n0 += p;
+                acc_term(limbs, or_diag(r->s, k) * (double)p);
+            } else if (nd == 2 || nd == 4) {
+                acc_term(limbs, or_hij(r->s, k + w, k) * (double)p);
+            }
+            continue;
+        }
         if (is_reference(r, k)) { n0 = p; continue; }
         int nd = 0;
-        for (int w = 0; w < r->W; ++w) nd += __builtin_popcountll(k[w] ^ r->s->ref[w]);
+        for (int x = 0; x < r->W; ++x) nd += __builtin_popcountll(k[x] ^ r->s->ref[x]);
         if (nd != 2 && nd != 4) continue;
         double h = or_hij(r->s, r->s->ref, k);
         acc_term(limbs, h * (double)p);
@@ -789,19 +826,26 @@ or_run *or_run_new(const or_sys *s, const or_qmc *q)
     if (q->excit_gen == OR_EXGEN_HUB && s->kind != OR_HUBBARD) return NULL;
     if (q->excit_gen == OR_EXGEN_UEG && s->kind != OR_UEG) return NULL;
     if (q->excit_gen == OR_EXGEN_HEATBATH && s->kind != OR_MOLECULAR) return NULL;
+    if (q->method < OR_FCIQMC || q->method > OR_IPDMQMC) return NULL;
+    /* density matrices: pairs of determinants of at most four words, no
+       initiator rule, deterministic space or time-step search */
+    if (q->method != OR_FCIQMC && (2 * s->W > OR_MAXW || q->initiator || q->ss_size > 0 || q->tau_search))
+        return NULL;
     or_run *r = (or_run *)calloc(1, sizeof(or_run));
     r->s = s;
     r->q = *q;
-    r->W = s->W;
+    r->W = q->method == OR_FCIQMC ? s->W : 2 * s->W;
     double scale = ldexp(1.0, q->fixed_point_bits);
     r->cu = q->fixed_point_bits ? (int64_t)floor(q->spawn_cutoff * scale + 0.5) : 0;
     r->thr = (int64_t)floor(q->initiator_threshold * scale);
     r->rkey[0] = (uint32_t)q->seed;
     r->rkey[1] = (uint32_t)(q->seed >> 32) ^ (uint32_t)q->replica_id;
     list_reserve(r, 1);
-    memcpy(r->keys, s->ref, sizeof(uint64_t) * r->W);
+    /* the reference, or the pair (D_0, D_0) */
+    memcpy(r->keys, s->ref, sizeof(uint64_t) * s->W);
+    if (r->W != s->W) memcpy(r->keys + s->W, s->ref, sizeof(uint64_t) * s->W);
     r->pops[0] = (int32_t)floor(q->init_pop * scale + 0.5);
-    r->kdiag[0] = 0.0;
+    r->kdiag[0] = entry_kdiag(r, r->keys);
     r->dslot[0] = -1;
     r->n = 1;
     r->S = q->initial_shift;
@@ -868,6 +912,60 @@ static int spawn_attempt(or_run *r, const uint64_t *key, uint64_t h, int32_t n0,
     int sn = n0 > 0 ? 1 : -1;
     int32_t amp = (int32_t)(-(sh * sn) * kk);
     push_spawn(r, child, amp, init);
+    return OR_OK;
+}
+
+/* ---- one spawning attempt of a density-matrix pair (Sec. 2.3) ----
+ * DMQMC, eq. (dmqmc): rho_ij gains -(dbeta/2) sum_k [H_ik rho_kj + rho_ik H_kj],
+ * so each pair spawns from both ends: attempt a acts on the bra (even a) or
+ * the ket (odd a), with the excitation generator of the half it acts on and
+ * amplitude (dbeta / 2)|H| / p_gen per walker. IP-DMQMC, eq. (ipdmqmc):
+ * df/dtau = H^0 f - f H with H^0 diagonal, so only the ket end spawns, with
+ * amplitude dtau |H| / p_gen. The random blocks are those of attempt a of the
+ * pair (keyed by the pair's hash). */
+static int spawn_attempt_pair(or_run *r, const uint64_t *key, uint64_t h, int32_t n0, int64_t nat, int64_t a,
+                              int side)
+{
+    const or_sys *s = r->s;
+    int w = det_words(r);
+    uint32_t wv[8], rnd[4];
+    uint32_t t = (uint32_t)r->t;
+    draw(r, TAG_SELECT, (uint32_t)a, t, h, wv);
+    draw(r, TAG_SELECT2, (uint32_t)a, t, h, wv + 4);
+    uint64_t half[OR_MAXW] = {0};
+    double pgen = 0.0, hij = 0.0;
+    if (!or_exgen(s, r->q.excit_gen, r->q.p_single, key + side * w, wv, half, &pgen, &hij)) return OR_OK;
+    if (hij == 0.0) return OR_OK;
+    uint64_t child[OR_MAXW] = {0};
+    memcpy(child, key, sizeof(uint64_t) * r->W);
+    memcpy(child + side * w, half, sizeof(uint64_t) * w);
+    double ah = fabs(hij);
+    double tau = r->q.method == OR_DMQMC ? r->q.tau * 0.5 : r->q.tau;
+    double m;
+    if (r->q.fixed_point_bits == 0) {
+        m = (tau * ah) / pgen;
+    } else {
+        double an = (double)(n0 < 0 ? -(int64_t)n0 : (int64_t)n0);
+        m = (((tau * ah) / pgen) * an) / (double)nat;
+    }
+    double u;
+    if (r->q.excit_gen == OR_EXGEN_HEATBATH) {
+        draw(r, TAG_SPAWN_ROUND, (uint32_t)a, t, h, rnd);
+        u = u53(rnd[0], rnd[1]);
+    } else {
+        u = u53(wv[2], wv[3]);
+    }
+    if (!(m < 0x1p31)) return OR_EOVERFLOW;
+    int64_t kk;
+    if (r->q.fixed_point_bits != 0 && m < (double)r->cu)
+        kk = (u * (double)r->cu < m) ? r->cu : 0;
+    else
+        kk = sround(m, u);
+    if (kk == 0) return OR_OK;
+    if (kk > 2147483647) return OR_EOVERFLOW;
+    int sh = hij > 0.0 ? 1 : -1;
+    int sn = n0 > 0 ? 1 : -1;
+    push_spawn(r, child, (int32_t)(-(sh * sn) * kk), 1);
     return OR_OK;
 }
 
@@ -1001,7 +1099,7 @@ static void insert_zero_entries(or_run *r, const uint64_t *add, int64_t na)
         } else {
             memcpy(nk + (size_t)o * W, add + (size_t)j * W, sizeof(uint64_t) * W);
             np[o] = 0;
-            nkd[o] = or_diag(r->s, add + (size_t)j * W) - r->s->H00;
+            nkd[o] = entry_kdiag(r, add + (size_t)j * W);
             nds[o] = -1;
             ++j;
         }
@@ -1089,6 +1187,23 @@ static int step_once(or_run *r)
         if (r->q.fixed_point_bits == 0 && (n0 >= (1 << 28) || n0 <= -(1 << 28))) return OR_EOVERFLOW;
         uint64_t h = or_hash64(key, W);
         int64_t nat = n_attempts(r, n0);
+        if (r->q.method == OR_DMQMC) {
+            /* nat attempts at each end: attempt 2k acts on the bra, 2k + 1 on the ket */
+            if (2 * nat >= ((int64_t)1 << 28)) return OR_EOVERFLOW;
+            for (int64_t k = 0; k < nat; ++k)
+                for (int side = 0; side < 2; ++side) {
+                    int st = spawn_attempt_pair(r, key, h, n0, nat, 2 * k + side, side);
+                    if (st) return st;
+                }
+            continue;
+        }
+        if (r->q.method == OR_IPDMQMC) {
+            for (int64_t k = 0; k < nat; ++k) {
+                int st = spawn_attempt_pair(r, key, h, n0, nat, k, 1);
+                if (st) return st;
+            }
+            continue;
+        }
         int64_t an = n0 < 0 ? -(int64_t)n0 : n0;
         int pin_d = r->ss_active && r->dslot[i] >= 0;
         uint8_t init = (uint8_t)(an > r->thr || is_reference(r, key) || pin_d);
@@ -1199,7 +1314,7 @@ static int step_once(or_run *r)
                 if (v > 2147483647 || v < -2147483647) status = OR_EOVERFLOW;
                 memcpy(nk + (size_t)o * W, ukeys + (size_t)b * W, sizeof(uint64_t) * W);
                 np[o] = (int32_t)v;
-                nkd[o] = or_diag(s, ukeys + (size_t)b * W) - s->H00;
+                nkd[o] = entry_kdiag(r, ukeys + (size_t)b * W);
                 nds[o] = -1;
                 ++o;
             } else {
@@ -1306,7 +1421,7 @@ int or_run_import(or_run *r, const uint64_t *keys, const int32_t *pops, int64_t 
         if (pops[ix[i]] == 0) continue;
         memcpy(r->keys + (size_t)o * W, keys + (size_t)ix[i] * W, sizeof(uint64_t) * W);
         r->pops[o] = pops[ix[i]];
-        r->kdiag[o] = or_diag(r->s, keys + (size_t)ix[i] * W) - r->s->H00;
+        r->kdiag[o] = entry_kdiag(r, keys + (size_t)ix[i] * W);
         r->dslot[o] = -1;
         ++o;
     }

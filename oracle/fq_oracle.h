@@ -18,6 +18,8 @@
  *   semi-stochastic          Sec. 2.1; tutorial appendix, semi_stoch block
  *   projected energy         tutorial appendix, E_corr estimator
  *   sorted main list, hash   appendix "Parallelization"
+ *   density matrix (DMQMC,
+ *   IP-DMQMC)                Sec. 2.3, eqs. (dmqmc) and (ipdmqmc); Sec. 2.4
  *
  * Parity pins (see the tests): brute-force second-quantised Hamiltonian,
  * exact diagonalisation, exhaustive generator enumeration, the rocRAND
@@ -59,7 +61,13 @@ typedef struct {
     int32_t ss_start_iteration;
     int32_t ss_shared;          /* 1: D chosen jointly with other runs (or_runs_select_shared) */
     int32_t tau_search;         /* 1: lower tau on the fly (see step_once) */
+    int32_t method;             /* OR_FCIQMC, OR_DMQMC or OR_IPDMQMC */
 } or_qmc;
+
+/* Methods (Sec. 2.1 FCIQMC; Sec. 2.3 DMQMC and interaction-picture DMQMC).
+ * The density-matrix methods sample pairs (D_i, D_j): a key of 2W words, the
+ * bra's W words first, then the ket's. */
+enum { OR_FCIQMC = 0, OR_DMQMC = 1, OR_IPDMQMC = 2 };
 
 /* estimators of the last completed iteration */
 typedef struct {

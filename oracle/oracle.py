@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "libfq_oracle.so")
 
 HUBBARD, UEG, MOLECULAR = 1, 2, 3
 EXGEN_HUB, EXGEN_UEG, EXGEN_HEATBATH = 1, 2, 3
+FCIQMC, DMQMC, IPDMQMC = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -38,7 +39,8 @@ class Qmc(C.Structure):
                 ("p_single", C.c_double), ("initiator", C.c_int32),
                 ("initiator_threshold", C.c_double), ("fixed_point_bits", C.c_int32),
                 ("spawn_cutoff", C.c_double), ("ss_size", C.c_int32),
-                ("ss_start_iteration", C.c_int32), ("ss_shared", C.c_int32), ("tau_search", C.c_int32)]
+                ("ss_start_iteration", C.c_int32), ("ss_shared", C.c_int32), ("tau_search", C.c_int32),
+                ("method", C.c_int32)]
 
 
 class Estimators(C.Structure):
@@ -194,7 +196,7 @@ def make_qmc(**kw) -> Qmc:
     d = dict(tau=0.01, seed=7, replica_id=0, init_pop=500.0, target_population=1e4,
              shift_period=10, shift_damping=0.05, initial_shift=0.0, excit_gen=EXGEN_HUB,
              p_single=0.1, initiator=0, initiator_threshold=3.0, fixed_point_bits=0,
-             spawn_cutoff=0.0, ss_size=0, ss_start_iteration=0, ss_shared=0, tau_search=0)
+             spawn_cutoff=0.0, ss_size=0, ss_start_iteration=0, ss_shared=0, tau_search=0, method=0)
     d.update(kw)
     return Qmc(**d)
 
@@ -224,12 +226,17 @@ class Run:
         lib().or_run_estimators(self.ptr, C.byref(e))
         return e.as_dict()
 
+    @property
+    def W(self):
+        """key words: the system's, doubled for the density-matrix methods"""
+        return self.sys.W * (1 if self.qmc.method == FCIQMC else 2)
+
     def export(self):
         n = int(lib().or_run_size(self.ptr))
-        keys = np.zeros(max(n, 1) * self.sys.W, np.uint64)
+        keys = np.zeros(max(n, 1) * self.W, np.uint64)
         pops = np.zeros(max(n, 1), np.int32)
         lib().or_run_export(self.ptr, keys, pops)
-        return keys[: n * self.sys.W].reshape(n, self.sys.W), pops[:n]
+        return keys[: n * self.W].reshape(n, self.W), pops[:n]
 
     def import_walkers(self, keys, pops, shift=0.0, iteration=0, vary=0, n_prev=0):
         keys = np.ascontiguousarray(keys, np.uint64).reshape(-1)
@@ -240,11 +247,11 @@ class Run:
 
     def spawns(self):
         n = int(lib().or_run_n_spawns(self.ptr))
-        keys = np.zeros(max(n, 1) * self.sys.W, np.uint64)
+        keys = np.zeros(max(n, 1) * self.W, np.uint64)
         amps = np.zeros(max(n, 1), np.int32)
         init = np.zeros(max(n, 1), np.uint8)
         lib().or_run_spawns(self.ptr, keys, amps, init)
-        return keys[: n * self.sys.W].reshape(n, self.sys.W), amps[:n], init[:n]
+        return keys[: n * self.W].reshape(n, self.W), amps[:n], init[:n]
 
     def detspace(self):
         n = int(lib().or_run_detspace(self.ptr, None))
