@@ -176,6 +176,28 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc,
                          int64_t spawn_capacity, void *d_workspace, size_t ws_bytes,
                          void *hip_stream);
 
+/* Allocation-free variant of fq_init_system, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The context's workspace is a static device
+ * array of FQ_STATIC_WORKSPACE_BYTES that the library holds on every device it
+ * runs on until the process ends; the call makes no hipMalloc, hipHostMalloc,
+ * hipFree or other allocating HIP or torch call (its host staging buffers are
+ * plain host memory). Arguments and results are those of fq_init_system
+ * without d_workspace / ws_bytes; the array of the current device is used.
+ * Errors: FQ_ECAPACITY (nothing created) when fq_workspace_bytes() of the
+ * arguments exceeds FQ_STATIC_WORKSPACE_BYTES (a few 1e4 determinants: the
+ * 8-site Hubbard ring with 16384 determinants and 65536 spawns needs 7.3 MiB);
+ * FQ_ESTATE when a context made by this call on the same device has not yet
+ * been destroyed (every such context would share the one array, and calls on
+ * two of them would race, so only one may live per device); FQ_EINVAL as for
+ * fq_init_system. The array keeps the contents of the last context; every part
+ * that must start at zero is cleared by this call. fq_destroy gives the array
+ * back. */
+#define FQ_STATIC_WORKSPACE_BYTES (16u << 20)
+fq_status fq_init_system_static(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc,
+                                const fq_semistoch *ss, int32_t n_instances, int64_t main_capacity,
+                                int64_t spawn_capacity, void *hip_stream);
+
 /* Advances every replica by n_iterations projector iterations (spawning,
  * death/cloning, semi-stochastic projection, annihilation with the initiator
  * rule, estimators, and the shift update every shift_period iterations:

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -362,6 +363,8 @@ struct fq_ctx {
     int64_t timed_iterations = 0;
     std::vector<double> iter_ms;  // per-iteration device time of the last timed fq_step
     std::string err;
+    bool pinned = true;   // host staging buffers from hipHostMalloc (else plain host memory)
+    int static_dev = -1;  // device whose static workspace array this context holds (-1: none)
 };
 
 namespace {
@@ -722,9 +725,16 @@ size_t fq_workspace_bytes(const fq_system *sys, const fq_qmc *qmc, const fq_semi
     return make_layout(n_instances, W, main_capacity, spawn_capacity, tables, D, nk).total + 256;
 }
 
-fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss,
-                         int32_t n_instances, int64_t main_capacity, int64_t spawn_capacity, void *d_workspace,
-                         size_t ws_bytes, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// Body of the two set-up entry points. pinned: stage estimators and counters
+// through page-locked host buffers (hipHostMalloc); otherwise through plain
+// host memory, so that the call allocates nothing through HIP.
+fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss,
+                      int32_t n_instances, int64_t main_capacity, int64_t spawn_capacity, void *d_workspace,
+                      size_t ws_bytes, void *hip_stream, bool pinned, int static_dev)
 {
     if (!out || !sys || !qmc || n_instances <= 0 || n_instances > 4096 || main_capacity < n_instances ||
         spawn_capacity < 1 || !d_workspace)
@@ -734,6 +744,7 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         if (qmc[r].tau_search && n_instances > 1) return FQ_EINVAL;  // the search is per context
     *out = nullptr;
     fq_ctx *c = new fq_ctx();
+    c->pinned = pinned;
     c->R = n_instances;
     c->stream = (hipStream_t)hip_stream;
     c->main_cap = main_capacity;
@@ -919,10 +930,16 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
         if (d2h(c->stream, &d, w.sys + r, sizeof(DevSys)) != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
         c->h00v[r] = d.H00;
     }
-    he = hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), 0);
-    if (he == hipSuccess) he = hipHostMalloc((void **)&c->h_hist, sizeof(EstAcc) * c->R * HIST_LEN, 0);
-    if (he == hipSuccess) he = hipHostMalloc((void **)&c->h_shift, 8 * c->R, 0);
-    if (he != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
+    if (pinned) {
+        he = hipHostMalloc((void **)&c->h_ctl, sizeof(Ctl), 0);
+        if (he == hipSuccess) he = hipHostMalloc((void **)&c->h_hist, sizeof(EstAcc) * c->R * HIST_LEN, 0);
+        if (he == hipSuccess) he = hipHostMalloc((void **)&c->h_shift, 8 * c->R, 0);
+        if (he != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
+    } else {
+        c->h_ctl = new Ctl();
+        c->h_hist = new EstAcc[(size_t)c->R * HIST_LEN]();
+        c->h_shift = new double[c->R]();
+    }
 
     // grids: persistent tile kernels sized to the resident capacity
     int dev = 0, ncu = 256;
@@ -998,8 +1015,80 @@ fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, 
     for (int r = 0; r < c->R; ++r) c->h_shift[r] = c->shift[r];
     if (h2d(c->stream, w.shift, c->h_shift, 8 * c->R) != hipSuccess) { fq_destroy(c); return FQ_EHIP; }
     if (upload_main(c, nz) != FQ_OK || host_estimators(c) != FQ_OK) { fq_destroy(c); return FQ_EHIP; }
+    c->static_dev = static_dev;  // from here on fq_destroy gives the static array back
     *out = c;
     return FQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Static device workspace of fq_init_system_static: one array per device
+// (each device that loads the library holds it until the process ends). Host
+// code never passes `scratch` itself to the device (the name is a host-side
+// stand-in); it passes the device address that hipGetSymbolAddress returns for
+// the current device, looked up once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FQ_STATIC_WORKSPACE_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[MAX_DEVICES] = {nullptr};  // device address of scratch, per device
+bool g_static_busy[MAX_DEVICES] = {false};    // a live context holds the device's array
+
+// reserves the current device's array; *dev receives the device index
+fq_status static_workspace_acquire(void **ptr, int *dev)
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= MAX_DEVICES) return FQ_EHIP;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[d]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FQ_EHIP;
+        g_static_ptr[d] = p;
+    }
+    if (g_static_busy[d]) return FQ_ESTATE;
+    g_static_busy[d] = true;
+    *ptr = g_static_ptr[d];
+    *dev = d;
+    return FQ_OK;
+}
+
+void static_workspace_release(int dev)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_busy[dev] = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+fq_status fq_init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss,
+                         int32_t n_instances, int64_t main_capacity, int64_t spawn_capacity, void *d_workspace,
+                         size_t ws_bytes, void *hip_stream)
+{
+    return init_system(out, sys, qmc, ss, n_instances, main_capacity, spawn_capacity, d_workspace, ws_bytes,
+                       hip_stream, true, -1);
+}
+
+fq_status fq_init_system_static(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss,
+                                int32_t n_instances, int64_t main_capacity, int64_t spawn_capacity,
+                                void *hip_stream)
+{
+    if (!out) return FQ_EINVAL;
+    *out = nullptr;
+    const size_t need = fq_workspace_bytes(sys, qmc, ss, n_instances, main_capacity, spawn_capacity);
+    if (need == 0) return FQ_EINVAL;
+    if (need > (size_t)FQ_STATIC_WORKSPACE_BYTES) return FQ_ECAPACITY;
+    void *ptr = nullptr;
+    int dev = -1;
+    const fq_status st = static_workspace_acquire(&ptr, &dev);
+    if (st != FQ_OK) return st;
+    const fq_status r = init_system(out, sys, qmc, ss, n_instances, main_capacity, spawn_capacity, ptr,
+                                    (size_t)FQ_STATIC_WORKSPACE_BYTES, hip_stream, false, dev);
+    // a failed set-up has freed its context, which never held the array
+    if (r != FQ_OK) static_workspace_release(dev);
+    return r;
 }
 
 fq_status fq_step(fq_ctx *c, int32_t n_iterations)
@@ -1530,9 +1619,16 @@ void fq_destroy(fq_ctx *c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
-    if (c->h_hist) (void)hipHostFree(c->h_hist);
-    if (c->h_shift) (void)hipHostFree(c->h_shift);
+    if (c->pinned) {
+        if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+        if (c->h_hist) (void)hipHostFree(c->h_hist);
+        if (c->h_shift) (void)hipHostFree(c->h_shift);
+    } else {
+        delete c->h_ctl;
+        delete[] c->h_hist;
+        delete[] c->h_shift;
+    }
+    if (c->static_dev >= 0) static_workspace_release(c->static_dev);
     delete c;
 }
 

@@ -21,7 +21,7 @@ EXGEN = {HUBBARD: 1, UEG: 2, MOLECULAR: 3}
 SS_FP64, SS_SPLIT_BF16 = 0, 1
 
 # every function the header declares
-C_API = ["fq_workspace_bytes", "fq_init_system", "fq_step", "fq_estimators", "fq_estimator_history",
+C_API = ["fq_workspace_bytes", "fq_init_system", "fq_init_system_static", "fq_step", "fq_estimators", "fq_estimator_history",
          "fq_export_walkers", "fq_import_walkers", "fq_shift_state", "fq_export_spawns", "fq_detspace", "fq_info",
          "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_iteration_times", "fq_set_graph",
          "fq_set_sort_key_bits", "fq_set_launch", "fq_get_launch", "fq_reblock_create", "fq_reblock_add",
@@ -95,6 +95,9 @@ def load_library():
     L.fq_init_system.argtypes = [C.POINTER(P), C.POINTER(System), C.POINTER(Qmc), C.POINTER(SemiStoch),
                                  C.c_int32, C.c_int64, C.c_int64, P, C.c_size_t, P]
     L.fq_init_system.restype = C.c_int32
+    L.fq_init_system_static.argtypes = [C.POINTER(P), C.POINTER(System), C.POINTER(Qmc), C.POINTER(SemiStoch),
+                                        C.c_int32, C.c_int64, C.c_int64, P]
+    L.fq_init_system_static.restype = C.c_int32
     L.fq_step.argtypes = [P, C.c_int32]
     L.fq_step.restype = C.c_int32
     L.fq_estimators.argtypes = [P, C.c_int32, C.POINTER(Estimators)]
@@ -186,7 +189,7 @@ class Context:
     """One FCIQMC context on a HIP device: n_instances replicas of one system shape."""
 
     def __init__(self, systems, qmcs, semistoch=None, main_capacity=1 << 16, spawn_capacity=1 << 16,
-                 device="cuda:0", stream=None, graph=False):
+                 device="cuda:0", stream=None, graph=False, static_workspace=False):
         import torch
 
         L = load_library()
@@ -213,14 +216,23 @@ class Context:
         if stream is None and graph:
             stream = torch.cuda.Stream(self.device)  # default priority; graph capture needs a real stream
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        off = (-base) % 256
         self.ctx = C.c_void_p()
-        st = L.fq_init_system(C.byref(self.ctx), sysarr, qarr, ssarr, self.R, main_capacity, spawn_capacity,
-                              C.c_void_p(base + off), nbytes, C.c_void_p(self.stream.cuda_stream))
-        if st != FQ_OK:
-            raise FqError(st, "fq_init_system failed")
+        if static_workspace:
+            # the library's static device array (fq_init_system_static): no workspace allocated here
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                st = L.fq_init_system_static(C.byref(self.ctx), sysarr, qarr, ssarr, self.R, main_capacity,
+                                             spawn_capacity, C.c_void_p(self.stream.cuda_stream))
+            if st != FQ_OK:
+                raise FqError(st, "fq_init_system_static failed")
+        else:
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            off = (-base) % 256
+            st = L.fq_init_system(C.byref(self.ctx), sysarr, qarr, ssarr, self.R, main_capacity, spawn_capacity,
+                                  C.c_void_p(base + off), nbytes, C.c_void_p(self.stream.cuda_stream))
+            if st != FQ_OK:
+                raise FqError(st, "fq_init_system failed")
         self.lib = L
         W, nso, e0 = C.c_int32(), C.c_int32(), C.c_double()
         L.fq_info(self.ctx, C.byref(W), C.byref(nso), C.byref(e0))
