@@ -110,7 +110,29 @@ typedef struct {
                                    attempt so far, 1 / (max K_ii - S) over the entries of the
                                    last death step), each bound applying when positive.
                                    Export/import keep tau and the running maximum. */
+    int32_t method;             /* FQ_FCIQMC, FQ_DMQMC or FQ_IPDMQMC (the same for every
+                                   instance of a context) */
 } fq_qmc;
+
+/* Methods (Sec. 2.1; Sec. 2.3, eqs. dmqmc and ipdmqmc; Sec. 2.4). The
+ * density-matrix methods sample pairs (D_i, D_j) holding rho_ij: a key of two
+ * words, the bra's determinant (word 0) and the ket's (word 1), so the system
+ * must have at most 64 spin-orbitals. Annihilation is the FCIQMC one on these
+ * keys. DMQMC (symmetrised Bloch equation): each pair makes ceil(|n| 2^-b)
+ * spawning attempts at each end (attempt 2k acts on the bra, 2k + 1 on the
+ * ket) with amplitude (tau / 2)|H| / p_gen per walker, and dies with
+ * (K_ii + K_jj) / 2 - S. IP-DMQMC (H^0 the diagonal part of H, df/dtau =
+ * H^0 f - f H): only the ket end spawns (amplitude tau |H| / p_gen), death
+ * with K_jj - K_ii - S. The initial list is round(init_pop 2^b) units on
+ * (D_0, D_0); a beta loop starts from the caller's sample of the identity (or
+ * of e^{-beta H^0}) given to fq_import_walkers. Estimators: ref_pop_units is
+ * the trace sum_i rho_ii and proj_numerator / num_limbs Tr(rho H) =
+ * sum rho_ij H_ji (H_ii on the diagonal, absolute), so proj_energy is the
+ * thermal energy Tr(rho H) / Tr(rho). Not with the initiator rule, a
+ * deterministic space or tau_search (FQ_EINVAL). */
+#define FQ_FCIQMC 0
+#define FQ_DMQMC 1
+#define FQ_IPDMQMC 2
 
 /* Semi-stochastic block (tutorial appendix, semi_stoch = {size,
  * start_iteration, space = "high"}): the size most highly weighted
@@ -163,7 +185,8 @@ typedef struct fq_ctx fq_ctx;
 
 /* Bytes of device workspace needed for n_instances replicas that share one
  * system shape (same kind and key width), with main_capacity determinants and
- * spawn_capacity spawned walkers summed over the instances. */
+ * spawn_capacity spawned walkers summed over the instances. qmc (may be NULL,
+ * meaning FCIQMC) gives the method, which sets the key width. */
 size_t fq_workspace_bytes(const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss,
                           int32_t n_instances, int64_t main_capacity, int64_t spawn_capacity);
 
@@ -301,6 +324,19 @@ fq_status fq_set_sort_key_bits(fq_ctx *ctx, int32_t bits);
  * the geometry (work is taken by ticket or grid stride); only speed does. */
 fq_status fq_set_launch(fq_ctx *ctx, const int32_t *blocks, int32_t n);
 fq_status fq_get_launch(const fq_ctx *ctx, int32_t *blocks, int32_t n);
+
+/* Tile shapes of the persistent kernels, among variants compiled into the
+ * library: [0] spawning attempts per thread (2, 4 or 8; tiles of 256 threads),
+ * [1] merge positions per thread (1, 2 or 4; tiles of 512 threads), [2]
+ * radix-sort keys per thread (8, 12 or 16; tiles of 256 threads). [0] and [1]
+ * apply to determinant keys of one or two words (longer keys and pair keys
+ * use 2 and 2, resp. 4 and 2); [2] to every context. Defaults 4, 2, 12. A value
+ * <= 0 keeps the current one; any other value outside the list is FQ_EINVAL
+ * (nothing changes). Results do not depend on the shapes (tiles only
+ * partition the work; every prefix crossing tiles is exact); only speed does.
+ * Changing them drops the captured graphs. */
+fq_status fq_set_tiles(fq_ctx *ctx, const int32_t *tiles, int32_t n);
+fq_status fq_get_tiles(const fq_ctx *ctx, int32_t *tiles, int32_t n);
 
 /* On-the-fly blocking analysis (Sec. 3.1: the reblocking of Flyvbjerg and
  * Petersen, accumulated as the data arrive, so that a run can stop once a

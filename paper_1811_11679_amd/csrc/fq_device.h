@@ -247,7 +247,11 @@ struct DevSys {
     double H00;
 };
 
-enum : int { K_HUBBARD = 1, K_UEG = 2, K_MOLECULAR = 3 };
+enum : int { K_HUBBARD = 1, K_UEG = 2, K_MOLECULAR = 3, K_PAIR = 8 };
+// kernels for pairs of determinants (density-matrix methods) take KIND =
+// system kind | K_PAIR: a key is the bra's words, then the ket's
+__host__ __device__ constexpr bool is_pair(int k) { return (k & K_PAIR) != 0; }
+__host__ __device__ constexpr int base_kind(int k) { return k & 7; }
 
 __device__ __forceinline__ double eri_at(const DevSys &s, int p, int q, int r, int t)
 {

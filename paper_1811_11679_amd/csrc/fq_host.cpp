@@ -252,7 +252,11 @@ bool same_system(const fq_system &a, const fq_system &b)
 }
 
 // spans of 256 attempts the attempt partition can hold
-int64_t span_capacity(int64_t mcap, int64_t scap, int W) { return tiles_of(std::max(mcap * 16, scap * 4), span_of(W)); }
+int64_t span_capacity(int64_t mcap, int64_t scap, int W)
+{
+    (void)W;
+    return tiles_of(std::max(mcap * 16, scap * 4), SPAN_MIN);
+}
 
 Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D, int nk)
 {
@@ -275,7 +279,7 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.mpart = take(8 * (size_t)(tiles_of(mcap + scap, 512) + 2));
     L.newdet = take((size_t)mcap + 16);
     L.st_scan = take(8 * (size_t)tiles_of(mcap, 2048));
-    L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, SORT_TILE));
+    L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, SORT_TILE_MIN));
     L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
     L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 512));
     L.st_spawn = take(8 * (size_t)(span_capacity(mcap, scap, W) + 2));
@@ -325,6 +329,8 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
 
 struct fq_ctx {
     int R = 0, W = 0, kind = 0, rb = 0;
+    int method = FQ_FCIQMC;  // FQ_FCIQMC, FQ_DMQMC or FQ_IPDMQMC (one per context)
+    int lkind = 0;           // kernel kind: the system kind, | K_PAIR for the density-matrix methods
     uint64_t hmask = ~0ull;  // hash bits that enter a sort key
     hipStream_t stream = nullptr;
     std::vector<HostSys> sys;
@@ -523,7 +529,7 @@ fq_status upload_main(fq_ctx *c, const std::vector<HostEntry> &e)
         HIPCHK(c, h2d(c->stream, c->w.ctl, &ctl0, sizeof(Ctl)));
     }
     HIPCHK(c, fill0(c->stream, c->ws + c->L.st_scan, c->L.st_sort - c->L.st_scan));
-    HIPCHK(c, enqueue_setup(1, c->kind, c->w, nullptr, 0, m, n, nullptr, nullptr, c->stream));
+    HIPCHK(c, enqueue_setup(1, c->lkind, c->w, nullptr, 0, m, n, nullptr, nullptr, c->stream));
     Ctl ctl;
     HIPCHK(c, d2h(c->stream, &ctl, c->w.ctl, sizeof(Ctl)));
     ctl.n_main = n;
@@ -555,7 +561,11 @@ fq_status host_estimators(fq_ctx *c)
             if ((int)rep != r) continue;
             a.nw += x.pop < 0 ? -(long long)x.pop : x.pop;
             a.nocc += 1;
-            if (key_cmp_host(x.key, c->sys[r].ref, c->W) == 0) a.n0 = x.pop;
+            if (c->method != FQ_FCIQMC) {
+                if (x.key[0] == x.key[1]) a.n0 += x.pop;  // the trace
+            } else if (key_cmp_host(x.key, c->sys[r].ref, c->W) == 0) {
+                a.n0 = x.pop;
+            }
         }
         estimators_from_acc(c, r, a, c->last[r]);
         c->last[r].shift = c->shift[r];
@@ -692,7 +702,7 @@ fq_status select_detspace(fq_ctx *c)
     HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[9], skk.data(), 8 * nd * W));
     HIPCHK(c, h2d(c->stream, c->ws + c->L.dkeys, dk.data(), 8 * nd * W));
     HIPCHK(c, fill0(c->stream, c->ws + c->L.ds[6], 8 * nd));
-    HIPCHK(c, enqueue_setup(2, c->kind, c->w, nullptr, 0, m, 0, (const uint64_t *)(c->ws + c->L.dkeys),
+    HIPCHK(c, enqueue_setup(2, c->lkind, c->w, nullptr, 0, m, 0, (const uint64_t *)(c->ws + c->L.dkeys),
                             (double *)(c->ws + c->L.ds[0]), c->stream));
     Ctl ctl;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -710,7 +720,6 @@ extern "C" {
 size_t fq_workspace_bytes(const fq_system *sys, const fq_qmc *qmc, const fq_semistoch *ss, int32_t n_instances,
                           int64_t main_capacity, int64_t spawn_capacity)
 {
-    (void)qmc;
     if (!sys || n_instances <= 0 || main_capacity <= 0 || spawn_capacity <= 0) return 0;
     int64_t tables = 0;
     int W = 1;
@@ -718,7 +727,9 @@ size_t fq_workspace_bytes(const fq_system *sys, const fq_qmc *qmc, const fq_semi
         HostSys s;
         if (!build_system(sys[r], s).empty()) return 0;
         tables += (int64_t)table_bytes(s);
-        W = std::max(W, round_w(s.n_so));
+        // the density-matrix methods key pairs of determinants
+        const int pair = qmc && qmc[r].method != FQ_FCIQMC ? 2 : 1;
+        W = std::max(W, pair * round_w(s.n_so));
     }
     const int D = ss ? std::max(0, ss[0].size) : 0;
     const int nk = ss && ss[0].shared ? 1 : n_instances;
@@ -755,9 +766,15 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     for (int r = 0; r < c->R; ++r) {
         const std::string m = build_system(sys[r], c->sys[r]);
         if (!m.empty()) { delete c; return FQ_EINVAL; }
-        const int W = round_w(c->sys[r].n_so);
-        if (r == 0) { c->W = W; c->kind = sys[r].kind; }
-        if (W != c->W || sys[r].kind != c->kind) { delete c; return FQ_EINVAL; }
+        // density-matrix methods: a key holds a pair of one-word determinants
+        const int Wd = round_w(c->sys[r].n_so);
+        const int W = qmc[r].method == FQ_FCIQMC ? Wd : 2 * Wd;
+        if (r == 0) { c->W = W; c->kind = sys[r].kind; c->method = qmc[0].method; }
+        if (W != c->W || sys[r].kind != c->kind || qmc[r].method != c->method) { delete c; return FQ_EINVAL; }
+        if (qmc[r].method < FQ_FCIQMC || qmc[r].method > FQ_IPDMQMC) { delete c; return FQ_EINVAL; }
+        if (qmc[r].method != FQ_FCIQMC &&
+            (Wd != 1 || qmc[r].initiator || qmc[r].tau_search || (ss && ss[0].size > 0)))
+            { delete c; return FQ_EINVAL; }
         const fq_qmc &q = qmc[r];
         const int need = c->kind == FQ_HUBBARD_REAL ? FQ_EXGEN_HUB_UNIFORM
                          : c->kind == FQ_UEG        ? FQ_EXGEN_UEG_UNIFORM
@@ -774,7 +791,8 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
         }
         tables += (int64_t)table_bytes(c->sys[r]);
     }
-    if (c->kind == FQ_HUBBARD_REAL && c->W != 1) { delete c; return FQ_EINVAL; }
+    if (c->kind == FQ_HUBBARD_REAL && c->W != (c->method == FQ_FCIQMC ? 1 : 2)) { delete c; return FQ_EINVAL; }
+    c->lkind = c->kind | (c->method == FQ_FCIQMC ? 0 : (int)K_PAIR);
     for (int r = 1; r < c->R; ++r)
         if (qmc[r].shift_period != qmc[0].shift_period) { delete c; return FQ_EINVAL; }
     c->rb = 0;
@@ -852,6 +870,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     w.rb = c->rb;
     w.hmask = c->hmask;
     w.tau_search = c->qmc[0].tau_search;
+    w.dm = c->method;
     w.W = c->W;
     w.hist_len = HIST_LEN;
     c->cur = 0;
@@ -921,7 +940,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     if (he == hipSuccess) he = h2d(c->stream, (void *)w.rep, rp.data(), sizeof(RepParams) * c->R);
     if (he == hipSuccess) he = fill0(c->stream, w.ctl, sizeof(Ctl));
     if (he == hipSuccess) he = fill0(c->stream, c->ws + c->L.st_scan, c->L.main[0][0] - c->L.st_scan);
-    if (he == hipSuccess) he = enqueue_setup(0, c->kind, w, (DevSys *)w.sys, c->R, c->buf[0], 0, nullptr, nullptr, c->stream);
+    if (he == hipSuccess) he = enqueue_setup(0, c->lkind, w, (DevSys *)w.sys, c->R, c->buf[0], 0, nullptr, nullptr, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) { delete c; return FQ_EHIP; }
     c->h00v.resize(c->R);
@@ -958,6 +977,8 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     // tables staged in LDS serve every replica when all replicas share one system
     bool one_system = true;
     for (int r = 1; r < c->R; ++r) one_system = one_system && same_system(sys[0], sys[r]);
+    // the LDS-staged table paths of the spawn and diagonal kernels serve determinant keys only
+    if (c->method != FQ_FCIQMC) one_system = false;
     if (one_system && (c->kind == FQ_UEG || c->kind == FQ_MOLECULAR)) {
         const size_t m = (size_t)c->sys[0].n_spatial;
         size_t bytes = c->kind == FQ_UEG ? 8 * (m + m * m) : 8 * (m + 2 * m * m);
@@ -1000,6 +1021,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
         HostEntry &e = init[r];
         std::memset(&e, 0, sizeof(e));
         std::memcpy(e.key, c->sys[r].ref, sizeof(e.key));
+        if (c->method != FQ_FCIQMC) e.key[1] = c->sys[r].ref[0];  // the pair (D_0, D_0)
         e.skey = host_skey(host_hash(e.key, c->W) & c->hmask, (uint32_t)r, c->rb);
         const double scale = std::ldexp(1.0, qmc[r].fixed_point_bits);
         const double u = std::floor(qmc[r].init_pop * scale + 0.5);
@@ -1137,7 +1159,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                 c->graphs[b] = nullptr;
                 HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
                 for (int k = 0; k < nb; ++k) {
-                    hipError_t he = enqueue_iteration(c->w, c->kind, c->grids, c->stream, nullptr);
+                    hipError_t he = enqueue_iteration(c->w, c->lkind, c->grids, c->stream, nullptr);
                     if (he != hipSuccess) {
                         hipGraph_t junk;
                         (void)hipStreamEndCapture(c->stream, &junk);
@@ -1158,7 +1180,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             set_main_views(c);
         } else {
             for (int k = 0; k < nb; ++k) {
-                hipError_t he = enqueue_iteration(c->w, c->kind, c->grids, c->stream, c->timing ? &evs[(size_t)k * NE] : nullptr);
+                hipError_t he = enqueue_iteration(c->w, c->lkind, c->grids, c->stream, c->timing ? &evs[(size_t)k * NE] : nullptr);
                 if (he != hipSuccess) return fail(c, FQ_EHIP, std::string("launch: ") + hipGetErrorString(he));
                 c->cur ^= 1;
                 set_main_views(c);
@@ -1592,6 +1614,28 @@ fq_status fq_set_launch(fq_ctx *c, const int32_t *blocks, int32_t n)
     for (int i = 0; i < n && i < 5; ++i)
         if (blocks[i] > 0) *dst[i] = blocks[i];
     drop_graphs(c);
+    return FQ_OK;
+}
+
+fq_status fq_set_tiles(fq_ctx *c, const int32_t *tiles, int32_t n)
+{
+    if (!c || !tiles || n < 0) return FQ_EINVAL;
+    int *dst[3] = {&c->grids.spawn_i, &c->grids.merge_i, &c->grids.sort_i};
+    const int ok[3][3] = {{2, 4, 8}, {1, 2, 4}, {8, 12, 16}};
+    for (int i = 0; i < n && i < 3; ++i)
+        if (tiles[i] > 0 && tiles[i] != ok[i][0] && tiles[i] != ok[i][1] && tiles[i] != ok[i][2])
+            return fail(c, FQ_EINVAL, "tile shape not among the compiled variants");
+    for (int i = 0; i < n && i < 3; ++i)
+        if (tiles[i] > 0) *dst[i] = tiles[i];
+    drop_graphs(c);
+    return FQ_OK;
+}
+
+fq_status fq_get_tiles(const fq_ctx *c, int32_t *tiles, int32_t n)
+{
+    if (!c || !tiles || n < 0) return FQ_EINVAL;
+    const int src[3] = {c->grids.spawn_i, c->grids.merge_i, c->grids.sort_i};
+    for (int i = 0; i < n && i < 3; ++i) tiles[i] = src[i];
     return FQ_OK;
 }
 

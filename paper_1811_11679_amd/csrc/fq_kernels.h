@@ -73,17 +73,16 @@ constexpr int EST_FIELDS = 14;
 // to global memory directly), and the largest grid of the kernels that write
 // partials
 constexpr int ACC_LDS_R = 64;
-// keys per radix-sort tile (the host sizes the per-tile digit status words by it)
-constexpr int SORT_TILE = 3072;
+// keys per radix-sort tile: 256 threads x sort_items, sort_items in {8, 12, 16}
+// chosen per context (the host sizes the per-tile digit status words for the
+// smallest tile)
+constexpr int SORT_TILE_MIN = 2048;
 
-// spawn tiles: SP_T threads, sp_items(W) attempts per thread (fewer for long
-// keys, whose children take more registers), span_of(W) attempts per tile
-#ifndef FQ_SPAWN_ITEMS
-#define FQ_SPAWN_ITEMS 4
-#endif
+// spawn tiles: SP_T threads of SI attempts each (2, 4 or 8 for keys of up to
+// two words, chosen per context; 2 for longer keys, whose children take more
+// registers); the attempt partition is sized for the smallest tile
 constexpr int SP_T = 256;
-__host__ __device__ constexpr int sp_items(int W) { return W <= 2 ? FQ_SPAWN_ITEMS : 2; }
-__host__ __device__ constexpr int span_of(int W) { return SP_T * sp_items(W); }
+constexpr int SPAN_MIN = 2 * SP_T;
 constexpr int PART_MAX_BLOCKS = 8192;
 // largest diagonal-table staging of the new-determinant kernel (bytes of LDS)
 constexpr int ND_LDS_MAX = 65536;
@@ -183,6 +182,9 @@ struct Work {
     int32_t tau_search;  // track the maxima of the time-step search (one instance)
     int32_t lds_tables;  // bytes of UEG tables the spawn kernel stages in LDS (0: read from global)
     int32_t lds_diag;    // bytes of diagonal tables the new-determinant kernel stages in LDS
+    // method: 0 FCIQMC; density matrices on pair keys (Sec. 2.3): 1 DMQMC
+    // (both ends spawn, 2 attempts per walker unit), 2 IP-DMQMC (the ket end)
+    int32_t dm;
 };
 
 // launch geometry of the persistent kernels
@@ -190,6 +192,11 @@ struct Grids {
     int scan, part, spawn, hist, sort, reduce, fixup, merge, det;
     int spawn_lds;  // dynamic LDS bytes of the spawn kernel
     int newdiag;    // blocks of the new-determinant diagonal kernel
+    // tile shapes (compile-time variants chosen at run time; results do not
+    // depend on them): spawning attempts per thread (2, 4, 8; keys of up to two
+    // words), merge positions per thread (1, 2, 4; keys of up to two words),
+    // radix-sort keys per thread (8, 12, 16)
+    int spawn_i = 4, merge_i = 2, sort_i = 12;
 };
 
 // kernels of one iteration, in launch order (per-kernel timing slots)

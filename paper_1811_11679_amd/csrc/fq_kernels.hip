@@ -376,12 +376,12 @@ __global__ void k_spawn_partition(Work w, int span_len)
 // SP_STAGE spawn records (written out coalesced); records beyond that, rare at
 // the spawn rates of the method, go to global memory directly.
 constexpr int SP_STAGE = 256;
-template <int KIND, int W, bool MULTI, bool LT>
+template <int KIND, int W, bool MULTI, bool LT, int SP_I>
 __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 {
     Ctl *c = w.ctl;
     if (c->err) return;
-    constexpr int SP_I = sp_items(W), SPAN = span_of(W);
+    constexpr int SPAN = SP_T * SP_I;
     constexpr int LCAP = SPAN + 2;
     __shared__ long long s_off[LCAP];
     __shared__ uint32_t s_cnt[SP_I][SP_T / 64];
@@ -534,17 +534,39 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 const uint64_t h = (!MULTI && W > 2) ? psk : hash64<W>(key);
                 const long long an = n0 < 0 ? -(long long)n0 : (long long)n0;
                 const bool pin_d = ss && dsl >= 0;
-                init[it] = (uint8_t)(an > rp.thr || key_eq<W>(key, *(const uint64_t(*)[W])sy.ref) || pin_d);
+                // the determinant the generator acts on: the entry itself, or for
+                // a pair (Sec. 2.3) the bra (even attempts of DMQMC) or the ket
+                // (odd attempts of DMQMC; every attempt of IP-DMQMC)
+                constexpr int BK = base_kind(KIND), WG = is_pair(KIND) ? W / 2 : W;
+                int side = 0;
+                long long nat_s = nat;  // attempts per end
+                if constexpr (is_pair(KIND)) {
+                    side = w.dm == 1 ? (int)(k & 1) : 1;
+                    if (w.dm == 1) nat_s = nat >> 1;
+                    init[it] = 1;  // no initiator rule on pairs
+                } else {
+                    init[it] = (uint8_t)(an > rp.thr || key_eq<W>(key, *(const uint64_t(*)[W])sy.ref) || pin_d);
+                }
+                uint64_t gdet[WG], gchild[WG];
+#pragma unroll
+                for (int q = 0; q < WG; ++q) {
+                    gdet[q] = key[side * WG + q];
+                    gchild[q] = 0;
+                }
                 const U4 r0 = draw(TAG_SELECT, (uint32_t)k, t, h, rp.k0, rp.k1);
                 double pgen = 0.0, hv = 0.0;
                 bool ok;
-                if constexpr (KIND == K_HUBBARD)
-                    ok = gen_hubbard<W>(sy, key, r0.x, child[it], pgen, hv);
-                else if constexpr (KIND == K_UEG)
-                    ok = gen_ueg<W>(LT ? lu : sy.u, key, r0.x, r0.y, child[it], pgen, hv);
+                if constexpr (BK == K_HUBBARD)
+                    ok = gen_hubbard<WG>(sy, gdet, r0.x, gchild, pgen, hv);
+                else if constexpr (BK == K_UEG)
+                    ok = gen_ueg<WG>(LT ? lu : sy.u, gdet, r0.x, r0.y, gchild, pgen, hv);
                 else
-                    ok = gen_heatbath<W>(sy, rp.p_single, key, r0, (uint32_t)k, t, h, rp.k0, rp.k1, child[it], pgen, hv,
-                                         hb_tri);
+                    ok = gen_heatbath<WG>(sy, rp.p_single, gdet, r0, (uint32_t)k, t, h, rp.k0, rp.k1, gchild, pgen, hv,
+                                          hb_tri);
+#pragma unroll
+                for (int q = 0; q < W; ++q) child[it][q] = key[q];
+#pragma unroll
+                for (int q = 0; q < WG; ++q) child[it][side * WG + q] = gchild[q];
                 if (ok && hv != 0.0) {
                     bool skip = false;
                     if (pin_d) {
@@ -574,16 +596,18 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                     if (!skip) {
                         const double ah = fabs(hv);
                         if (ts) rs_max = fmax(rs_max, ah / pgen);
+                        // DMQMC: the symmetrised Bloch equation's dbeta / 2 at each end
+                        const double tau_s = (is_pair(KIND) && w.dm == 1) ? rp.tau * 0.5 : rp.tau;
                         double m;
                         if (rp.bits == 0)
-                            m = (rp.tau * ah) / pgen;
+                            m = (tau_s * ah) / pgen;
                         else
-                            m = (((rp.tau * ah) / pgen) * (double)an) / (double)nat;
+                            m = (((tau_s * ah) / pgen) * (double)an) / (double)nat_s;
                         // the Hubbard and electron-gas generators leave the last two
                         // words of the selection block unused: they give the
                         // rounding uniform; heat-bath uses a block of its own
                         double u;
-                        if constexpr (KIND == K_MOLECULAR) {
+                        if constexpr (BK == K_MOLECULAR) {
                             const U4 rr = draw(TAG_SPAWN_ROUND, (uint32_t)k, t, h, rp.k0, rp.k1);
                             u = u53(rr.x, rr.y);
                         } else {
@@ -690,9 +714,10 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 // ---------------------------------------------------------------------------
 // onesweep LSD radix sort of (sort key, index) pairs, 8 passes of 8 bits
 // ---------------------------------------------------------------------------
-// 3072-key tiles (12 per thread): three blocks fit a compute unit's LDS
-constexpr int OS_T = 256, OS_I = SORT_TILE / OS_T, OS_TILE = SORT_TILE, OS_WAVES = OS_T / 64;
-static_assert(OS_I * OS_T == SORT_TILE, "sort tiles are whole rows of 256 threads");
+// Tiles of 256 threads x OS_I keys: 2048 (8 per thread), 3072 (12: three
+// blocks fit a compute unit's LDS) or 4096 (16), chosen per context
+constexpr int OS_T = 256, OS_WAVES = OS_T / 64;
+static_assert(SORT_TILE_MIN == 8 * OS_T, "the status words are sized for the smallest sort tile");
 
 __global__ __launch_bounds__(256) void k_sort_hist(Work w)
 {
@@ -714,9 +739,11 @@ __global__ __launch_bounds__(256) void k_sort_hist(Work w)
     }
 }
 
+template <int OS_I>
 __global__ __launch_bounds__(OS_T) void k_sort_pass(Work w, int pass, const uint64_t *kin, const uint32_t *iin,
                                                     uint64_t *kout, uint32_t *iout)
 {
+    constexpr int OS_TILE = OS_T * OS_I;
     Ctl *c = w.ctl;
     if (c->err) return;
     __shared__ uint64_t lk[OS_TILE];
@@ -1101,15 +1128,16 @@ __global__ void k_fixup(Work w)
 // with 256 threads of four; two such blocks fit a compute unit's registers
 // and LDS. Longer keys: 256 threads of two positions (their LDS slice is
 // larger, and three such blocks per compute unit measured faster).
-#ifndef FQ_MERGE_ITEMS
-#define FQ_MERGE_ITEMS 2  // merge positions per thread and tile, keys of up to two words
-#endif
-template <int W>
+// MI: merge positions per thread and tile, 1, 2 or 4 for keys of up to two
+// words (chosen per context), 2 for longer keys
+template <int W, int MI>
 struct MergeCfg {
     static constexpr int T = W <= 2 ? 512 : 256;
-    static constexpr int I = W <= 2 ? FQ_MERGE_ITEMS : 2;
+    static constexpr int I = MI;
     static constexpr int TILE = T * I;
 };
+static_assert(MergeCfg<1, 1>::TILE == 512 && MergeCfg<8, 2>::TILE == 512,
+              "the merge partition and status arrays are sized for 512-position tiles");
 
 template <int W>
 __device__ __forceinline__ void load_key(const uint64_t *base, long long cap, long long i, uint64_t (&k)[W])
@@ -1139,12 +1167,12 @@ __device__ __forceinline__ bool le_ab(const Work &w, long long i, uint64_t si, l
     return key_cmp<W>(a, b) <= 0;
 }
 
-template <int W>
+template <int W, int MI>
 __global__ void k_merge_partition(Work w)
 {
     const Ctl *c = w.ctl;
     if (c->err) return;
-    constexpr int TILE = MergeCfg<W>::TILE;
+    constexpr int TILE = MergeCfg<W, MI>::TILE;
     const long long na = c->n_main, nb = c->n_uniq;
     const long long ntiles = (na + nb + TILE - 1) / TILE;
     for (long long tile = (long long)blockIdx.x * blockDim.x + threadIdx.x; tile <= ntiles;
@@ -1251,24 +1279,23 @@ __device__ double limbs_to_double(long long a0, long long a1, long long a2, long
     return neg ? -r : r;
 }
 
-// spawning attempts of a determinant holding p units: |p| for integer walkers,
-// ceil(|p| 2^-b) for fixed point
-__device__ __forceinline__ long long attempts_of(long long p, int bits, Ctl *c)
+// spawning attempts of an entry holding p units: |p| for integer walkers,
+// ceil(|p| 2^-b) for fixed point, times mult (2 for DMQMC pairs: that many
+// at each end); 2^28 or more does not fit the counter's attempt field
+__device__ __forceinline__ long long attempts_of(long long p, int bits, int mult, Ctl *c)
 {
     const long long ap = p < 0 ? -p : p;
-    if (bits == 0) {
-        if (ap >= (1ll << 28)) atomicOr(&c->err, ERR_ATTEMPTS);
-        return ap;
-    }
-    return (ap + (1ll << bits) - 1) >> bits;
+    const long long n = mult * (bits == 0 ? ap : (ap + (1ll << bits) - 1) >> bits);
+    if (n >= (1ll << 28)) atomicOr(&c->err, ERR_ATTEMPTS);
+    return n;
 }
 
-template <int KIND, int W, bool MULTI>
-__global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
+template <int KIND, int W, bool MULTI, int MI>
+__global__ __launch_bounds__((MergeCfg<W, MI>::T)) void k_merge(Work w)
 {
     Ctl *c = w.ctl;
     if (c->err) return;
-    constexpr int MG_T = MergeCfg<W>::T, MI = MergeCfg<W>::I, TILE = MergeCfg<W>::TILE;
+    constexpr int MG_T = MergeCfg<W, MI>::T, TILE = MergeCfg<W, MI>::TILE;
     __shared__ uint64_t s_sk[TILE];
     __shared__ uint64_t s_key[W][TILE];
     __shared__ long long s_val[TILE];   // main: population, then the new one; spawned: sum
@@ -1468,7 +1495,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
             ++cnt;
             const int slot = s_src[m];
             const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
-            asum += attempts_of(s_val[slot], w.rep[rep].bits, c);
+            asum += attempts_of(s_val[slot], w.rep[rep].bits, w.dm == 1 ? 2 : 1, c);
         }
         long long tot, atot, ex, aex;
         block_excl_scan2((long long)cnt, asum, ex, aex, tot, atot, s_red);
@@ -1493,7 +1520,7 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
                 const int slot = s_src[m];
                 const int rep = MULTI ? (int)skey_rep(s_sk[slot], w.rb) : 0;
                 w.att_off[s_base + s_dst[m]] = ar;
-                ar += attempts_of(s_val[slot], w.rep[rep].bits, c);
+                ar += attempts_of(s_val[slot], w.rep[rep].bits, w.dm == 1 ? 2 : 1, c);
             }
         }
         const long long obase = s_base;
@@ -1527,15 +1554,35 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
                 any = true;
                 acc.v[F_NW] += ap;
                 acc.v[F_NOCC] += 1;
-                const uint64_t(&ref)[W] = *(const uint64_t(*)[W])sy.ref;
-                int nd = 0;
+                if constexpr (is_pair(KIND)) {
+                    // density matrix (Sec. 2.3): the trace sum_i rho_ii and
+                    // Tr(rho H) = sum rho_ij H_ji over pairs at most doubly excited
+                    constexpr int BK = base_kind(KIND), WH = W / 2;
+                    uint64_t a[WH], b[WH];
+                    int nd = 0;
 #pragma unroll
-                for (int x = 0; x < W; ++x) nd += __popcll(key[x] ^ ref[x]);
-                if (nd == 0) {
-                    acc.v[F_N0] += p;
-                } else if (nd == 2 || nd == 4) {
-                    const double hv = hij<KIND, W>(sy, ref, key);
-                    add_limbs(acc.v, hv * (double)p);
+                    for (int x = 0; x < WH; ++x) {
+                        a[x] = key[x];
+                        b[x] = key[WH + x];
+                        nd += __popcll(a[x] ^ b[x]);
+                    }
+                    if (nd == 0) {
+                        acc.v[F_N0] += p;
+                        add_limbs(acc.v, diag_element<BK, WH>(sy, a) * (double)p);
+                    } else if (nd == 2 || nd == 4) {
+                        add_limbs(acc.v, hij<BK, WH>(sy, b, a) * (double)p);
+                    }
+                } else {
+                    const uint64_t(&ref)[W] = *(const uint64_t(*)[W])sy.ref;
+                    int nd = 0;
+#pragma unroll
+                    for (int x = 0; x < W; ++x) nd += __popcll(key[x] ^ ref[x]);
+                    if (nd == 0) {
+                        acc.v[F_N0] += p;
+                    } else if (nd == 2 || nd == 4) {
+                        const double hv = hij<KIND, W>(sy, ref, key);
+                        add_limbs(acc.v, hv * (double)p);
+                    }
                 }
             }
         }
@@ -1555,6 +1602,29 @@ __global__ __launch_bounds__(MergeCfg<W>::T) void k_merge(Work w)
         c->n_main_new = 0;
         w.att_off[0] = 0;
         c->n_att_new = 0;
+    }
+}
+
+// The diagonal element death uses, relative to H_00: K_ii for a determinant;
+// for a pair (i, j) of the density-matrix methods (Sec. 2.3) (K_ii + K_jj) / 2
+// (DMQMC, the symmetrised Bloch equation) or K_jj - K_ii (IP-DMQMC, with H^0
+// the diagonal part of H).
+template <int KIND, int W>
+__device__ double entry_kdiag(const Work &w, const DevSys &sy, const uint64_t (&key)[W])
+{
+    if constexpr (is_pair(KIND)) {
+        constexpr int BK = base_kind(KIND), WH = W / 2;
+        uint64_t a[WH], b[WH];
+#pragma unroll
+        for (int x = 0; x < WH; ++x) {
+            a[x] = key[x];
+            b[x] = key[WH + x];
+        }
+        const double ki = diag_element<BK, WH>(sy, a) - sy.H00;
+        const double kj = diag_element<BK, WH>(sy, b) - sy.H00;
+        return w.dm == 1 ? (ki + kj) * 0.5 : kj - ki;
+    } else {
+        return diag_element<KIND, W>(sy, key) - sy.H00;
     }
 }
 
@@ -1658,7 +1728,7 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
             } else {
                 const int rep = w.rb ? (int)skey_rep(w.nxt.skey[i], w.rb) : 0;
                 const DevSys &sy = w.sys[w.rep[rep].sys];
-                w.nxt.kdiag[i] = diag_element<KIND, W>(sy, key) - sy.H00;
+                w.nxt.kdiag[i] = entry_kdiag<KIND, W>(w, sy, key);
             }
         }
         __syncthreads();
@@ -1845,39 +1915,68 @@ __global__ void k_split_planes(Work w)
 }
 
 // explicit instantiations
+#define FQ_INSTM(KIND, W, MI)                                    \
+    template __global__ void k_merge<KIND, W, false, MI>(Work);   \
+    template __global__ void k_merge<KIND, W, true, MI>(Work);
+#define FQ_INSTS(KIND, W, SI)                                            \
+    template __global__ void k_spawn<KIND, W, false, false, SI>(Work);    \
+    template __global__ void k_spawn<KIND, W, true, false, SI>(Work);
+#define FQ_INSTT(KIND, W, SI)                                            \
+    template __global__ void k_spawn<KIND, W, false, true, SI>(Work);     \
+    template __global__ void k_spawn<KIND, W, true, true, SI>(Work);
 #define FQ_INST(KIND, W)                                          \
     template __global__ void k_new_diag<KIND, W>(Work);            \
-    template __global__ void k_spawn<KIND, W, false, false>(Work); \
-    template __global__ void k_spawn<KIND, W, true, false>(Work);  \
-    template __global__ void k_merge<KIND, W, false>(Work);        \
-    template __global__ void k_merge<KIND, W, true>(Work);
-FQ_INST(K_HUBBARD, 1)
-FQ_INST(K_UEG, 1)
-FQ_INST(K_UEG, 2)
+    FQ_INSTM(KIND, W, 2)
+// keys of up to two words: the 1- and 4-position merge tiles as well
+#define FQ_INST_SHORT(KIND, W) \
+    FQ_INST(KIND, W)           \
+    FQ_INSTM(KIND, W, 1)       \
+    FQ_INSTM(KIND, W, 4)
+// spawn kernels of one kind and key width over the attempts-per-thread variants
+#define FQ_SPAWN3(KIND, W) FQ_INSTS(KIND, W, 2) FQ_INSTS(KIND, W, 4) FQ_INSTS(KIND, W, 8)
+#define FQ_SPAWN3T(KIND, W) FQ_INSTT(KIND, W, 2) FQ_INSTT(KIND, W, 4) FQ_INSTT(KIND, W, 8)
+FQ_INST_SHORT(K_HUBBARD, 1)
+FQ_INST_SHORT(K_UEG, 1)
+FQ_INST_SHORT(K_UEG, 2)
 FQ_INST(K_UEG, 4)
 FQ_INST(K_UEG, 8)
-template __global__ void k_spawn<K_UEG, 1, false, true>(Work);
-template __global__ void k_spawn<K_UEG, 2, false, true>(Work);
-template __global__ void k_spawn<K_UEG, 4, false, true>(Work);
-template __global__ void k_spawn<K_UEG, 8, false, true>(Work);
-template __global__ void k_spawn<K_MOLECULAR, 1, false, true>(Work);
-template __global__ void k_spawn<K_MOLECULAR, 2, false, true>(Work);
-template __global__ void k_spawn<K_UEG, 1, true, true>(Work);
-template __global__ void k_spawn<K_UEG, 2, true, true>(Work);
-template __global__ void k_spawn<K_UEG, 4, true, true>(Work);
-template __global__ void k_spawn<K_UEG, 8, true, true>(Work);
-template __global__ void k_spawn<K_MOLECULAR, 1, true, true>(Work);
-template __global__ void k_spawn<K_MOLECULAR, 2, true, true>(Work);
-FQ_INST(K_MOLECULAR, 1)
-FQ_INST(K_MOLECULAR, 2)
+FQ_INST_SHORT(K_MOLECULAR, 1)
+FQ_INST_SHORT(K_MOLECULAR, 2)
+// pairs of one-word determinants (density-matrix methods)
+FQ_INST_SHORT(K_HUBBARD | K_PAIR, 2)
+FQ_INST_SHORT(K_UEG | K_PAIR, 2)
+FQ_INST_SHORT(K_MOLECULAR | K_PAIR, 2)
+FQ_SPAWN3(K_HUBBARD, 1)
+FQ_SPAWN3(K_UEG, 1)
+FQ_SPAWN3(K_UEG, 2)
+FQ_SPAWN3(K_MOLECULAR, 1)
+FQ_SPAWN3(K_MOLECULAR, 2)
+FQ_SPAWN3T(K_UEG, 1)
+FQ_SPAWN3T(K_UEG, 2)
+FQ_SPAWN3T(K_MOLECULAR, 1)
+FQ_SPAWN3T(K_MOLECULAR, 2)
+FQ_INSTS(K_UEG, 4, 2)
+FQ_INSTS(K_UEG, 8, 2)
+FQ_INSTT(K_UEG, 4, 2)
+FQ_INSTT(K_UEG, 8, 2)
+FQ_INSTS(K_HUBBARD | K_PAIR, 2, 4)
+FQ_INSTS(K_UEG | K_PAIR, 2, 4)
+FQ_INSTS(K_MOLECULAR | K_PAIR, 2, 4)
 #define FQ_INSTW(W)                                        \
     template __global__ void k_reduce<W>(Work, int);       \
     template __global__ void k_fixup<W>(Work);             \
-    template __global__ void k_merge_partition<W>(Work);
+    template __global__ void k_merge_partition<W, 2>(Work);
 FQ_INSTW(1)
 FQ_INSTW(2)
 FQ_INSTW(4)
 FQ_INSTW(8)
+template __global__ void k_merge_partition<1, 1>(Work);
+template __global__ void k_merge_partition<1, 4>(Work);
+template __global__ void k_merge_partition<2, 1>(Work);
+template __global__ void k_merge_partition<2, 4>(Work);
+template __global__ void k_sort_pass<8>(Work, int, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *);
+template __global__ void k_sort_pass<12>(Work, int, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *);
+template __global__ void k_sort_pass<16>(Work, int, const uint64_t *, const uint32_t *, uint64_t *, uint32_t *);
 
 }  // namespace fq
 
@@ -1908,10 +2007,10 @@ __global__ void k_kdiag(Work w, MainList L, long long n)
         const int rep = (int)skey_rep(L.skey[i], w.rb);
         const RepParams rp = w.rep[rep];
         const DevSys &sy = w.sys[rp.sys];
-        L.kdiag[i] = diag_element<KIND, W>(sy, key) - sy.H00;
+        L.kdiag[i] = entry_kdiag<KIND, W>(w, sy, key);
         const int32_t p = L.pop[i];
         const long long ap = p < 0 ? -(long long)p : (long long)p;
-        L.natt[i] = (int32_t)(rp.bits == 0 ? ap : ((ap + (1ll << rp.bits) - 1) >> rp.bits));
+        L.natt[i] = (int32_t)((w.dm == 1 ? 2 : 1) * (rp.bits == 0 ? ap : ((ap + (1ll << rp.bits) - 1) >> rp.bits)));
     }
 }
 
@@ -1952,10 +2051,43 @@ FQ_INST2(K_UEG, 4)
 FQ_INST2(K_UEG, 8)
 FQ_INST2(K_MOLECULAR, 1)
 FQ_INST2(K_MOLECULAR, 2)
+template __global__ void k_kdiag<K_HUBBARD | K_PAIR, 2>(Work, MainList, long long);
+template __global__ void k_kdiag<K_UEG | K_PAIR, 2>(Work, MainList, long long);
+template __global__ void k_kdiag<K_MOLECULAR | K_PAIR, 2>(Work, MainList, long long);
 
 // ---------------------------------------------------------------------------
 // launchers used by the host library
 // ---------------------------------------------------------------------------
+// spawning, SI attempts per thread: LDS-staged generator tables when the
+// host staged them, the multi-replica kernel for several instances
+template <int KIND, int W, int SI>
+static void launch_spawn(const Work &w, const Grids &g, hipStream_t s)
+{
+    constexpr bool TAB = KIND == K_UEG || KIND == K_MOLECULAR;
+    if (w.R > 1 && TAB && w.lds_tables > 0)
+        k_spawn<KIND, W, true, TAB, SI><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
+    else if (w.R > 1)
+        k_spawn<KIND, W, true, false, SI><<<g.spawn, SP_T, 0, s>>>(w);
+    else if (TAB && w.lds_tables > 0)
+        k_spawn<KIND, W, false, TAB, SI><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
+    else
+        k_spawn<KIND, W, false, false, SI><<<g.spawn, SP_T, 0, s>>>(w);
+}
+
+// merge partition and merge, MI positions per thread (rec: records the event
+// after each launch)
+template <int KIND, int W, int MI, typename Rec>
+static void launch_merge(const Work &w, const Grids &g, hipStream_t s, int accb, Rec &rec)
+{
+    k_merge_partition<W, MI><<<g.part, 256, 0, s>>>(w);
+    rec();
+    if (w.R > 1)
+        k_merge<KIND, W, true, MI><<<g.merge, MergeCfg<W, MI>::T, accb, s>>>(w);
+    else
+        k_merge<KIND, W, false, MI><<<g.merge, MergeCfg<W, MI>::T, accb, s>>>(w);
+    rec();
+}
+
 template <int KIND, int W>
 static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t *ev)
 {
@@ -1968,25 +2100,32 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     rec();
     k_begin<<<1, 256, 0, s>>>(w);
     rec();
-    k_spawn_partition<<<g.part, 256, 0, s>>>(w, span_of(W));
+    // attempts per thread: a tile-shape variant for keys of up to two words
+    constexpr bool VAR = W <= 2 && !is_pair(KIND);
+    int si = VAR ? g.spawn_i : (W <= 2 ? 4 : 2);
+    if (si != 2 && si != 8) si = W <= 2 ? 4 : 2;  // the partition must match the launched variant
+    k_spawn_partition<<<g.part, 256, 0, s>>>(w, SP_T * si);
     rec();
-    constexpr bool TAB = KIND == K_UEG || KIND == K_MOLECULAR;
-    if (w.R > 1 && TAB && w.lds_tables > 0)
-        k_spawn<KIND, W, true, TAB><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
-    else if (w.R > 1)
-        k_spawn<KIND, W, true, false><<<g.spawn, SP_T, 0, s>>>(w);
-    else if ((KIND == K_UEG || KIND == K_MOLECULAR) && w.lds_tables > 0)
-        k_spawn<KIND, W, false, KIND == K_UEG || KIND == K_MOLECULAR><<<g.spawn, SP_T, g.spawn_lds, s>>>(w);
+    if (si == 2)
+        launch_spawn<KIND, W, VAR ? 2 : (W <= 2 ? 4 : 2)>(w, g, s);
+    else if (si == 8)
+        launch_spawn<KIND, W, VAR ? 8 : (W <= 2 ? 4 : 2)>(w, g, s);
     else
-        k_spawn<KIND, W, false, false><<<g.spawn, SP_T, 0, s>>>(w);
+        launch_spawn<KIND, W, W <= 2 ? 4 : 2>(w, g, s);
     rec();
     k_sort_hist<<<g.hist, 256, 0, s>>>(w);
     rec();
     uint64_t *K[2] = {w.sp.skey, w.sp.skey2};
     uint32_t *I[2] = {w.sp.idx, w.sp.idx2};
     for (int p = 0; p < 8; ++p) {
-        k_sort_pass<<<g.sort, OS_T, 0, s>>>(w, p, K[p & 1], p == 0 ? nullptr : I[p & 1], K[(p + 1) & 1],
-                                             I[(p + 1) & 1]);
+        const uint64_t *ki = K[p & 1];
+        const uint32_t *ii = p == 0 ? nullptr : I[p & 1];
+        if (g.sort_i == 8)
+            k_sort_pass<8><<<g.sort, OS_T, 0, s>>>(w, p, ki, ii, K[(p + 1) & 1], I[(p + 1) & 1]);
+        else if (g.sort_i == 16)
+            k_sort_pass<16><<<g.sort, OS_T, 0, s>>>(w, p, ki, ii, K[(p + 1) & 1], I[(p + 1) & 1]);
+        else
+            k_sort_pass<12><<<g.sort, OS_T, 0, s>>>(w, p, ki, ii, K[(p + 1) & 1], I[(p + 1) & 1]);
         rec();
     }
     const int accb = acc_rows(w.R) * EST_FIELDS * 8;
@@ -2005,13 +2144,14 @@ static void launch_kind(const Work &w, const Grids &g, hipStream_t s, hipEvent_t
     rec();
     k_det_project_fp64<<<g.det, 256, 0, s>>>(w, 1);
     rec();
-    k_merge_partition<W><<<g.part, 256, 0, s>>>(w);
-    rec();
-    if (w.R > 1)
-        k_merge<KIND, W, true><<<g.merge, MergeCfg<W>::T, accb, s>>>(w);
-    else
-        k_merge<KIND, W, false><<<g.merge, MergeCfg<W>::T, accb, s>>>(w);
-    rec();
+    const int mi = W <= 2 ? g.merge_i : 2;
+    if (mi == 1) {
+        launch_merge<KIND, W, W <= 2 ? 1 : 2>(w, g, s, accb, rec);
+    } else if (mi == 4) {
+        launch_merge<KIND, W, W <= 2 ? 4 : 2>(w, g, s, accb, rec);
+    } else {
+        launch_merge<KIND, W, 2>(w, g, s, accb, rec);
+    }
     k_new_diag<KIND, W><<<g.newdiag, ND_T, w.lds_diag, s>>>(w);
     rec();
     k_end<<<w.R, 1024, 0, s>>>(w, g.reduce, g.merge);
@@ -2028,6 +2168,9 @@ hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_
     case K_UEG * 16 + 8: launch_kind<K_UEG, 8>(w, g, s, ev); break;
     case K_MOLECULAR * 16 + 1: launch_kind<K_MOLECULAR, 1>(w, g, s, ev); break;
     case K_MOLECULAR * 16 + 2: launch_kind<K_MOLECULAR, 2>(w, g, s, ev); break;
+    case (K_HUBBARD | K_PAIR) * 16 + 2: launch_kind<K_HUBBARD | K_PAIR, 2>(w, g, s, ev); break;
+    case (K_UEG | K_PAIR) * 16 + 2: launch_kind<K_UEG | K_PAIR, 2>(w, g, s, ev); break;
+    case (K_MOLECULAR | K_PAIR) * 16 + 2: launch_kind<K_MOLECULAR | K_PAIR, 2>(w, g, s, ev); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2037,16 +2180,19 @@ template <int KIND, int W>
 static void setup_kind(int what, const Work &w, DevSys *sys, int n_sys, MainList L, long long n, const uint64_t *dk,
                        double *K, hipStream_t s)
 {
-    if (what == 0) k_h00<KIND, W><<<(n_sys + 63) / 64, 64, 0, s>>>(sys, n_sys);
+    // H_00 of the reference determinant (for pairs: of one half)
+    if (what == 0) k_h00<base_kind(KIND), is_pair(KIND) ? W / 2 : W><<<(n_sys + 63) / 64, 64, 0, s>>>(sys, n_sys);
     if (what == 1) {
         if (n > 0) k_kdiag<KIND, W><<<(int)std::min<long long>((n + 255) / 256, 4096), 256, 0, s>>>(w, L, n);
         Work w2 = w;
         w2.cur = L;
         k_scan_attempts<<<256, SCAN_T, 0, s>>>(w2);
     }
-    if (what == 2) {
-        k_build_kdd<KIND, W><<<2048, 256, 0, s>>>(w, dk, K);
-        if (w.ds.precision == 1) k_split_planes<<<2048, 256, 0, s>>>(w);
+    if constexpr (!is_pair(KIND)) {
+        if (what == 2) {
+            k_build_kdd<KIND, W><<<2048, 256, 0, s>>>(w, dk, K);
+            if (w.ds.precision == 1) k_split_planes<<<2048, 256, 0, s>>>(w);
+        }
     }
 }
 
@@ -2061,6 +2207,11 @@ hipError_t enqueue_setup(int what, int kind, const Work &w, DevSys *sys, int n_s
     case K_UEG * 16 + 8: setup_kind<K_UEG, 8>(what, w, sys, n_sys, L, n, dk, K, s); break;
     case K_MOLECULAR * 16 + 1: setup_kind<K_MOLECULAR, 1>(what, w, sys, n_sys, L, n, dk, K, s); break;
     case K_MOLECULAR * 16 + 2: setup_kind<K_MOLECULAR, 2>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case (K_HUBBARD | K_PAIR) * 16 + 2: setup_kind<K_HUBBARD | K_PAIR, 2>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case (K_UEG | K_PAIR) * 16 + 2: setup_kind<K_UEG | K_PAIR, 2>(what, w, sys, n_sys, L, n, dk, K, s); break;
+    case (K_MOLECULAR | K_PAIR) * 16 + 2:
+        setup_kind<K_MOLECULAR | K_PAIR, 2>(what, w, sys, n_sys, L, n, dk, K, s);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2071,12 +2222,12 @@ int occupancy_blocks(int which)
     int nb = 1;
     hipError_t e = hipSuccess;
     switch (which) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass, OS_T, 0); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false>, MergeCfg<2>::T, 0); break;
-    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 8, false>, MergeCfg<8>::T, 0); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sort_pass<12>, OS_T, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 2, false, 2>, MergeCfg<2, 2>::T, 0); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_merge<K_UEG, 8, false, 2>, MergeCfg<8, 2>::T, 0); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_reduce<2>, RD_T, 0); break;
     case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_scan_attempts, SCAN_T, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false, true>, SP_T, 8192); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_spawn<K_UEG, 2, false, true, 4>, SP_T, 8192); break;
     default: break;
     }
     if (e != hipSuccess) nb = 1;  // a persistent grid of one block per CU still covers every tile

@@ -19,15 +19,20 @@ FQ_OK, FQ_EINVAL, FQ_ECAPACITY, FQ_EOVERFLOW, FQ_EHIP, FQ_ESTATE = 0, -1, -2, -3
 HUBBARD, UEG, MOLECULAR = 1, 2, 3
 EXGEN = {HUBBARD: 1, UEG: 2, MOLECULAR: 3}
 SS_FP64, SS_SPLIT_BF16 = 0, 1
+FCIQMC, DMQMC, IPDMQMC = 0, 1, 2
 
 # every function the header declares
 C_API = ["fq_workspace_bytes", "fq_init_system", "fq_init_system_static", "fq_step", "fq_estimators", "fq_estimator_history",
          "fq_export_walkers", "fq_import_walkers", "fq_shift_state", "fq_export_spawns", "fq_detspace", "fq_info",
          "fq_set_timing", "fq_stage_times", "fq_kernel_times", "fq_iteration_times", "fq_set_graph",
-         "fq_set_sort_key_bits", "fq_set_launch", "fq_get_launch", "fq_reblock_create", "fq_reblock_add",
+         "fq_set_sort_key_bits", "fq_set_launch", "fq_get_launch", "fq_set_tiles", "fq_get_tiles",
+         "fq_reblock_create", "fq_reblock_add",
          "fq_reblock_level", "fq_reblock_optimal", "fq_reblock_ratio", "fq_reblock_destroy", "fq_last_error",
          "fq_destroy"]
 LAUNCH_KERNELS = ["spawn", "merge", "sort", "reduce", "new_diag"]
+# tile shapes (fq_set_tiles): spawning attempts, merge positions and sort keys per thread
+TILE_KNOBS = ["spawn_items", "merge_items", "sort_items"]
+TILE_VARIANTS = {"spawn_items": (2, 4, 8), "merge_items": (1, 2, 4), "sort_items": (8, 12, 16)}
 
 KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "sort_hist"] + \
     [f"sort_pass{p}" for p in range(8)] + ["reduce", "fixup", "reduce2", "det_gather", "det_project", "det_check",
@@ -53,7 +58,7 @@ class Qmc(C.Structure):
                 ("shift_period", C.c_int32), ("shift_damping", C.c_double), ("initial_shift", C.c_double),
                 ("excit_gen", C.c_int32), ("p_single", C.c_double), ("initiator", C.c_int32),
                 ("initiator_threshold", C.c_double), ("fixed_point_bits", C.c_int32),
-                ("spawn_cutoff", C.c_double), ("tau_search", C.c_int32)]
+                ("spawn_cutoff", C.c_double), ("tau_search", C.c_int32), ("method", C.c_int32)]
 
 
 class SemiStoch(C.Structure):
@@ -148,6 +153,10 @@ def load_library():
     L.fq_set_launch.restype = C.c_int32
     L.fq_get_launch.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
     L.fq_get_launch.restype = C.c_int32
+    L.fq_set_tiles.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
+    L.fq_set_tiles.restype = C.c_int32
+    L.fq_get_tiles.argtypes = [P, C.POINTER(C.c_int32), C.c_int32]
+    L.fq_get_tiles.restype = C.c_int32
     L.fq_last_error.argtypes = [P]
     L.fq_last_error.restype = C.c_char_p
     L.fq_destroy.argtypes = [P]
@@ -330,6 +339,16 @@ class Context:
         arr = (C.c_int32 * len(LAUNCH_KERNELS))()
         self._check(self.lib.fq_get_launch(self.ctx, arr, len(LAUNCH_KERNELS)))
         return dict(zip(LAUNCH_KERNELS, list(arr)))
+
+    def set_tiles(self, tiles):
+        """tiles: {name: value} for names in TILE_KNOBS (see fq_set_tiles)"""
+        arr = (C.c_int32 * len(TILE_KNOBS))(*[int(tiles.get(k, 0)) for k in TILE_KNOBS])
+        self._check(self.lib.fq_set_tiles(self.ctx, arr, len(TILE_KNOBS)))
+
+    def get_tiles(self):
+        arr = (C.c_int32 * len(TILE_KNOBS))()
+        self._check(self.lib.fq_get_tiles(self.ctx, arr, len(TILE_KNOBS)))
+        return dict(zip(TILE_KNOBS, list(arr)))
 
     def set_timing(self, on=True):
         self._check(self.lib.fq_set_timing(self.ctx, int(on)))

@@ -43,8 +43,11 @@ UEG54 = dict(
     qmc=dict(tau=0.0005, rng_seed=7, init_pop=1e4, target_population=2e7, shift_period=10,
              shift_damping=1.0, initial_shift=0.0, initiator=1, initiator_threshold=3.0,
              fixed_point_bits=8, spawn_cutoff=0.1),
-    semistoch=dict(size=8192),
+    semistoch=dict(size=8192, start_iteration=900),
     iterations=500,
+    # untimed warm-up before the 500 timed iterations; the list is at its
+    # working size (about 1.8e8 determinants) from iteration ~300 on
+    equilibration=1000,
 )
 
 UEG_ECUT_FOR_BASIS = {19: 2, 27: 3, 57: 5, 123: 9}

@@ -1,9 +1,10 @@
-"""Batching: graph replay, launch geometry and mixed-width batches, all bit-exact.
+"""Batching: graph replay, launch geometry, tile shapes and mixed-width
+batches, all bit-exact.
 
-Replaying a captured block of iterations, changing the number of blocks of the
-persistent kernels and spreading instances over several contexts change how
-the work is scheduled, never what is computed: every case below must give the
-oracle's walker lists and estimators to the last bit.
+Replaying a captured block of iterations, changing the number of blocks or the
+tile shapes of the persistent kernels and spreading instances over several
+contexts change how the work is scheduled, never what is computed: every case
+below must give the oracle's walker lists and estimators to the last bit.
 """
 import numpy as np
 import pytest
@@ -11,6 +12,7 @@ import pytest
 from gpu_helpers import assert_same_estimators, assert_same_lists, gpu_context, oracle_qmc, oracle_system, say
 from oracle import oracle as O
 from paper_1811_11679_amd import workloads
+from paper_1811_11679_amd.fciqmc import TILE_VARIANTS as F_TILE_VARIANTS
 
 pytestmark = pytest.mark.gpu
 
@@ -71,13 +73,52 @@ def test_autotuner_keeps_the_run_exact():
     run = _oracle_run(sysd, q)
     best = autotune.tune(ctx, iters=2, kernels=["merge", "sort"], log=say)
     n = int(ctx.estimators()["iteration"])
+    tiles = best.pop("tiles")
     assert set(best) == {"spawn", "merge", "sort", "reduce", "new_diag"} and all(v > 0 for v in best.values())
+    assert all(tiles[k] in F_TILE_VARIANTS[k] for k in tiles) and tiles == ctx.get_tiles()
     run.step(n)
     assert_same_lists(ctx, run, where=f"after autotuning ({n} iterations)")
     ctx.step(20)
     run.step(20)
     assert_same_lists(ctx, run, where="after autotuning + 20")
     ctx.close()
+
+
+def test_every_tile_variant_matches_the_oracle():
+    """Each compiled tile shape (spawning attempts, merge positions, radix-sort
+    keys per thread) gives the oracle's walker lists: one-word Hubbard keys,
+    two-word electron-gas keys (initiator, fixed point) and a batched pair of
+    electron-gas replicas; the shape changes between blocks of iterations."""
+    from paper_1811_11679_amd import fciqmc as F
+    cases = [
+        ([dict(kind="hubbard", n_sites=8, periodic=1, t=1.0, U=4.0, n_alpha=4, n_beta=4)],
+         [dict(tau=0.01, rng_seed=7, init_pop=500.0, target_population=1e4, initial_shift=-4.0)]),
+        ([dict(kind="ueg", rs=1.0, ecut_n2=5, n_alpha=7, n_beta=7)],
+         [dict(tau=0.002, rng_seed=7, init_pop=3e3, target_population=3e4, initiator=1, initiator_threshold=3.0,
+               fixed_point_bits=8, spawn_cutoff=0.1)]),
+        ([dict(kind="ueg", rs=1.0, ecut_n2=2, n_alpha=7, n_beta=7)] * 2,
+         [dict(tau=0.003, rng_seed=7, init_pop=2e3 * (r + 1), target_population=2e4, initiator=1,
+               initiator_threshold=3.0, fixed_point_bits=8, spawn_cutoff=0.1, replica_id=r) for r in range(2)]),
+    ]
+    for sysds, qs in cases:
+        say(f"[case] tile variants: {sysds[0]['kind']} x {len(sysds)}")
+        ctx = gpu_context(sysds, qs, replicas=list(range(len(qs))) if len(qs) > 1 else None)
+        runs = [_oracle_run(sysds[r], qs[r], replica=r) for r in range(len(qs))]
+        ctx.step(30)
+        for r in runs:
+            r.step(30)
+        for knob in F.TILE_KNOBS:
+            for v in F.TILE_VARIANTS[knob]:
+                ctx.set_tiles({knob: v})
+                ctx.step(10)
+                for i, r in enumerate(runs):
+                    r.step(10)
+                    assert_same_lists(ctx, r, instance=i, where=f"{knob} = {v}, instance {i}")
+                    assert_same_estimators(ctx.estimators(i), r.estimators(), where=f"{knob} = {v}")
+            ctx.set_tiles({knob: {"spawn_items": 4, "merge_items": 2, "sort_items": 12}[knob]})
+        with pytest.raises(F.FqError):
+            ctx.set_tiles({"merge_items": 3})
+        ctx.close()
 
 
 def test_mixed_width_batch_matches_plain_runs_and_oracle():
@@ -138,3 +179,39 @@ def test_graph_replay_with_tau_search_matches_oracle():
         assert_same_estimators(ctx.estimators(), run.estimators(), where="graph replay with tau search")
     assert ctx.estimators()["tau"] < 0.02
     ctx.close()
+
+
+def test_batch64_workload_one_instance_per_key_width_against_oracle():
+    """The 64-instance batched electron-gas workload at its full size (three
+    contexts: one-, two- and four-word keys). After 300 batched iterations, the
+    smallest instance of each context is exported and continued by the oracle
+    from that state for 20 iterations while the whole batch advances: its list
+    and estimators stay identical to the oracle's."""
+    from paper_1811_11679_amd import batch as B
+    import bench
+
+    inst = workloads.batch64()
+    bt = B.Batch(inst, capacity=bench.batch_capacity(inst))
+    say(f"[case] batch64: {len(inst)} instances in {len(bt.contexts)} contexts "
+        f"(key words {[c.W for c in bt.contexts]})")
+    assert sorted(c.W for c in bt.contexts) == [1, 2, 4]
+    bt.step(300)
+    checked = []
+    for g, members in enumerate(bt.groups):
+        i = min(members, key=lambda m: inst[m][1]["target_population"])
+        sysd, q = inst[i]
+        keys, pops = bt.export(i)
+        shift, nprev, vary = bt.shift_state(i)
+        e = bt.estimators(i)
+        run = _oracle_run(sysd, q, replica=q["replica_id"])
+        run.import_walkers(keys, pops, shift=shift, iteration=int(e["iteration"]), vary=vary, n_prev=nprev)
+        checked.append((i, run))
+        say(f"[case] instance {i}: {len(pops)} determinants, {e['n_walkers_units'] / 256:.4g} walkers, "
+            f"key words {bt.contexts[g].W}")
+    bt.step(20)
+    for i, run in checked:
+        run.step(20)
+        g, slot = bt.where[i]
+        assert_same_lists(bt.contexts[g], run, instance=slot, where=f"batch64 instance {i}")
+        assert_same_estimators(bt.estimators(i), run.estimators(), where=f"batch64 instance {i}")
+    bt.close()
