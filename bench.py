@@ -49,7 +49,9 @@ def algorithmic_bytes(hist_prev, hist, W, ds_active=False, instances=1):
     kb = 8 * W
     ds = 4 if ds_active else 0
     sk = 8 if instances > 1 or W > 2 else 0
-    out["spawn"] = nm * (kb + sk + 4 + ds + 8) + ns * (8 + kb + 8 + 8 + 4)
+    # spawn: parent key, sort key, population, slot and attempt offset read;
+    # per spawn its sort key and record (key words, amplitude | initiator flag)
+    out["spawn"] = nm * (kb + sk + 4 + ds + 8) + ns * (8 + kb + 8)
     out["sort_pass0"] = ns * (8 + 8 + 4)
     for p in range(1, 8):
         out[f"sort_pass{p}"] = ns * (8 + 4) * 2
@@ -94,6 +96,11 @@ class ProfilerRegion:
                 break
             except OSError:
                 continue
+        if self.lib is not None:
+            # roctx_thread_id_t: 64 bits; 0 = every thread of the process
+            for f in (self.lib.roctxProfilerResume, self.lib.roctxProfilerPause):
+                f.argtypes = [ctypes.c_uint64]
+                f.restype = None
 
     def resume(self):
         if self.lib is not None:
@@ -411,15 +418,25 @@ def run_single(args):
     scale = 2.0 ** q["fixed_point_bits"]
     t_w0 = time.perf_counter()
     pre = spec["equilibration"] + args.warmup
+    # tile shapes and block counts are searched on the live run once the
+    # population is at its working size (results do not depend on them)
+    tune_at = pre // 2 if not args.no_autotune else None
+    tuned = None
     done = 0
     while done < pre:
         k = min(250, pre - done)
+        if tune_at is not None and done < tune_at < done + k:
+            k = tune_at - done
         ctx.step(k)
         done += k
         e = ctx.estimators()
         log(f"equilibration {done}/{pre}: N_w {e['n_walkers_units'] / scale:.4g} walkers, "
             f"{e['n_occupied']} determinants, N_0 {e['ref_pop_units'] / scale:.4g}, shift {e['shift']:.5f}, "
             f"E_proj {e['proj_energy']:.5f}, {time.perf_counter() - t_w0:.1f} s")
+        if tune_at is not None and done == tune_at:
+            from paper_1811_11679_amd import autotune
+            tuned = autotune.tune(ctx, iters=3, log=log)
+            done = int(ctx.estimators()["iteration"])
     warm_s = time.perf_counter() - t_w0
     e_start = ctx.estimators()
     start_state = None
@@ -478,7 +495,8 @@ def run_single(args):
                 "equilibration_iterations": spec["equilibration"],
                 "timed_iterations": f"{e_start['iteration'] + 1}..{hist[-1]['iteration']}",
                 "kernel_timing_iterations": f"{e_k0['iteration'] + 1}..{hk[-1]['iteration']}",
-                "graph_replay": True, "parallelism": "single GPU"})
+                "graph_replay": True, "autotuned": tuned, "tiles": ctx.get_tiles(), "blocks": ctx.get_launch(),
+                "parallelism": "single GPU"})
     out = {
         "metric": METRIC,
         "value": upd / dt,
@@ -548,6 +566,8 @@ def main():
                     help="determinant capacity (default 2^28; ueg54: 3.3e8)")
     ap.add_argument("--spawn-capacity", type=int, default=None, help="spawn capacity (default 2^27; ueg54: 2e8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shapes and block counts (no search during equilibration)")
     ap.add_argument("--target", type=float, default=None, help="ueg54: target walkers")
     ap.add_argument("--init-pop", type=float, default=None, help="ueg54: initial walkers on the reference")
     ap.add_argument("--shift-damping", type=float, default=None, help="ueg54: shift damping (zeta)")

@@ -225,6 +225,10 @@ struct UegTables {
     const double *vx;     // [M][M] v(|n_p - n_q|^2), or nullptr: use vtab and npk
     const int16_t *grid;  // momentum grid -> plane-wave index, -1 outside
     int32_t M, nel, gmax, gdim;
+    // p_gen of an excitation from a same-spin / an opposite-spin pair:
+    // 2 / (C(N,2) M) and 2 / (C(N,2) 2M), each one correctly rounded FP64
+    // division done on the host (the same value the generator would compute)
+    double pgen_same, pgen_opp;
 };
 
 struct DevSys {
@@ -526,14 +530,11 @@ __device__ bool gen_ueg(const UegTables &s, const uint64_t (&D)[W], uint32_t w0,
     const int j = i + 1 + (k - i * (2 * N - i - 1) / 2);
     const int P = select_bit<W>(D, i), Q = select_bit<W>(D, j);
     const int sP = P & 1, sQ = Q & 1, M = s.M;
-    int A, na;
-    if (sP == sQ) {
-        na = M;
+    int A;
+    if (sP == sQ)
         A = 2 * (int)pick(w1, (uint32_t)M) + sP;
-    } else {
-        na = 2 * M;
+    else
         A = (int)pick(w1, (uint32_t)(2 * M));
-    }
     const int sA = A & 1, sB = sP + sQ - sA;
     const int p = P >> 1, q = Q >> 1, a = A >> 1;
     const int32_t bp = s.npk[p] + s.npk[q] - s.npk[a];
@@ -551,7 +552,7 @@ __device__ bool gen_ueg(const UegTables &s, const uint64_t (&D)[W], uint32_t w0,
     flipbit<W>(child, Q);
     flipbit<W>(child, lo);
     flipbit<W>(child, hi);
-    pgen = 2.0 / (double)((int64_t)npairs * na);
+    pgen = sP == sQ ? s.pgen_same : s.pgen_opp;  // 2 / (C(N,2) n_A), n_A = M or 2M
     uint64_t tmp[W];
 #pragma unroll
     for (int t2 = 0; t2 < W; ++t2) tmp[t2] = D[t2];

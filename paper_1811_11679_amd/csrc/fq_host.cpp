@@ -229,7 +229,7 @@ size_t table_bytes(const HostSys &s)
 struct Layout {
     size_t total = 0;
     size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge, st_spawn, st_att;
-    size_t part_red, part_mrg, newdet;
+    size_t part_red, part_mrg, newdet, bpart;
     size_t main[2][6];
     size_t sp[7];
     size_t u[4];
@@ -278,6 +278,7 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.span = take(8 * (size_t)(span_capacity(mcap, scap, W) + 2));
     L.mpart = take(8 * (size_t)(tiles_of(mcap + scap, 512) + 2));
     L.newdet = take((size_t)mcap + 16);
+    L.bpart = take(sizeof(BoundaryPart) * (size_t)tiles_of(scap, 1024));
     L.st_scan = take(8 * (size_t)tiles_of(mcap, 2048));
     L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, SORT_TILE_MIN));
     L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
@@ -827,6 +828,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     w.span_lo = (long long *)(c->ws + c->L.span);
     w.mpart = (long long *)(c->ws + c->L.mpart);
     w.newdet = (uint8_t *)(c->ws + c->L.newdet);
+    w.bpart = (BoundaryPart *)(c->ws + c->L.bpart);
     w.st_scan = (unsigned long long *)(c->ws + c->L.st_scan);
     w.st_sort = (unsigned long long *)(c->ws + c->L.st_sort);
     w.st_red = (unsigned long long *)(c->ws + c->L.st_red);
@@ -905,6 +907,12 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
         d.u.gdim = s.gdim;
         d.u.M = s.n_spatial;
         d.u.nel = s.nel;
+        if (s.kind == FQ_UEG) {
+            // the generator's p_gen = 2 / (C(N,2) n_A) for n_A = M and 2M
+            const int64_t npairs = (int64_t)s.nel * (s.nel - 1) / 2;
+            d.u.pgen_same = 2.0 / (double)(npairs * s.n_spatial);
+            d.u.pgen_opp = 2.0 / (double)(npairs * 2 * s.n_spatial);
+        }
         d.vlen = s.vlen;
         d.u.npk = (const int32_t *)put(s.npk.data(), 4 * s.npk.size());
         d.u.vx = (const double *)put(s.vx.data(), 8 * s.vx.size());
@@ -1376,6 +1384,40 @@ fq_status instance_range(fq_ctx *c, int instance, int64_t &lo, int64_t &hi)
     return first_rep_at_least((uint64_t)instance + 1, hi);
 }
 
+}  // extern "C"
+
+namespace {
+
+// word-major keys kk[q * n + i] and populations, written out in key order
+template <int W>
+void sort_rows(const std::vector<uint64_t> &kk, const std::vector<int32_t> &pp, int64_t n, uint64_t *keys,
+               int32_t *pops)
+{
+    struct Row {
+        uint64_t k[W];
+        int32_t pop;
+    };
+    std::vector<Row> rows(n);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int q = 0; q < W; ++q) rows[i].k[q] = kk[(size_t)q * n + i];
+        rows[i].pop = pp[i];
+    }
+    std::sort(rows.begin(), rows.end(), [](const Row &a, const Row &b) {
+        for (int q = W - 1; q >= 0; --q)
+            if (a.k[q] != b.k[q]) return a.k[q] < b.k[q];
+        return false;
+    });
+    for (int64_t i = 0; i < n; ++i) {
+        if (keys)
+            for (int q = 0; q < W; ++q) keys[(size_t)i * W + q] = rows[i].k[q];
+        if (pops) pops[i] = rows[i].pop;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
 fq_status fq_export_walkers(const fq_ctx *cc, int32_t instance, uint64_t *keys, int32_t *pops, int64_t cap,
                             int64_t *n_out)
 {
@@ -1397,20 +1439,13 @@ fq_status fq_export_walkers(const fq_ctx *cc, int32_t instance, uint64_t *keys, 
             HIPCHK(c, d2h(c->stream, kk.data() + (size_t)q * n, m.key + (size_t)q * c->main_cap + lo, 8 * n));
         HIPCHK(c, d2h(c->stream, pp.data(), m.pop + lo, 4 * n));
     }
-    // key order: most significant word first
-    std::vector<int64_t> ord(n);
-    for (int64_t i = 0; i < n; ++i) ord[i] = i;
-    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
-        for (int q = W - 1; q >= 0; --q) {
-            const uint64_t x = kk[(size_t)q * n + a], y = kk[(size_t)q * n + b];
-            if (x != y) return x < y;
-        }
-        return false;
-    });
-    for (int64_t i = 0; i < n; ++i) {
-        if (keys)
-            for (int q = 0; q < W; ++q) keys[(size_t)i * W + q] = kk[(size_t)q * n + ord[i]];
-        if (pops) pops[i] = pp[ord[i]];
+    // key order (most significant word first): rows of (key words, population)
+    // sorted in place, so that every comparison reads one contiguous row
+    switch (W) {
+    case 1: sort_rows<1>(kk, pp, n, keys, pops); break;
+    case 2: sort_rows<2>(kk, pp, n, keys, pops); break;
+    case 4: sort_rows<4>(kk, pp, n, keys, pops); break;
+    default: sort_rows<8>(kk, pp, n, keys, pops); break;
     }
     return FQ_OK;
 }

@@ -157,6 +157,17 @@ struct DetSpace {
     const uint64_t *key_sorted;   // [W][R*n]
 };
 
+// The part of a spawned-list segment that lies in one reduction tile when the
+// segment's head is in an earlier tile (at most one per tile): added to the
+// segment's total after the reduction.
+struct BoundaryPart {
+    long long sum;
+    long long seg;
+    uint32_t flag;
+    uint32_t valid;
+    long long pad;
+};
+
 struct Work {
     Ctl *ctl;
     EstAcc *acc;        // [R]
@@ -168,6 +179,7 @@ struct Work {
     long long *span_lo;    // [spans + 1]
     long long *mpart;      // merge partition [tiles + 1]
     uint8_t *newdet;       // [main_cap]: 1 where the merge wrote a new determinant (K_jj still to compute)
+    BoundaryPart *bpart;   // [reduction tiles]
     unsigned long long *st_scan, *st_sort, *st_red, *st_merge, *st_spawn, *st_att;  // look-back status
     // per-block estimator partials of the reduction and the merge:
     // [block][acc_rows(R)][EST_FIELDS], folded into acc by the epilogue

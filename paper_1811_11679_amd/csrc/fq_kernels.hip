@@ -601,6 +601,8 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                         double m;
                         if (rp.bits == 0)
                             m = (tau_s * ah) / pgen;
+                        else if (nat_s == 1)
+                            m = ((tau_s * ah) / pgen) * (double)an;  // x / 1.0 is x
                         else
                             m = (((tau_s * ah) / pgen) * (double)an) / (double)nat_s;
                         // the Hubbard and electron-gas generators leave the last two
@@ -686,8 +688,6 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 #pragma unroll
                 for (int q = 0; q < W; ++q) rec[q] = key[q];
                 rec[W] = (uint64_t)(uint32_t)s_ramp[p] | ((uint64_t)s_rinit[p] << 32);
-                w.u.sum[o] = 0;
-                w.u.flag[o] = 0;
             }
 #pragma unroll
             for (int it = 0; it < SP_I; ++it)
@@ -698,8 +698,6 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
 #pragma unroll
                     for (int q = 0; q < W; ++q) rec[q] = child[it][q];
                     rec[W] = (uint64_t)(uint32_t)amp[it] | ((uint64_t)init[it] << 32);
-                    w.u.sum[o] = 0;
-                    w.u.flag[o] = 0;
                 }
         }
         if (span == nspans - 1 && threadIdx.x == 0) c->n_spawn = (unsigned long long)(base + tot);
@@ -903,6 +901,9 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
     __shared__ uint64_t s_lasts[RD_T];
     __shared__ long long s_tile, s_base;
     __shared__ long long s_red[8];
+    __shared__ long long s_ws[RD_T / 64];
+    __shared__ uint32_t s_wf[RD_T / 64];
+    __shared__ int s_wr[RD_T / 64];
     const long long n = (long long)min(c->n_spawn, (unsigned long long)w.spawn_cap);
     const long long ntiles = (n + RD_TILE - 1) / RD_TILE;
     const uint32_t epoch = epoch_of(c->t, second ? 10 : 9);
@@ -979,6 +980,82 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
             for (int q = 0; q < W; ++q) pk[q] = kk[i][q];
             have_prev = true;
         }
+        // the open segment at this thread's end (after its last head, or all
+        // of its elements without a head), passed to the right
+        long long lead_s = 0, tail_s = 0;
+        uint32_t lead_f = 0, tail_f = 0;
+        {
+            bool seen = false;
+#pragma unroll
+            for (int i = 0; i < RD_I; ++i) {
+                if (!valid[i]) continue;
+                if (head[i]) {
+                    seen = true;
+                    tail_s = 0;
+                    tail_f = 0;
+                }
+                if (seen) {
+                    tail_s += am[i];
+                    tail_f |= fl[i];
+                } else {
+                    lead_s += am[i];
+                    lead_f |= fl[i];
+                }
+            }
+        }
+        // exclusive segmented scan over the tile's threads: the partial sum and
+        // flags of the segment open at this thread's first element (threads
+        // with a head restart it)
+        long long carry_s;
+        uint32_t carry_f;
+        {
+            const int lane = lane_id(), wid = threadIdx.x >> 6;
+            bool r = nh > 0;
+            long long xs = r ? tail_s : lead_s;
+            uint32_t xf = r ? tail_f : lead_f;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const long long ys = __shfl_up(xs, o, 64);
+                const uint32_t yf = __shfl_up(xf, o, 64);
+                const bool yr = __shfl_up((int)r, o, 64) != 0;
+                if (lane >= o && !r) {
+                    xs += ys;
+                    xf |= yf;
+                    r = yr;
+                }
+            }
+            // wave totals, then the prefix of the earlier waves
+            if (lane == 63) {
+                s_ws[wid] = xs;
+                s_wf[wid] = xf;
+                s_wr[wid] = r ? 1 : 0;
+            }
+            long long es = __shfl_up(xs, 1, 64);
+            uint32_t ef = __shfl_up(xf, 1, 64);
+            bool er = __shfl_up((int)r, 1, 64) != 0;
+            if (lane == 0) {
+                es = 0;
+                ef = 0;
+                er = false;
+            }
+            __syncthreads();
+            if (!er) {
+                long long ps = 0;
+                uint32_t pf = 0;
+                for (int q = 0; q < wid; ++q) {
+                    if (s_wr[q]) {
+                        ps = 0;
+                        pf = 0;
+                    }
+                    ps += s_ws[q];
+                    pf |= s_wf[q];
+                }
+                es += ps;
+                ef |= pf;
+            }
+            carry_s = es;
+            carry_f = ef;
+        }
         long long tot;
         const long long ex = block_excl_scan<long long>((long long)nh, tot, s_red);
         if (threadIdx.x < 64) {
@@ -986,40 +1063,72 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
             if (threadIdx.x == 0) s_base = lb_;
         }
         __syncthreads();
-        long long seg = s_base + ex - 1;  // segment of the element before this thread's first
-        long long run_sum = 0;
-        uint32_t run_flag = 0;
-        long long run_seg = -1;
+        // Segment totals. A segment is stored by the thread holding its last
+        // element in the tile: the thread of the next head, or the thread of
+        // the tile's last element. The part of a segment whose head lies in an
+        // earlier tile becomes this tile's boundary part.
+        const long long tile_end = min(tile * RD_TILE + RD_TILE, n);
+        long long seg = s_base + ex - 1;  // segment open at this thread's first element
+        long long run_s = carry_s;
+        uint32_t run_f = carry_f;
+        bool run_here = ex > 0;  // its head is in this tile
+        // whether the open segment holds elements of this tile before this thread
+        bool run_nonempty = threadIdx.x > 0;
+        BoundaryPart bp;
+        bp.sum = 0;
+        bp.seg = 0;
+        bp.flag = 0;
+        bp.valid = 0;
+        bp.pad = 0;
+        bool bp_mine = false;
+        if (threadIdx.x == 0 && valid[0] && head[0]) bp_mine = true;  // no boundary part: record it as such
 #pragma unroll
         for (int i = 0; i < RD_I; ++i) {
             if (!valid[i]) continue;
             if (head[i]) {
+                if (run_nonempty) {
+                    if (run_here) {
+                        w.u.sum[seg] = run_s;
+                        w.u.flag[seg] = run_f;
+                    } else {
+                        bp.sum = run_s;
+                        bp.flag = run_f;
+                        bp.seg = s_base - 1;
+                        bp.valid = 1;
+                        bp_mine = true;
+                    }
+                }
                 ++seg;
                 w.u.skey[seg] = sk[i];
 #pragma unroll
                 for (int q = 0; q < W; ++q) w.u.key[(size_t)q * w.spawn_cap + seg] = kk[i][q];
+                run_s = 0;
+                run_f = 0;
+                run_here = true;
             }
-            if (seg != run_seg) {
-                if (run_seg >= 0) {
-                    atomicAdd((unsigned long long *)&w.u.sum[run_seg], (unsigned long long)run_sum);
-                    if (run_flag) atomicOr(&w.u.flag[run_seg], run_flag);
+            run_s += am[i];
+            run_f |= fl[i];
+            run_nonempty = true;
+            if (base + i == tile_end - 1) {
+                // the tile's last element closes its open segment here
+                if (run_here) {
+                    w.u.sum[seg] = run_s;
+                    w.u.flag[seg] = run_f;
+                } else {
+                    bp.sum = run_s;
+                    bp.flag = run_f;
+                    bp.seg = s_base - 1;
+                    bp.valid = 1;
+                    bp_mine = true;
                 }
-                run_seg = seg;
-                run_sum = 0;
-                run_flag = 0;
             }
-            run_sum += am[i];
-            run_flag |= fl[i];
             acc_switch(acc, (int)skey_rep(sk[i], w.rb), tab, rl, w.acc);
             acc.v[F_NSPAWN] += 1;
             acc.v[F_SPAWN] += am[i];
             acc.v[F_NUNIQ] += head[i] ? 1 : 0;
             any = true;
         }
-        if (run_seg >= 0) {
-            atomicAdd((unsigned long long *)&w.u.sum[run_seg], (unsigned long long)run_sum);
-            if (run_flag) atomicOr(&w.u.flag[run_seg], run_flag);
-        }
+        if (bp_mine) w.bpart[tile] = bp;
         if (tile == ntiles - 1 && threadIdx.x == 0) c->n_uniq = s_base + tot;
         __syncthreads();
     }
@@ -1052,10 +1161,6 @@ __global__ void k_fixup(Work w)
     uint32_t *idx = w.sp.idx;
     uint32_t *tmp = w.sp.idx2;
     const long long gs = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) {
-        w.u.sum[i] = 0;
-        w.u.flag[i] = 0;
-    }
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < w.R * (int)(sizeof(EstAcc) / 8); i += blockDim.x) {
             const int r = i / (int)(sizeof(EstAcc) / 8), f = i % (int)(sizeof(EstAcc) / 8);
@@ -1172,6 +1277,19 @@ __global__ void k_merge_partition(Work w)
 {
     const Ctl *c = w.ctl;
     if (c->err) return;
+    {
+        // the segmented reduction's boundary parts (one per reduction tile at
+        // most): the last reduction launch of the iteration has finished
+        const long long ns = (long long)min(c->n_spawn, (unsigned long long)w.spawn_cap);
+        const long long nrt = (ns + RD_TILE - 1) / RD_TILE;
+        for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nrt; t += (long long)gridDim.x * blockDim.x) {
+            const BoundaryPart b = w.bpart[t];
+            if (b.valid) {
+                atomicAdd((unsigned long long *)&w.u.sum[b.seg], (unsigned long long)b.sum);
+                if (b.flag) atomicOr(&w.u.flag[b.seg], b.flag);
+            }
+        }
+    }
     constexpr int TILE = MergeCfg<W, MI>::TILE;
     const long long na = c->n_main, nb = c->n_uniq;
     const long long ntiles = (na + nb + TILE - 1) / TILE;

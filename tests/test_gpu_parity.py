@@ -184,6 +184,18 @@ def test_empty_spawn_iterations_and_tiny_lists():
     _compare_run(sysd, q, 60, 20, tag="tiny")
 
 
+def test_segments_spanning_several_reduction_tiles():
+    """Determinants that receive thousands of spawns in one iteration: the
+    annihilation's segments of equal determinants span whole tiles of the
+    segmented reduction (1024 spawns), so segment totals are assembled across
+    tiles. A 6-site ring whose reference holds 2e5 integer walkers spawns
+    ~2e4 times into each of its few neighbours."""
+    sysd = dict(kind="hubbard", n_sites=6, periodic=1, t=1.0, U=4.0, n_alpha=3, n_beta=3)
+    q = dict(tau=0.01, rng_seed=13, init_pop=2e5, target_population=1e9, initial_shift=-3.0)
+    e = _compare_run(sysd, q, 12, 3, tag="long segments", main_cap=1 << 16, spawn_cap=1 << 22)
+    assert e["n_spawned"] > 50 * e["n_spawn_events"]  # many spawns per distinct determinant
+
+
 def test_export_import_roundtrip_and_resume():
     w = workloads.UEG14
     q = dict(w["qmc"], init_pop=2e4, target_population=1e9)

@@ -59,7 +59,8 @@ def test_byte_model_counts_the_moved_fields():
     b1 = bench.algorithmic_bytes(prev, cur, 2)
     # one instance, W = 2, no deterministic space: main read 16+4+8, distinct 8+16+8+4, output 16+4+8+8+1
     assert b1["merge"] == 1000 * 28 + 200 * 36 + 1100 * 37
-    assert b1["spawn"] == 1000 * (16 + 4 + 8) + 300 * (8 + 16 + 8 + 8 + 4)
+    # spawn: parent key, population, attempt offset; per spawn sort key + key words + amplitude word
+    assert b1["spawn"] == 1000 * (16 + 4 + 8) + 300 * (8 + 16 + 8)
     b2 = bench.algorithmic_bytes(prev, cur, 2, ds_active=True, instances=4)
     assert b2["merge"] - b1["merge"] == 1000 * 12 + 1100 * 12
     b8 = bench.algorithmic_bytes(prev, cur, 8)
