@@ -154,9 +154,21 @@ def test_ueg54_full_size_iteration_sampled_against_oracle():
     say(f"[case] {n_checked} sampled spawns and {deaths} death steps identical to the oracle")
     assert n_checked > 100 and deaths > N_SAMPLE // 2
 
-    # 2. merged populations of sampled spawned-to determinants
-    n_occ = n_new = 0
-    for g in rng.choice(len(g_lo), 300, replace=False):
+    # 2. merged populations of sampled spawned-to determinants: most spawns land
+    # on unoccupied determinants, so the occupied ones are sampled on their own
+    # (found through fingerprints of the old list, then compared in full)
+    say("[case] finding spawned-to determinants that were occupied")
+    fp0 = np.sort(_fingerprint(k0))
+    gf = gfp[g_lo]
+    pos = np.minimum(np.searchsorted(fp0, gf), len(fp0) - 1)
+    occ_groups = np.flatnonzero(fp0[pos] == gf)
+    del fp0
+    occ_groups = occ_groups[~np.isin(gf[occ_groups], _fingerprint(dkeys))]  # not in the deterministic space
+    say(f"[case] {len(occ_groups)} of them may have been occupied")
+    picks = np.concatenate([rng.choice(len(g_lo), 300, replace=False),
+                            rng.choice(occ_groups, min(150, len(occ_groups)), replace=False)])
+    n_occ = n_new = n_rej = 0
+    for g in picks:
         key = gk[g_lo[g]]
         if _tup(key) in dset:
             continue
@@ -170,8 +182,10 @@ def test_ueg54_full_size_iteration_sampled_against_oracle():
         else:
             want = int(amps.sum()) if (inits.any() and int(amps.sum()) != 0) else 0
             n_new += int(want != 0)
+            n_rej += int(want == 0)
         j = _find(k1, key)
         assert (int(p1[j]) if j >= 0 else 0) == want, (_tup(key), want)
-    say(f"[case] merged populations of sampled spawned-to determinants identical: {n_occ} occupied, {n_new} created")
-    assert n_occ + n_new > 100
+    say(f"[case] merged populations of sampled spawned-to determinants identical: {n_occ} occupied, {n_new} created, "
+        f"{n_rej} rejected or cancelled")
+    assert n_occ + n_new + n_rej > 300 and n_occ >= min(50, len(occ_groups) // 2)
     ctx.close()
