@@ -53,7 +53,7 @@ static uint32_t pick(uint32_t w, uint32_t n)
     return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32);
 }
 
-enum { TAG_SELECT = 0, TAG_SELECT2 = 1, TAG_SPAWN_ROUND = 2, TAG_DEATH = 3, TAG_SEMISTOCH = 4 };
+enum { TAG_SELECT = 0, TAG_SELECT2 = 1, TAG_SPAWN_ROUND = 2, TAG_DEATH = 3, TAG_SEMISTOCH = 4, TAG_CLUSTER = 5 };
 
 static void draw(const or_run *r, uint32_t tag, uint32_t attempt, uint32_t t, uint64_t h,
                  uint32_t out[4]);
@@ -738,7 +738,7 @@ static int det_words(const or_run *r) { return r->s->W; }
 static double entry_kdiag(const or_run *r, const uint64_t *key)
 {
     const or_sys *s = r->s;
-    if (r->q.method == OR_FCIQMC) return or_diag(s, key) - s->H00;
+    if (r->q.method == OR_FCIQMC || r->q.method == OR_CCMC) return or_diag(s, key) - s->H00;
     int w = det_words(r);
     double ki = or_diag(s, key) - s->H00;
     double kj = or_diag(s, key + w) - s->H00;
@@ -776,8 +776,11 @@ static void compute_estimators(or_run *r)
 {
     or_estimators *e = &r->est;
     int64_t nw = 0, n0 = 0;
-    int64_t limbs[4] = {0, 0, 0, 0};
-    int dm = r->q.method != OR_FCIQMC;
+    int64_t limbs[4] = {0, 0, 0, 0}, plimbs[4] = {0, 0, 0, 0};
+    int64_t n1 = 0;
+    int64_t *singles = NULL;
+    if (r->q.method == OR_CCMC) singles = (int64_t *)malloc(sizeof(int64_t) * (size_t)(r->n ? r->n : 1));
+    int dm = r->q.method == OR_DMQMC || r->q.method == OR_IPDMQMC;
     int w = det_words(r);
     for (int64_t i = 0; i < r->n; ++i) {
         const uint64_t *k = r->keys + (size_t)i * r->W;
@@ -797,16 +800,34 @@ static void compute_estimators(or_run *r)
         if (is_reference(r, k)) { n0 = p; continue; }
         int nd = 0;
         for (int x = 0; x < r->W; ++x) nd += __builtin_popcountll(k[x] ^ r->s->ref[x]);
+        if (singles && nd == 2 && p != 0) singles[n1++] = i;
         if (nd != 2 && nd != 4) continue;
         double h = or_hij(r->s, r->s->ref, k);
         acc_term(limbs, h * (double)p);
     }
+    /* CCMC (Sec. 2.2): t~_j = <D_j|Psi> of a double also holds the products of
+       pairs of singles, (1 / N_0) sgn N_a N_b for a_a a_b D_0 = sgn D_j; their
+       part of sum_j H_0j t~_j is summed exactly here and divided by N_0 below */
+    for (int64_t x = 0; x < n1; ++x)
+        for (int64_t y = x + 1; y < n1; ++y) {
+            uint64_t ex[2 * OR_MAXW], D[OR_MAXW];
+            memcpy(ex, r->keys + (size_t)singles[x] * r->W, sizeof(uint64_t) * r->W);
+            memcpy(ex + r->W, r->keys + (size_t)singles[y] * r->W, sizeof(uint64_t) * r->W);
+            int sg = or_cluster_collapse(r->s, ex, 2, D);
+            if (sg == 0) continue;
+            double h = or_hij(r->s, r->s->ref, D);
+            double term = (h * (double)r->pops[singles[x]]) * (double)r->pops[singles[y]];
+            acc_term(plimbs, sg > 0 ? term : -term);
+        }
+    free(singles);
     e->iteration = r->t;
     e->n_walkers_units = nw;
     e->n_occupied = r->n;
     e->ref_pop_units = n0;
     memcpy(e->num_limbs, limbs, sizeof(limbs));
+    memcpy(e->pair_limbs, plimbs, sizeof(plimbs));
     double num = limbs_value(limbs);
+    if (r->q.method == OR_CCMC && n0 != 0) num = num + limbs_value(plimbs) / (double)n0;
     double scale = ldexp(1.0, -r->q.fixed_point_bits);
     e->proj_numerator = num * scale;
     e->proj_energy = n0 != 0 ? num / (double)n0 : NAN;
@@ -826,15 +847,21 @@ or_run *or_run_new(const or_sys *s, const or_qmc *q)
     if (q->excit_gen == OR_EXGEN_HUB && s->kind != OR_HUBBARD) return NULL;
     if (q->excit_gen == OR_EXGEN_UEG && s->kind != OR_UEG) return NULL;
     if (q->excit_gen == OR_EXGEN_HEATBATH && s->kind != OR_MOLECULAR) return NULL;
-    if (q->method < OR_FCIQMC || q->method > OR_IPDMQMC) return NULL;
+    if (q->method < OR_FCIQMC || q->method > OR_CCMC) return NULL;
+    /* CCMC: excitors of level 1..6 (clusters of at most 8 excitors), no
+       initiator rule, deterministic space or time-step search */
+    if (q->method == OR_CCMC && (q->ccmc_truncation < 1 || q->ccmc_truncation > 6 || q->initiator ||
+                                 q->ss_size > 0 || q->tau_search))
+        return NULL;
     /* density matrices: pairs of determinants of at most four words, no
        initiator rule, deterministic space or time-step search */
-    if (q->method != OR_FCIQMC && (2 * s->W > OR_MAXW || q->initiator || q->ss_size > 0 || q->tau_search))
+    if ((q->method == OR_DMQMC || q->method == OR_IPDMQMC) &&
+        (2 * s->W > OR_MAXW || q->initiator || q->ss_size > 0 || q->tau_search))
         return NULL;
     or_run *r = (or_run *)calloc(1, sizeof(or_run));
     r->s = s;
     r->q = *q;
-    r->W = q->method == OR_FCIQMC ? s->W : 2 * s->W;
+    r->W = (q->method == OR_FCIQMC || q->method == OR_CCMC) ? s->W : 2 * s->W;
     double scale = ldexp(1.0, q->fixed_point_bits);
     r->cu = q->fixed_point_bits ? (int64_t)floor(q->spawn_cutoff * scale + 0.5) : 0;
     r->thr = (int64_t)floor(q->initiator_threshold * scale);
@@ -863,6 +890,62 @@ void or_run_free(or_run *r)
     free(r);
 }
 
+/* Excitation level of a determinant relative to D_0: electrons moved. */
+static int excit_level(const or_sys *s, const uint64_t *key)
+{
+    int d = 0;
+    for (int x = 0; x < s->W; ++x) d += __builtin_popcountll(key[x] ^ s->ref[x]);
+    return d / 2;
+}
+
+/* ---- coupled cluster Monte Carlo (Sec. 2.2, eq. ccmc) ----
+ * The excitor of determinant D_e moves the electrons of its holes
+ * H_e = D_0 \ D_e to its particles P_e = D_e \ D_0. Written as a product of
+ * single moves c+_p c_h (k-th lowest hole to k-th lowest particle, applied
+ * lowest first), it acts on a determinant D by the second-quantised rules: a
+ * move needs h occupied and p empty (else the product vanishes) and gives
+ * (-1)^(occupied spin-orbitals strictly between h and p). The excitor a_e is
+ * that product times the sign sigma_e making a_e D_0 = +D_e. Pairs c+ c on
+ * distinct spin-orbitals commute, so excitors commute and the product of a
+ * cluster does not depend on the order of its excitors. */
+static int moves_apply(const or_sys *s, const uint64_t *e, uint64_t *D)
+{
+    int holes[64], parts[64], nh = 0, np = 0;
+    for (int P = 0; P < s->n_so; ++P) {
+        int in0 = getbit(s->ref, P), ine = getbit(e, P);
+        if (in0 && !ine) holes[nh++] = P;
+        if (!in0 && ine) parts[np++] = P;
+        if (nh == 64 || np == 64) return 0;
+    }
+    if (nh != np) return 0;
+    int sign = 1;
+    for (int k = 0; k < nh; ++k) {
+        int h = holes[k], p = parts[k];
+        if (!getbit(D, h) || getbit(D, p)) return 0;
+        if (parity_between(D, h, p) < 0.0) sign = -sign;
+        clrbit(D, h);
+        setbit(D, p);
+    }
+    return sign;
+}
+
+int or_cluster_collapse(const or_sys *s, const uint64_t *ex, int n, uint64_t *out)
+{
+    uint64_t D[OR_MAXW], D0[OR_MAXW];
+    memcpy(D, s->ref, sizeof(uint64_t) * s->W);
+    int sign = 1;
+    for (int j = 0; j < n; ++j) {
+        const uint64_t *e = ex + (size_t)j * s->W;
+        memcpy(D0, s->ref, sizeof(uint64_t) * s->W);
+        int sigma = moves_apply(s, e, D0); /* a_e D_0 = sigma * (moves) D_0 = +D_e */
+        int m = moves_apply(s, e, D);
+        if (sigma == 0 || m == 0) return 0;
+        sign *= sigma * m;
+    }
+    memcpy(out, D, sizeof(uint64_t) * s->W);
+    return sign;
+}
+
 /* ---- one spawning attempt (Sec. 2.4 "spawning"; Sec. 2.1 real weights) ---- */
 static int spawn_attempt(or_run *r, const uint64_t *key, uint64_t h, int32_t n0, int64_t nat, int64_t k,
                          uint8_t init, int parent_in_d)
@@ -876,6 +959,8 @@ static int spawn_attempt(or_run *r, const uint64_t *key, uint64_t h, int32_t n0,
     double pgen = 0.0, hij = 0.0;
     if (!or_exgen(s, r->q.excit_gen, r->q.p_single, key, w, child, &pgen, &hij)) return OR_OK;
     if (hij == 0.0) return OR_OK;
+    /* CCMC: amplitudes exist only up to the truncation level */
+    if (r->q.method == OR_CCMC && excit_level(s, child) > r->q.ccmc_truncation) return OR_OK;
     if (parent_in_d && dspace_find(r, child) >= 0) return OR_OK;
     double ah = fabs(hij);
     if (r->q.tau_search) {
@@ -967,6 +1052,169 @@ static int spawn_attempt_pair(or_run *r, const uint64_t *key, uint64_t h, int32_
     int sn = n0 > 0 ? 1 : -1;
     push_spawn(r, child, (int32_t)(-(sh * sn) * kk), 1);
     return OR_OK;
+}
+
+/* ---- CCMC: composite clusters (Sec. 2.2: the cluster expansion of t~_j is
+ * sampled and each sampled term propagated on its own) ----
+ * With T = sum_i N_i a_i over the excitors of the list (not the reference)
+ * and t_HF = N_0, Psi = N_0 exp(T / N_0) D_0 expands into terms
+ * N_0^(1-s) N_{e_1} ... N_{e_s} a_{e_1} ... a_{e_s} D_0 over sets of s distinct
+ * excitors (a repeated excitor gives zero). The terms with s = 0 (D_0) and
+ * s = 1 (each excitor on its own determinant) are the list entries
+ * themselves and propagate exactly as FCIQMC parents do. Terms with s >= 2
+ * are sampled: n_c = ceil(N_ex 2^-b) selections per iteration, N_ex the sum
+ * of |N_i| over the excitors. Selection c draws its size s in [2, s_max]
+ * with p(s) = 2^-(s-1) (s < s_max) and p(s_max) = 2^-(s_max-2), s_max = the
+ * truncation level + 2 (a larger cluster is beyond the reach of H from any
+ * amplitude kept), then s excitors independently with probability
+ * |N_i| / N_ex each. A set of s distinct excitors is drawn with probability
+ * p(s) s! prod |N_i| / N_ex^s, so the term's weight per selection is
+ *   w = sgn * N_0 (N_ex / N_0)^s / (p(s) s! n_c)  (units of 2^-b walkers),
+ * sgn the sign of N_0^(1-s) prod N_i times the sign of the collapsed
+ * product a_{e_1} ... a_{e_s} D_0 = +-D. The term then makes one spawning
+ * attempt from D (amplitude dtau |H_jD| w / p_gen, rounded as a parent's) onto
+ * a D_j within the truncation level, and, when D itself is within it, the
+ * death step of the term, -dtau (K_DD - S) w stochastically rounded, as a
+ * spawn onto D. Both are unbiased, so the expected change of each amplitude
+ * is -dtau <D_i|K - S|Psi>, eq. (ccmc).
+ * Selection order: the excitors ordered by (64-bit hash of the key, key), a
+ * cumulative sum of |N_i| in that order, and a 64-bit uniform integer r
+ * mapped to floor(r N_ex / 2^64) within it. Random numbers: Philox under the
+ * key (seed_lo, seed_hi ^ replica_id ^ 2^31), counter (tag, draw, t, c). */
+static void draw_cluster(const or_run *r, uint32_t tag, uint32_t k, uint32_t t, uint64_t c, uint32_t out[4])
+{
+    uint32_t ctr[4] = {(tag << 28) | k, t, (uint32_t)c, (uint32_t)(c >> 32)};
+    uint32_t key[2] = {r->rkey[0], r->rkey[1] ^ 0x80000000u};
+    or_philox4x32_10(ctr, key, out);
+}
+
+static struct { const or_run *r; const uint64_t *h; } g_hord;
+static int hash_order_cmp(const void *a, const void *b)
+{
+    int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+    uint64_t hi = g_hord.h[i], hj = g_hord.h[j];
+    if (hi != hj) return hi < hj ? -1 : 1;
+    return key_cmp(g_hord.r->keys + (size_t)i * g_hord.r->W, g_hord.r->keys + (size_t)j * g_hord.r->W, g_hord.r->W);
+}
+
+/* one spawning attempt of a sampled cluster (collapsed determinant D,
+   weight magnitude mag and sign sw); random blocks as an attempt 0 of a
+   parent with hash c, under the cluster key */
+static int cluster_spawn(or_run *r, const uint64_t *D, uint64_t c, double mag, int sw)
+{
+    const or_sys *s = r->s;
+    uint32_t w[8], rnd[4];
+    uint32_t t = (uint32_t)r->t;
+    draw_cluster(r, TAG_SELECT, 0, t, c, w);
+    draw_cluster(r, TAG_SELECT2, 0, t, c, w + 4);
+    uint64_t child[OR_MAXW] = {0};
+    double pgen = 0.0, hij = 0.0;
+    if (!or_exgen(s, r->q.excit_gen, r->q.p_single, D, w, child, &pgen, &hij)) return OR_OK;
+    if (hij == 0.0) return OR_OK;
+    if (excit_level(s, child) > r->q.ccmc_truncation) return OR_OK;
+    double ah = fabs(hij);
+    double m = ((r->q.tau * ah) / pgen) * mag;
+    double u;
+    if (r->q.excit_gen == OR_EXGEN_HEATBATH) {
+        draw_cluster(r, TAG_SPAWN_ROUND, 0, t, c, rnd);
+        u = u53(rnd[0], rnd[1]);
+    } else {
+        u = u53(w[2], w[3]);
+    }
+    if (!(m < 0x1p31)) return OR_EOVERFLOW;
+    int64_t kk;
+    if (r->q.fixed_point_bits != 0 && m < (double)r->cu)
+        kk = (u * (double)r->cu < m) ? r->cu : 0;
+    else
+        kk = sround(m, u);
+    if (kk == 0) return OR_OK;
+    if (kk > 2147483647) return OR_EOVERFLOW;
+    int sh = hij > 0.0 ? 1 : -1;
+    push_spawn(r, child, (int32_t)(-(sh * sw) * kk), 1);
+    return OR_OK;
+}
+
+static int ccmc_composite(or_run *r, int32_t n0)
+{
+    const or_sys *s = r->s;
+    int W = r->W;
+    uint32_t t = (uint32_t)r->t;
+    int trunc = r->q.ccmc_truncation;
+    int smax = trunc + 2 < s->nel ? trunc + 2 : s->nel;
+    /* the excitors in (hash, key) order and the cumulative sum of |N_i| */
+    int64_t ne = 0;
+    int64_t *ord = (int64_t *)malloc(sizeof(int64_t) * (size_t)(r->n ? r->n : 1));
+    uint64_t *hh = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(r->n ? r->n : 1));
+    for (int64_t i = 0; i < r->n; ++i) {
+        hh[i] = or_hash64(r->keys + (size_t)i * W, W);
+        if (!is_reference(r, r->keys + (size_t)i * W)) ord[ne++] = i;
+    }
+    g_hord.r = r;
+    g_hord.h = hh;
+    qsort(ord, (size_t)ne, sizeof(int64_t), hash_order_cmp);
+    int64_t *cum = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ne + 1));
+    cum[0] = 0;
+    for (int64_t x = 0; x < ne; ++x) {
+        int32_t p = r->pops[ord[x]];
+        cum[x + 1] = cum[x] + (p < 0 ? -(int64_t)p : p);
+    }
+    int64_t nex = cum[ne];
+    int b = r->q.fixed_point_bits;
+    int64_t nc = b ? (nex + ((int64_t)1 << b) - 1) >> b : nex;
+    int status = OR_OK;
+    double an0 = (double)(n0 < 0 ? -(int64_t)n0 : (int64_t)n0);
+    for (int64_t c = 0; c < nc && smax >= 2 && status == OR_OK; ++c) {
+        uint32_t rr[4];
+        draw_cluster(r, TAG_CLUSTER, 0, t, (uint64_t)c, rr);
+        double u = u53(rr[0], rr[1]);
+        int sz = 2;
+        while (sz < smax && u >= 1.0 - ldexp(1.0, -(sz - 1))) ++sz;
+        double ps = sz < smax ? ldexp(1.0, -(sz - 1)) : ldexp(1.0, -(smax - 2));
+        int64_t pick_ix[8];
+        uint64_t ex[8 * OR_MAXW];
+        int sgn = 1, dup = 0;
+        for (int j = 0; j < sz; ++j) {
+            draw_cluster(r, TAG_CLUSTER, (uint32_t)(1 + j), t, (uint64_t)c, rr);
+            uint64_t r64 = ((uint64_t)rr[0] << 32) | rr[1];
+            int64_t target = (int64_t)(((unsigned __int128)r64 * (uint64_t)nex) >> 64);
+            int64_t lo = 0, hi = ne; /* last x with cum[x] <= target */
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) / 2;
+                if (cum[mid] <= target) lo = mid; else hi = mid;
+            }
+            pick_ix[j] = ord[lo];
+            for (int q = 0; q < j; ++q) dup |= pick_ix[q] == pick_ix[j];
+            memcpy(ex + (size_t)j * W, r->keys + (size_t)pick_ix[j] * W, sizeof(uint64_t) * W);
+            if (r->pops[pick_ix[j]] < 0) sgn = -sgn;
+        }
+        if (dup) continue;
+        uint64_t D[OR_MAXW];
+        int cs = or_cluster_collapse(s, ex, sz, D);
+        if (cs == 0) continue;
+        int lev = excit_level(s, D);
+        if (lev > trunc + 2) continue;
+        sgn *= cs;
+        if ((sz % 2 == 0) && n0 < 0) sgn = -sgn; /* sign of N_0^(1-s) */
+        double x = (double)nex / an0;
+        double f = x;
+        for (int j = 1; j < sz; ++j) f = f * x;
+        double fact = 1.0;
+        for (int j = 2; j <= sz; ++j) fact *= (double)j;
+        double mag = (an0 * f) / ((ps * fact) * (double)nc);
+        status = cluster_spawn(r, D, (uint64_t)c, mag, sgn);
+        if (status != OR_OK || lev > trunc) continue;
+        /* the death step of the term, as a spawn onto D */
+        double md = (r->q.tau * ((or_diag(s, D) - s->H00) - r->S)) * mag;
+        draw_cluster(r, TAG_DEATH, 0, t, (uint64_t)c, rr);
+        double ud = u53(rr[0], rr[1]);
+        if (!(fabs(md) < 0x1p31)) { status = OR_EOVERFLOW; break; }
+        int64_t k = sround(fabs(md), ud);
+        if (k == 0) continue;
+        int dsg = md >= 0.0 ? -sgn : sgn;
+        push_spawn(r, D, (int32_t)(dsg * k), 1);
+    }
+    free(ord); free(hh); free(cum);
+    return status;
 }
 
 typedef struct { const uint64_t *keys; int W; } sort_ctx_t;
@@ -1177,6 +1425,13 @@ static int step_once(or_run *r)
     uint32_t t = (uint32_t)r->t;
     int64_t n = r->n;
     int64_t flips = 0;
+    /* CCMC: the cluster weights divide by t_HF = N_0 */
+    int32_t ccmc_n0 = 0;
+    if (r->q.method == OR_CCMC) {
+        for (int64_t i = 0; i < n; ++i)
+            if (is_reference(r, r->keys + (size_t)i * W)) ccmc_n0 = r->pops[i];
+        if (ccmc_n0 == 0) return OR_ENOREF;
+    }
     /* 1. spawning from the start-of-iteration populations */
     r->ns = 0;
     r->kd_any = 0;
@@ -1211,6 +1466,10 @@ static int step_once(or_run *r)
             int st = spawn_attempt(r, key, h, n0, nat, k, init, pin_d);
             if (st) return st;
         }
+    }
+    if (r->q.method == OR_CCMC) {
+        int st = ccmc_composite(r, ccmc_n0);
+        if (st) return st;
     }
     /* 2. death/cloning (Sec. 2.4 "death"; shift as diagonal offset, Sec. 2.1),
      *    3. deterministic projection for D entries; both from start-of-iteration values */
@@ -1410,6 +1669,12 @@ int or_run_import(or_run *r, const uint64_t *keys, const int32_t *pops, int64_t 
     qsort(ix, (size_t)n, sizeof(int64_t), idx_cmp);
     for (int64_t i = 1; i < n; ++i)
         if (key_cmp(keys + (size_t)ix[i] * W, keys + (size_t)ix[i - 1] * W, W) == 0) {
+            free(ix);
+            return OR_EINVAL;
+        }
+    /* CCMC: no amplitude beyond the truncation level */
+    for (int64_t i = 0; i < n && r->q.method == OR_CCMC; ++i)
+        if (excit_level(r->s, keys + (size_t)i * W) > r->q.ccmc_truncation) {
             free(ix);
             return OR_EINVAL;
         }

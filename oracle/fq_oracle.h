@@ -37,7 +37,7 @@ extern "C" {
 
 enum { OR_HUBBARD = 1, OR_UEG = 2, OR_MOLECULAR = 3 };
 enum { OR_EXGEN_HUB = 1, OR_EXGEN_UEG = 2, OR_EXGEN_HEATBATH = 3 };
-enum { OR_OK = 0, OR_EINVAL = -1, OR_EOVERFLOW = -3 };
+enum { OR_OK = 0, OR_EINVAL = -1, OR_EOVERFLOW = -3, OR_ENOREF = -7 };
 
 typedef struct or_sys or_sys;
 typedef struct or_run or_run;
@@ -61,13 +61,16 @@ typedef struct {
     int32_t ss_start_iteration;
     int32_t ss_shared;          /* 1: D chosen jointly with other runs (or_runs_select_shared) */
     int32_t tau_search;         /* 1: lower tau on the fly (see step_once) */
-    int32_t method;             /* OR_FCIQMC, OR_DMQMC or OR_IPDMQMC */
+    int32_t method;             /* OR_FCIQMC, OR_DMQMC, OR_IPDMQMC or OR_CCMC */
+    int32_t ccmc_truncation;    /* CCMC: highest excitation level of an excitor (2: CCSD, ...) */
 } or_qmc;
 
-/* Methods (Sec. 2.1 FCIQMC; Sec. 2.3 DMQMC and interaction-picture DMQMC).
- * The density-matrix methods sample pairs (D_i, D_j): a key of 2W words, the
- * bra's W words first, then the ket's. */
-enum { OR_FCIQMC = 0, OR_DMQMC = 1, OR_IPDMQMC = 2 };
+/* Methods (Sec. 2.1 FCIQMC; Sec. 2.2 CCMC; Sec. 2.3 DMQMC and
+ * interaction-picture DMQMC). The density-matrix methods sample pairs
+ * (D_i, D_j): a key of 2W words, the bra's W words first, then the ket's.
+ * CCMC samples excitor amplitudes on the determinants D_i = a_i D_0 up to the
+ * truncation level (the reference's entry holds t_HF = N_0). */
+enum { OR_FCIQMC = 0, OR_DMQMC = 1, OR_IPDMQMC = 2, OR_CCMC = 3 };
 
 /* estimators of the last completed iteration */
 typedef struct {
@@ -77,6 +80,9 @@ typedef struct {
     int32_t vary_shift, status;
     double shift, proj_numerator, proj_energy, e_ref;
     int64_t num_limbs[4];
+    /* CCMC: sum over pairs of singles a < b of H_0,ab sgn(a_a a_b D_0) N_a N_b
+       (units 2^-2b, exact limbs at 2^-64); proj_energy adds it over N_0^2 */
+    int64_t pair_limbs[4];
     double tau;             /* time step in force for the next iteration */
     double spawn_ratio_max; /* largest |H_ji| / p_gen of any attempt so far (tau search only) */
 } or_estimators;
@@ -120,6 +126,10 @@ void or_run_spawns(const or_run *r, uint64_t *keys, int32_t *amps, uint8_t *init
 int64_t or_run_detspace(const or_run *r, uint64_t *keys);
 /* last deterministic projection y = K_DD n_D (FP64, fixed order), D order */
 void or_run_last_projection(const or_run *r, double *y);
+/* CCMC: a_{e_1} ... a_{e_n} D_0 = sign D for the excitors of the n keys ex
+   (n x W words; a_e D_0 = +D_e); returns sign (+1/-1) and fills out, or 0
+   when the product vanishes */
+int or_cluster_collapse(const or_sys *s, const uint64_t *ex, int n, uint64_t *out);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libfq_oracle.so")
 
 HUBBARD, UEG, MOLECULAR = 1, 2, 3
 EXGEN_HUB, EXGEN_UEG, EXGEN_HEATBATH = 1, 2, 3
-FCIQMC, DMQMC, IPDMQMC = 0, 1, 2
+FCIQMC, DMQMC, IPDMQMC, CCMC = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -40,7 +40,7 @@ class Qmc(C.Structure):
                 ("initiator_threshold", C.c_double), ("fixed_point_bits", C.c_int32),
                 ("spawn_cutoff", C.c_double), ("ss_size", C.c_int32),
                 ("ss_start_iteration", C.c_int32), ("ss_shared", C.c_int32), ("tau_search", C.c_int32),
-                ("method", C.c_int32)]
+                ("method", C.c_int32), ("ccmc_truncation", C.c_int32)]
 
 
 class Estimators(C.Structure):
@@ -52,11 +52,13 @@ class Estimators(C.Structure):
                 ("vary_shift", C.c_int32), ("status", C.c_int32),
                 ("shift", C.c_double), ("proj_numerator", C.c_double),
                 ("proj_energy", C.c_double), ("e_ref", C.c_double),
-                ("num_limbs", C.c_int64 * 4), ("tau", C.c_double), ("spawn_ratio_max", C.c_double)]
+                ("num_limbs", C.c_int64 * 4), ("pair_limbs", C.c_int64 * 4), ("tau", C.c_double),
+                ("spawn_ratio_max", C.c_double)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "num_limbs"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("num_limbs", "pair_limbs")}
         d["num_limbs"] = list(self.num_limbs)
+        d["pair_limbs"] = list(self.pair_limbs)
         return d
 
 
@@ -115,6 +117,8 @@ def lib():
         L.or_run_detspace.argtypes = [P, C.c_void_p]
         L.or_run_detspace.restype = C.c_int64
         L.or_run_last_projection.argtypes = [P, f64p]
+        L.or_cluster_collapse.argtypes = [P, u64p, C.c_int, u64p]
+        L.or_cluster_collapse.restype = C.c_int
         _lib = L
     return _lib
 
@@ -180,6 +184,14 @@ class System:
     def diag(self, key):
         return float(lib().or_diag(self.ptr, np.asarray(key, np.uint64)))
 
+    def cluster_collapse(self, excitors):
+        """a_{e_1} ... a_{e_n} D_0 = sign D (CCMC excitors, a_e D_0 = +D_e):
+        (sign, D), sign 0 when the product vanishes"""
+        ex = np.ascontiguousarray(np.asarray(excitors, np.uint64).reshape(-1))
+        out = np.zeros(self.W, np.uint64)
+        sg = int(lib().or_cluster_collapse(self.ptr, ex, len(ex) // self.W, out))
+        return sg, out
+
     def exgen(self, exgen, key, words, p_single=0.1):
         child = np.zeros(self.W, np.uint64)
         pg, h = C.c_double(), C.c_double()
@@ -196,7 +208,8 @@ def make_qmc(**kw) -> Qmc:
     d = dict(tau=0.01, seed=7, replica_id=0, init_pop=500.0, target_population=1e4,
              shift_period=10, shift_damping=0.05, initial_shift=0.0, excit_gen=EXGEN_HUB,
              p_single=0.1, initiator=0, initiator_threshold=3.0, fixed_point_bits=0,
-             spawn_cutoff=0.0, ss_size=0, ss_start_iteration=0, ss_shared=0, tau_search=0, method=0)
+             spawn_cutoff=0.0, ss_size=0, ss_start_iteration=0, ss_shared=0, tau_search=0, method=0,
+             ccmc_truncation=0)
     d.update(kw)
     return Qmc(**d)
 
@@ -229,7 +242,7 @@ class Run:
     @property
     def W(self):
         """key words: the system's, doubled for the density-matrix methods"""
-        return self.sys.W * (1 if self.qmc.method == FCIQMC else 2)
+        return self.sys.W * (2 if self.qmc.method in (DMQMC, IPDMQMC) else 1)
 
     def export(self):
         n = int(lib().or_run_size(self.ptr))
