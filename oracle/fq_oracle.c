@@ -815,8 +815,10 @@ static void compute_estimators(or_run *r)
             memcpy(ex + r->W, r->keys + (size_t)singles[y] * r->W, sizeof(uint64_t) * r->W);
             int sg = or_cluster_collapse(r->s, ex, 2, D);
             if (sg == 0) continue;
+            /* H_0,ab (N_a N_b): the product of the pair first, so the term is
+               the same whichever single comes first */
             double h = or_hij(r->s, r->s->ref, D);
-            double term = (h * (double)r->pops[singles[x]]) * (double)r->pops[singles[y]];
+            double term = h * ((double)r->pops[singles[x]] * (double)r->pops[singles[y]]);
             acc_term(plimbs, sg > 0 ? term : -term);
         }
     free(singles);
