@@ -308,7 +308,8 @@ def run_mol30(args):
         qs = [F.make_qmc(excit_gen=F.MOLECULAR, **dict(w["qmc"], target_population=tgt, init_pop=tgt / 20,
                                                        replica_id=r)) for r in range(R)]
         ss = F.SemiStoch(size=2000, start_iteration=start, precision=prec, check_period=10, shared=1 if R > 1 else 0)
-        ctx = F.Context([sysd] * R, qs, ss, main_capacity=args.main_capacity, spawn_capacity=args.spawn_capacity)
+        ctx = F.Context([sysd] * R, qs, ss, main_capacity=args.main_capacity, spawn_capacity=args.spawn_capacity,
+                        graph=True)
         t0 = time.perf_counter()
         done = 0
         while done < equil:
@@ -318,15 +319,20 @@ def run_mol30(args):
             nw = sum(ctx.estimators(r)["n_walkers_units"] for r in range(R)) / 256.0
             log(f"{name} warmup {done}: N_w {nw:.4g}, {time.perf_counter() - t0:.1f} s")
         e0 = [ctx.estimators(r) for r in range(R)]
-        ctx.set_timing(True)
+        # timed window under graph replay, then a kernel window of at most 200
+        # iterations with an event around every launch
+        ctx.stream.synchronize()
         t1 = time.perf_counter()
         ctx.step(args.steps)
         ctx.stream.synchronize()
         dt = time.perf_counter() - t1
+        hists = [ctx.history(r) for r in range(R)]
+        ctx.set_timing(True)
+        ctx.step(min(args.steps, 200))
+        ctx.stream.synchronize()
         kt, niter = ctx.kernel_times()
         it_ms = sorted(ctx.iteration_times())
         ctx.set_timing(False)
-        hists = [ctx.history(r) for r in range(R)]
         upd = sum((e0[r]["n_walkers_units"] + sum(h["n_walkers_units"] for h in hists[r][:-1])) / 256.0
                   for r in range(R))
         errs = [h["ss_error"] for hh in hists for h in hh if h["ss_error"] > 0]
@@ -339,7 +345,8 @@ def run_mol30(args):
             "projection_ms_per_iteration": kt["det_project"] / max(niter, 1),
             "gather_ms_per_iteration": kt["det_gather"] / max(niter, 1),
             "fp64_check_ms_per_iteration": kt["det_check"] / max(niter, 1),
-            "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in kt.items() if v / max(niter, 1) > 0.005},
+            "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in kt.items()
+                                        if v / max(niter, 1) > 0.005 and not k.startswith("ccmc")},
             "projected_energy_window": num / den if den else None,
             "ss_error_max": max(errs) if errs else None,
             "ss_error_bound": hists[0][-1]["ss_error_bound"],
@@ -365,7 +372,8 @@ def run_mol30(args):
         "data": "synthetic",
         "config": {"workload": f"mol30_semistochastic_D2000_R{R}_target1e7", "replicas": R,
                    "deterministic_space": 2000, "shared_space": R > 1, "selection_iteration": start,
-                   "timed_iterations": f"{equil + 1}..{equil + args.steps}",
+                   "timed_iterations": f"{equil + 1}..{equil + args.steps}", "graph_replay": True,
+                   "kernel_timing_iterations": f"{equil + args.steps + 1}..{equil + args.steps + min(args.steps, 200)}",
                    "parallelism": "single GPU"},
         "fp64": fp,
         "split_bf16x3": split,
@@ -522,7 +530,9 @@ def run_single(args):
         "determinant_updates_per_s": dets / dt,
         "spawns_per_s": spawned / dt,
         "stage_ms_per_iteration": {k: v / max(niter, 1) for k, v in stages.items()},
-        "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in ktimes.items() if v > 0},
+        # (the two CCMC slots time only the gap between two events on this path)
+        "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in ktimes.items()
+                                    if v > 0 and not k.startswith("ccmc")},
         "walkers_start": e_start["n_walkers_units"] / scale,
         "walkers_end": hist[-1]["n_walkers_units"] / scale,
         "determinants_start": e_start["n_occupied"],

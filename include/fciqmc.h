@@ -53,6 +53,7 @@ typedef int32_t fq_status;
 #define FQ_EOVERFLOW (-3)
 #define FQ_EHIP (-4)
 #define FQ_ESTATE (-5)
+#define FQ_ENOREF (-6) /* CCMC: the reference determinant holds no walkers */
 
 /* model systems (paper Sec. 4.3: uniform electron gas, Hubbard) and molecular
  * integrals (Sec. 3.1 and the tutorial appendix: h_pq and (pq|rs)) */
@@ -110,8 +111,10 @@ typedef struct {
                                    attempt so far, 1 / (max K_ii - S) over the entries of the
                                    last death step), each bound applying when positive.
                                    Export/import keep tau and the running maximum. */
-    int32_t method;             /* FQ_FCIQMC, FQ_DMQMC or FQ_IPDMQMC (the same for every
-                                   instance of a context) */
+    int32_t method;             /* FQ_FCIQMC, FQ_DMQMC, FQ_IPDMQMC or FQ_CCMC (the same for
+                                   every instance of a context) */
+    int32_t ccmc_truncation;    /* FQ_CCMC: highest excitation level of an excitor, 1..6
+                                   (1: CCS, 2: CCSD, ...); ignored otherwise */
 } fq_qmc;
 
 /* Methods (Sec. 2.1; Sec. 2.3, eqs. dmqmc and ipdmqmc; Sec. 2.4). The
@@ -133,6 +136,28 @@ typedef struct {
 #define FQ_FCIQMC 0
 #define FQ_DMQMC 1
 #define FQ_IPDMQMC 2
+
+/* Coupled cluster Monte Carlo (Sec. 2.2, eq. ccmc; Sec. 2.4). The list holds
+ * excitor amplitudes N_i on D_i = a_i D_0 up to the truncation level
+ * (a_i D_0 = +D_i) and t_HF = N_0 on D_0; Psi = N_0 exp(T / N_0) D_0 with
+ * T = sum_i N_i a_i. Each iteration: every entry spawns and dies as an
+ * FCIQMC parent (spawns beyond the truncation level are not made); then
+ * n_c = ceil(N_ex 2^-b) composite clusters are sampled, N_ex = sum |N_i|
+ * over the excitors: size s in [2, truncation + 2] with p(s) = 2^-(s-1) (the
+ * largest size taking the remainder), s excitors with probability
+ * |N_i| / N_ex each in list order (64-bit hash, then key), the product
+ * a_{e_1}...a_{e_s} D_0 = sgn D (zero when two excitors share a hole or a
+ * particle); the term of weight sgn N_0 (N_ex / |N_0|)^s / (p(s) s! n_c)
+ * makes one spawning attempt from D and, when D is within the truncation
+ * level, adds its death step -dtau (K_DD - S) w as a spawn onto D. Spawns
+ * and annihilation are FCIQMC's. Random numbers of cluster c: Philox under
+ * (seed_lo, seed_hi ^ replica_id ^ 2^31), counter (tag, draw, t, c). The
+ * projected energy is sum_j H_0j t~_j / N_0 where t~_j = <D_j|Psi> holds, for
+ * a double, the products (1 / N_0) sgn N_a N_b of pairs of singles
+ * (fq_estimators_t.pair_limbs). One instance per context; not with the
+ * initiator rule, a deterministic space or tau_search (FQ_EINVAL). A
+ * step whose reference holds no walkers fails with FQ_ENOREF. */
+#define FQ_CCMC 3
 
 /* Semi-stochastic block (tutorial appendix, semi_stoch = {size,
  * start_iteration, space = "high"}): the size most highly weighted
@@ -179,6 +204,11 @@ typedef struct {
     double tau;               /* time step of the next iteration (tau_search may lower it) */
     double spawn_ratio_max;   /* tau_search: largest |H_ji| / p_gen of any attempt so far, as of
                                  the end of the fq_step call (0 without tau_search) */
+    int64_t pair_limbs[4];    /* CCMC: exact fixed-point (2^-64) sum over pairs of singles a < b
+                                 of H_0,ab sgn(a_a a_b D_0) N_a N_b (units^2); proj_numerator and
+                                 proj_energy add it divided by N_0. Zero otherwise. */
+    int64_t n_cluster_spawns; /* CCMC: spawn records written by the sampled composite clusters
+                                 this iteration (their spawns and death steps); part of n_spawned */
 } fq_estimators_t;
 
 typedef struct fq_ctx fq_ctx;

@@ -1469,10 +1469,12 @@ static int step_once(or_run *r)
             if (st) return st;
         }
     }
+    int64_t n_cluster = r->ns;
     if (r->q.method == OR_CCMC) {
         int st = ccmc_composite(r, ccmc_n0);
         if (st) return st;
     }
+    n_cluster = r->ns - n_cluster;
     /* 2. death/cloning (Sec. 2.4 "death"; shift as diagonal offset, Sec. 2.1),
      *    3. deterministic projection for D entries; both from start-of-iteration values */
     int64_t *newpop = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
@@ -1594,6 +1596,7 @@ static int step_once(or_run *r)
     /* 5. estimators on the new list */
     compute_estimators(r);
     r->est.n_spawned = ns;
+    r->est.n_cluster_spawns = n_cluster;
     r->est.n_sign_flips = flips;
     r->est.n_rejected_units = rejected;
     r->est.n_spawn_events = nu;

@@ -85,6 +85,7 @@ typedef struct {
     int64_t pair_limbs[4];
     double tau;             /* time step in force for the next iteration */
     double spawn_ratio_max; /* largest |H_ji| / p_gen of any attempt so far (tau search only) */
+    int64_t n_cluster_spawns; /* CCMC: spawn records of the sampled composite clusters, last iteration */
 } or_estimators;
 
 /* Philox4x32-10, Salmon et al. (SC'11) */

@@ -53,7 +53,7 @@ class Estimators(C.Structure):
                 ("shift", C.c_double), ("proj_numerator", C.c_double),
                 ("proj_energy", C.c_double), ("e_ref", C.c_double),
                 ("num_limbs", C.c_int64 * 4), ("pair_limbs", C.c_int64 * 4), ("tau", C.c_double),
-                ("spawn_ratio_max", C.c_double)]
+                ("spawn_ratio_max", C.c_double), ("n_cluster_spawns", C.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("num_limbs", "pair_limbs")}

@@ -7,8 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfqgpu.so")
-SOURCES = ["fq_kernels.hip", "fq_host.cpp", "analysis/fq_reblock.cpp"]
-HEADERS = ["fq_device.h", "fq_kernels.h"]
+SOURCES = ["fq_kernels.hip", "fq_ccmc.hip", "fq_host.cpp", "analysis/fq_reblock.cpp"]
+HEADERS = ["fq_device.h", "fq_kernels.h", "fq_scan.h"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # every product and sum rounds as written: no FMA contraction, no fast math

@@ -47,7 +47,7 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     return U4{c0, c1, c2, c3};
 }
 
-enum : uint32_t { TAG_SELECT = 0, TAG_SELECT2 = 1, TAG_SPAWN_ROUND = 2, TAG_DEATH = 3, TAG_SEMISTOCH = 4 };
+enum : uint32_t { TAG_SELECT = 0, TAG_SELECT2 = 1, TAG_SPAWN_ROUND = 2, TAG_DEATH = 3, TAG_SEMISTOCH = 4, TAG_CLUSTER = 5 };
 
 __device__ __forceinline__ U4 draw(uint32_t tag, uint32_t attempt, uint32_t t, uint64_t h, uint32_t k0,
                                    uint32_t k1)

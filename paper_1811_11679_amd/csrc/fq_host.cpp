@@ -235,9 +235,21 @@ struct Layout {
     size_t u[4];
     size_t ds[14];
     size_t dkeys;
+    size_t cc_cum, st_ccmc, single_key, single_pop;  // CCMC (empty otherwise)
 };
 
 int64_t tiles_of(int64_t n, int64_t tile) { return (n + tile - 1) / tile + 1; }
+
+// the density-matrix methods key pairs of determinants
+bool dm_method(int m) { return m == FQ_DMQMC || m == FQ_IPDMQMC; }
+
+// CCMC: room for every single excitation of the reference (the queue of
+// singles of the projected energy); 0 for the other methods
+int64_t single_capacity(const HostSys &s, int method)
+{
+    if (method != FQ_CCMC) return 0;
+    return (int64_t)s.na * (s.n_spatial - s.na) + (int64_t)s.nb * (s.n_spatial - s.nb) + 1;
+}
 
 // two descriptions of the same Hamiltonian (integral arrays compared by value)
 bool same_system(const fq_system &a, const fq_system &b)
@@ -258,7 +270,7 @@ int64_t span_capacity(int64_t mcap, int64_t scap, int W)
     return tiles_of(std::max(mcap * 16, scap * 4), SPAN_MIN);
 }
 
-Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D, int nk)
+Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int D, int nk, int64_t singles)
 {
     Layout L;
     size_t o = 0;
@@ -322,6 +334,11 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.ds[11] = take(2 * (size_t)R * np); // c lo bf16
     L.ds[12] = take(8 * nd);             // FP64 reference y
     L.dkeys = take(8 * nd * W);          // keys in D order
+    const bool cc = singles > 0;
+    L.cc_cum = take(cc ? 8 * (size_t)(mcap + 1) : 0);
+    L.st_ccmc = take(cc ? 8 * (size_t)tiles_of(mcap, 2048) : 0);
+    L.single_key = take(8 * (size_t)singles * W);
+    L.single_pop = take(4 * (size_t)singles);
     L.total = o;
     return L;
 }
@@ -330,7 +347,7 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
 
 struct fq_ctx {
     int R = 0, W = 0, kind = 0, rb = 0;
-    int method = FQ_FCIQMC;  // FQ_FCIQMC, FQ_DMQMC or FQ_IPDMQMC (one per context)
+    int method = FQ_FCIQMC;  // FQ_FCIQMC, FQ_DMQMC, FQ_IPDMQMC or FQ_CCMC (one per context)
     int lkind = 0;           // kernel kind: the system kind, | K_PAIR for the density-matrix methods
     uint64_t hmask = ~0ull;  // hash bits that enter a sort key
     hipStream_t stream = nullptr;
@@ -423,12 +440,20 @@ void estimators_from_acc(const fq_ctx *c, int r, const EstAcc &a, fq_estimators_
     e.spawn_sum = a.spawn_sum;
     e.rejected_sum = a.rej_sum;
     for (int k = 0; k < 4; ++k) e.num_limbs[k] = a.limbs[k];
+    for (int k = 0; k < 4; ++k) e.pair_limbs[k] = a.pair[k];
+    e.n_cluster_spawns = a.ccmc_rec;
     e.ss_error = a.ss_err;
     if (c->has_ss && c->ss.precision == FQ_SS_SPLIT_BF16)
         e.ss_error_bound = 3.0 * 0x1p-16 + 3.0 * (double)c->D * 0x1p-24;
     __int128 tot = 0;
     for (int k = 0; k < 4; ++k) tot += (__int128)a.limbs[k] * ((__int128)1 << (32 * k));
-    const double num = (double)tot * 0x1p-64;
+    double num = (double)tot * 0x1p-64;
+    if (c->method == FQ_CCMC && a.n0 != 0) {
+        // t~_j of the doubles holds the products of pairs of singles over N_0
+        __int128 pt = 0;
+        for (int k = 0; k < 4; ++k) pt += (__int128)a.pair[k] * ((__int128)1 << (32 * k));
+        num = num + ((double)pt * 0x1p-64) / (double)a.n0;
+    }
     e.proj_numerator = num * std::ldexp(1.0, -c->qmc[r].fixed_point_bits);
     e.proj_energy = a.n0 != 0 ? num / (double)a.n0 : NAN;
     e.e_ref = c->h00v[r];
@@ -529,7 +554,12 @@ fq_status upload_main(fq_ctx *c, const std::vector<HostEntry> &e)
         std::memset(ctl0.tickets, 0, sizeof(ctl0.tickets));
         HIPCHK(c, h2d(c->stream, c->w.ctl, &ctl0, sizeof(Ctl)));
     }
-    HIPCHK(c, fill0(c->stream, c->ws + c->L.st_scan, c->L.st_sort - c->L.st_scan));
+    // every look-back status array: an import may set the iteration counter
+    // back, and a rollback re-runs the failed iteration, so words of an
+    // earlier pass could carry the epoch the next iterations use
+    HIPCHK(c, fill0(c->stream, c->ws + c->L.st_scan, c->L.part_red - c->L.st_scan));
+    if (c->L.single_key > c->L.st_ccmc)
+        HIPCHK(c, fill0(c->stream, c->ws + c->L.st_ccmc, c->L.single_key - c->L.st_ccmc));
     HIPCHK(c, enqueue_setup(1, c->lkind, c->w, nullptr, 0, m, n, nullptr, nullptr, c->stream));
     Ctl ctl;
     HIPCHK(c, d2h(c->stream, &ctl, c->w.ctl, sizeof(Ctl)));
@@ -562,11 +592,20 @@ fq_status host_estimators(fq_ctx *c)
             if ((int)rep != r) continue;
             a.nw += x.pop < 0 ? -(long long)x.pop : x.pop;
             a.nocc += 1;
-            if (c->method != FQ_FCIQMC) {
+            if (dm_method(c->method)) {
                 if (x.key[0] == x.key[1]) a.n0 += x.pop;  // the trace
             } else if (key_cmp_host(x.key, c->sys[r].ref, c->W) == 0) {
                 a.n0 = x.pop;
             }
+        }
+        if (c->method == FQ_CCMC) {
+            // the singles-pair part of the projected energy, on the device
+            HIPCHK(c, fill0(c->stream, &c->w.acc[0], sizeof(EstAcc)));
+            HIPCHK(c, fill0(c->stream, (char *)c->w.ctl + offsetof(Ctl, n_single), sizeof(uint32_t)));
+            HIPCHK(c, enqueue_ccmc(2, c->lkind, c->w, c->grids, c->stream));
+            EstAcc dv;
+            HIPCHK(c, d2h(c->stream, &dv, &c->w.acc[0], sizeof(EstAcc)));
+            for (int k = 0; k < 4; ++k) a.pair[k] = dv.pair[k];
         }
         estimators_from_acc(c, r, a, c->last[r]);
         c->last[r].shift = c->shift[r];
@@ -722,19 +761,19 @@ size_t fq_workspace_bytes(const fq_system *sys, const fq_qmc *qmc, const fq_semi
                           int64_t main_capacity, int64_t spawn_capacity)
 {
     if (!sys || n_instances <= 0 || main_capacity <= 0 || spawn_capacity <= 0) return 0;
-    int64_t tables = 0;
+    int64_t tables = 0, singles = 0;
     int W = 1;
     for (int r = 0; r < n_instances; ++r) {
         HostSys s;
         if (!build_system(sys[r], s).empty()) return 0;
         tables += (int64_t)table_bytes(s);
-        // the density-matrix methods key pairs of determinants
-        const int pair = qmc && qmc[r].method != FQ_FCIQMC ? 2 : 1;
+        const int pair = qmc && dm_method(qmc[r].method) ? 2 : 1;
         W = std::max(W, pair * round_w(s.n_so));
+        singles = std::max(singles, single_capacity(s, qmc ? qmc[r].method : FQ_FCIQMC));
     }
     const int D = ss ? std::max(0, ss[0].size) : 0;
     const int nk = ss && ss[0].shared ? 1 : n_instances;
-    return make_layout(n_instances, W, main_capacity, spawn_capacity, tables, D, nk).total + 256;
+    return make_layout(n_instances, W, main_capacity, spawn_capacity, tables, D, nk, singles).total + 256;
 }
 
 }  // extern "C"
@@ -769,12 +808,18 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
         if (!m.empty()) { delete c; return FQ_EINVAL; }
         // density-matrix methods: a key holds a pair of one-word determinants
         const int Wd = round_w(c->sys[r].n_so);
-        const int W = qmc[r].method == FQ_FCIQMC ? Wd : 2 * Wd;
+        const int W = dm_method(qmc[r].method) ? 2 * Wd : Wd;
         if (r == 0) { c->W = W; c->kind = sys[r].kind; c->method = qmc[0].method; }
         if (W != c->W || sys[r].kind != c->kind || qmc[r].method != c->method) { delete c; return FQ_EINVAL; }
-        if (qmc[r].method < FQ_FCIQMC || qmc[r].method > FQ_IPDMQMC) { delete c; return FQ_EINVAL; }
-        if (qmc[r].method != FQ_FCIQMC &&
+        if (qmc[r].method < FQ_FCIQMC || qmc[r].method > FQ_CCMC) { delete c; return FQ_EINVAL; }
+        if (dm_method(qmc[r].method) &&
             (Wd != 1 || qmc[r].initiator || qmc[r].tau_search || (ss && ss[0].size > 0)))
+            { delete c; return FQ_EINVAL; }
+        // CCMC: one instance, excitors of level 1..6, no initiator rule,
+        // deterministic space or time-step search
+        if (qmc[r].method == FQ_CCMC &&
+            (n_instances != 1 || qmc[r].ccmc_truncation < 1 || qmc[r].ccmc_truncation > 6 || qmc[r].initiator ||
+             qmc[r].tau_search || (ss && ss[0].size > 0)))
             { delete c; return FQ_EINVAL; }
         const fq_qmc &q = qmc[r];
         const int need = c->kind == FQ_HUBBARD_REAL ? FQ_EXGEN_HUB_UNIFORM
@@ -792,8 +837,8 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
         }
         tables += (int64_t)table_bytes(c->sys[r]);
     }
-    if (c->kind == FQ_HUBBARD_REAL && c->W != (c->method == FQ_FCIQMC ? 1 : 2)) { delete c; return FQ_EINVAL; }
-    c->lkind = c->kind | (c->method == FQ_FCIQMC ? 0 : (int)K_PAIR);
+    if (c->kind == FQ_HUBBARD_REAL && c->W != (dm_method(c->method) ? 2 : 1)) { delete c; return FQ_EINVAL; }
+    c->lkind = c->kind | (dm_method(c->method) ? (int)K_PAIR : 0);
     for (int r = 1; r < c->R; ++r)
         if (qmc[r].shift_period != qmc[0].shift_period) { delete c; return FQ_EINVAL; }
     c->rb = 0;
@@ -814,7 +859,8 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
                 if (!same_system(sys[0], sys[r])) { delete c; return FQ_EINVAL; }
     }
     const int nk = c->has_ss && c->ss.shared ? 1 : c->R;
-    c->L = make_layout(c->R, c->W, main_capacity, spawn_capacity, tables, c->D, nk);
+    const int64_t singles = single_capacity(c->sys[0], c->method);
+    c->L = make_layout(c->R, c->W, main_capacity, spawn_capacity, tables, c->D, nk, singles);
     if (ws_bytes < c->L.total || ((uintptr_t)d_workspace & 255)) { delete c; return FQ_EINVAL; }
     c->ws = (char *)d_workspace;
     Work &w = c->w;
@@ -872,7 +918,13 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     w.rb = c->rb;
     w.hmask = c->hmask;
     w.tau_search = c->qmc[0].tau_search;
-    w.dm = c->method;
+    w.dm = dm_method(c->method) ? c->method : 0;
+    w.ccmc_trunc = c->method == FQ_CCMC ? c->qmc[0].ccmc_truncation : 0;
+    w.single_cap = (int32_t)singles;
+    w.ccmc_cum = (long long *)(c->ws + c->L.cc_cum);
+    w.st_ccmc = (unsigned long long *)(c->ws + c->L.st_ccmc);
+    w.single_key = (uint64_t *)(c->ws + c->L.single_key);
+    w.single_pop = (int32_t *)(c->ws + c->L.single_pop);
     w.W = c->W;
     w.hist_len = HIST_LEN;
     c->cur = 0;
@@ -948,6 +1000,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     if (he == hipSuccess) he = h2d(c->stream, (void *)w.rep, rp.data(), sizeof(RepParams) * c->R);
     if (he == hipSuccess) he = fill0(c->stream, w.ctl, sizeof(Ctl));
     if (he == hipSuccess) he = fill0(c->stream, c->ws + c->L.st_scan, c->L.main[0][0] - c->L.st_scan);
+    if (he == hipSuccess && c->L.single_key > c->L.st_ccmc) he = fill0(c->stream, c->ws + c->L.st_ccmc, c->L.single_key - c->L.st_ccmc);
     if (he == hipSuccess) he = enqueue_setup(0, c->lkind, w, (DevSys *)w.sys, c->R, c->buf[0], 0, nullptr, nullptr, c->stream);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) { delete c; return FQ_EHIP; }
@@ -986,7 +1039,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     bool one_system = true;
     for (int r = 1; r < c->R; ++r) one_system = one_system && same_system(sys[0], sys[r]);
     // the LDS-staged table paths of the spawn and diagonal kernels serve determinant keys only
-    if (c->method != FQ_FCIQMC) one_system = false;
+    if (dm_method(c->method)) one_system = false;
     if (one_system && (c->kind == FQ_UEG || c->kind == FQ_MOLECULAR)) {
         const size_t m = (size_t)c->sys[0].n_spatial;
         size_t bytes = c->kind == FQ_UEG ? 8 * (m + m * m) : 8 * (m + 2 * m * m);
@@ -1029,7 +1082,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
         HostEntry &e = init[r];
         std::memset(&e, 0, sizeof(e));
         std::memcpy(e.key, c->sys[r].ref, sizeof(e.key));
-        if (c->method != FQ_FCIQMC) e.key[1] = c->sys[r].ref[0];  // the pair (D_0, D_0)
+        if (dm_method(c->method)) e.key[1] = c->sys[r].ref[0];  // the pair (D_0, D_0)
         e.skey = host_skey(host_hash(e.key, c->W) & c->hmask, (uint32_t)r, c->rb);
         const double scale = std::ldexp(1.0, qmc[r].fixed_point_bits);
         const double u = std::floor(qmc[r].init_pop * scale + 0.5);
@@ -1147,8 +1200,11 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         // word written 2^20 iterations earlier can carry a matching epoch.
         constexpr int64_t EPOCH_PERIOD = int64_t(1) << 20;
         stop = std::min<int64_t>(stop, ((c->t + 1) / EPOCH_PERIOD + 1) * EPOCH_PERIOD - 1);
-        if ((c->t + 1) % EPOCH_PERIOD == 0)
+        if ((c->t + 1) % EPOCH_PERIOD == 0) {
             HIPCHK(c, fill0(c->stream, c->ws + c->L.st_scan, c->L.part_red - c->L.st_scan));
+            if (c->L.single_key > c->L.st_ccmc)
+                HIPCHK(c, fill0(c->stream, c->ws + c->L.st_ccmc, c->L.single_key - c->L.st_ccmc));
+        }
         const int64_t t0 = c->t;
         const int cur0 = c->cur;
         const int nb = (int)(stop - t0);
@@ -1200,7 +1256,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         if (c->timing) {
             // stage boundaries in the launch order: scan+partition, spawn, sort
             // (histogram + 8 passes), reduce (2 passes + fix-up), projection, merge
-            static const int stage_of[N_KERNEL_SLOTS] = {0, 0, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 5, 5, 5, 4, 4, 4, 4};
+            static const int stage_of[N_KERNEL_SLOTS] = {0, 0, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 3, 3, 3, 5, 5, 5, 4, 4, 4, 4, 4};
             for (int k = 0; k < nb; ++k) {
                 hipEvent_t *e = &evs[(size_t)k * NE];
                 float ms = 0.f;
@@ -1265,6 +1321,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             c->t = tf - 1;
             if (err & (ERR_OVERFLOW | ERR_ATTEMPTS)) return fail(c, FQ_EOVERFLOW, "population or spawn exceeds the fixed-point range");
             if (err & ERR_COLLISION) return fail(c, FQ_ESTATE, "more than 64 spawned determinants share one sort key (not a hash collision)");
+            if (err & ERR_NOREF) return fail(c, FQ_ENOREF, "CCMC: the reference determinant holds no walkers");
             if (err & ERR_SPAWN_CAP) return fail(c, FQ_ECAPACITY, "spawn capacity exceeded");
             return fail(c, FQ_ECAPACITY, "main list capacity exceeded");
         }
@@ -1470,6 +1527,12 @@ fq_status fq_import_walkers(fq_ctx *c, int32_t instance, const uint64_t *keys, c
         HostEntry x;
         std::memset(&x, 0, sizeof(x));
         for (int q = 0; q < c->W; ++q) x.key[q] = keys[(size_t)i * c->W + q];
+        if (c->method == FQ_CCMC) {
+            // CCMC: no amplitude beyond the truncation level
+            int d = 0;
+            for (int q = 0; q < c->W; ++q) d += __builtin_popcountll(x.key[q] ^ c->sys[instance].ref[q]);
+            if (d / 2 > c->qmc[0].ccmc_truncation) return fail(c, FQ_EINVAL, "excitor beyond the truncation level");
+        }
         x.skey = host_skey(host_hash(x.key, c->W) & c->hmask, (uint32_t)instance, c->rb);
         x.pop = pops[i];
         x.dslot = -1;

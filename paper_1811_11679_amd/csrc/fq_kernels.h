@@ -28,6 +28,7 @@ enum : uint32_t {
     ERR_ATTEMPTS = 8u,
     ERR_UNIQ_CAP = 16u,
     ERR_COLLISION = 32u,
+    ERR_NOREF = 64u,  // CCMC: the reference holds no walkers (cluster weights divide by N_0)
 };
 
 enum : int {
@@ -37,6 +38,7 @@ enum : int {
     TK_RED2 = 10,
     TK_MERGE = 11,
     TK_SPAWN = 12,
+    TK_CCMC = 13,
     TK_COUNT = 16,
 };
 
@@ -58,6 +60,12 @@ struct Ctl {
     unsigned long long kd_max;
     uint32_t tickets[TK_COUNT];
     uint32_t hist[8][256];  // radix-sort digit histogram of the spawned keys
+    // CCMC: N_0 and the sum of |N_i| over the excitors at the start of the
+    // iteration, and the singles of the new list queued for the estimator
+    long long ccmc_n0;
+    long long ccmc_nex;
+    uint32_t n_single;
+    uint32_t pad_ccmc;
 };
 
 // Per-replica estimator accumulators (exact integers).
@@ -65,8 +73,11 @@ struct EstAcc {
     long long nw, nocc, n0, nspawn, nuniq, flips, rej_units, death_sum, spawn_sum, rej_sum;
     long long limbs[4];
     long long t;
-    long long pad;
+    long long ccmc_rec;  // CCMC: records written by the composite clusters this iteration
     double ss_err;  // split projection: max relative error of the last check
+    // CCMC: exact limbs (2^-64) of sum over pairs of singles a < b of
+    // H_0,ab sgn(a_a a_b D_0) N_a N_b
+    long long pair[4];
 };
 constexpr int EST_FIELDS = 14;
 // replicas whose estimator partials a block keeps in LDS (the rest are added
@@ -197,6 +208,15 @@ struct Work {
     // method: 0 FCIQMC; density matrices on pair keys (Sec. 2.3): 1 DMQMC
     // (both ends spawn, 2 attempts per walker unit), 2 IP-DMQMC (the ket end)
     int32_t dm;
+    // CCMC (Sec. 2.2): truncation level of the excitors (0: not CCMC), the
+    // exclusive prefix of |N_i| over the current list (reference masked),
+    // its look-back status words and the queue of singles of the new list
+    int32_t ccmc_trunc;
+    int32_t single_cap;
+    long long *ccmc_cum;        // [main_cap + 1]
+    unsigned long long *st_ccmc;
+    uint64_t *single_key;       // word-major [W][single_cap]
+    int32_t *single_pop;        // [single_cap]
 };
 
 // launch geometry of the persistent kernels
@@ -209,12 +229,18 @@ struct Grids {
     // words), merge positions per thread (1, 2, 4; keys of up to two words),
     // radix-sort keys per thread (8, 12, 16)
     int spawn_i = 4, merge_i = 2, sort_i = 12;
+    int ccmc = 1024;  // blocks of the cluster-sampling kernel
 };
 
-// kernels of one iteration, in launch order (per-kernel timing slots)
-constexpr int N_KERNEL_SLOTS = 22;
+// kernels of one iteration, in launch order (per-kernel timing slots; the
+// two CCMC slots are empty for the other methods)
+constexpr int N_KERNEL_SLOTS = 24;
 // enqueue one whole iteration on a stream (ev: N_KERNEL_SLOTS + 1 events or nullptr)
 hipError_t enqueue_iteration(const Work &w, int kind, const Grids &g, hipStream_t s, hipEvent_t *ev);
+// CCMC stages: 0 = prefix of |N_i| and composite-cluster spawns (after the
+// spawn kernel), 1 = singles-pair estimator of the new list (after the
+// merge), 2 = the same for the current list (set-up)
+hipError_t enqueue_ccmc(int stage, int kind, const Work &w, const Grids &g, hipStream_t s);
 // set-up work: 0 = H_00 of every system, 1 = K_ii - H_00, attempt counts and
 // attempt offsets of the current list of n entries, 2 = K_DD of the
 // deterministic space

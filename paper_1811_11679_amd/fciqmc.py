@@ -15,11 +15,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfqgpu.so")
 
-FQ_OK, FQ_EINVAL, FQ_ECAPACITY, FQ_EOVERFLOW, FQ_EHIP, FQ_ESTATE = 0, -1, -2, -3, -4, -5
+FQ_OK, FQ_EINVAL, FQ_ECAPACITY, FQ_EOVERFLOW, FQ_EHIP, FQ_ESTATE, FQ_ENOREF = 0, -1, -2, -3, -4, -5, -6
 HUBBARD, UEG, MOLECULAR = 1, 2, 3
 EXGEN = {HUBBARD: 1, UEG: 2, MOLECULAR: 3}
 SS_FP64, SS_SPLIT_BF16 = 0, 1
-FCIQMC, DMQMC, IPDMQMC = 0, 1, 2
+FCIQMC, DMQMC, IPDMQMC, CCMC = 0, 1, 2, 3
 
 # every function the header declares
 C_API = ["fq_workspace_bytes", "fq_init_system", "fq_init_system_static", "fq_step", "fq_estimators", "fq_estimator_history",
@@ -34,9 +34,9 @@ LAUNCH_KERNELS = ["spawn", "merge", "sort", "reduce", "new_diag"]
 TILE_KNOBS = ["spawn_items", "merge_items", "sort_items"]
 TILE_VARIANTS = {"spawn_items": (2, 4, 8), "merge_items": (1, 2, 4), "sort_items": (8, 12, 16)}
 
-KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "sort_hist"] + \
+KERNEL_SLOTS = ["begin", "spawn_partition", "spawn", "ccmc_clusters", "sort_hist"] + \
     [f"sort_pass{p}" for p in range(8)] + ["reduce", "fixup", "reduce2", "det_gather", "det_project", "det_check",
-                                            "merge_partition", "merge", "new_diag", "end"]
+                                            "merge_partition", "merge", "new_diag", "ccmc_pairs", "end"]
 
 
 class FqError(RuntimeError):
@@ -58,7 +58,8 @@ class Qmc(C.Structure):
                 ("shift_period", C.c_int32), ("shift_damping", C.c_double), ("initial_shift", C.c_double),
                 ("excit_gen", C.c_int32), ("p_single", C.c_double), ("initiator", C.c_int32),
                 ("initiator_threshold", C.c_double), ("fixed_point_bits", C.c_int32),
-                ("spawn_cutoff", C.c_double), ("tau_search", C.c_int32), ("method", C.c_int32)]
+                ("spawn_cutoff", C.c_double), ("tau_search", C.c_int32), ("method", C.c_int32),
+                ("ccmc_truncation", C.c_int32)]
 
 
 class SemiStoch(C.Structure):
@@ -74,11 +75,13 @@ class Estimators(C.Structure):
                 ("vary_shift", C.c_int32), ("status", C.c_int32), ("shift", C.c_double),
                 ("proj_numerator", C.c_double), ("proj_energy", C.c_double), ("e_ref", C.c_double),
                 ("num_limbs", C.c_int64 * 4), ("ss_error", C.c_double), ("ss_error_bound", C.c_double),
-                ("tau", C.c_double), ("spawn_ratio_max", C.c_double)]
+                ("tau", C.c_double), ("spawn_ratio_max", C.c_double), ("pair_limbs", C.c_int64 * 4),
+                ("n_cluster_spawns", C.c_int64)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "num_limbs"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("num_limbs", "pair_limbs")}
         d["num_limbs"] = list(self.num_limbs)
+        d["pair_limbs"] = list(self.pair_limbs)
         return d
 
 

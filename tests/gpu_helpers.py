@@ -33,7 +33,7 @@ def oracle_qmc(sysd, q, replica=0, ss=None):
 
 
 def gpu_context(sysds, qs, ints=None, ss=None, main_capacity=1 << 21, spawn_capacity=1 << 21,
-                replicas=None):
+                replicas=None, graph=False):
     from paper_1811_11679_amd import fciqmc as F
     systems, qmcs = [], []
     for i, (sysd, q) in enumerate(zip(sysds, qs)):
@@ -51,7 +51,7 @@ def gpu_context(sysds, qs, ints=None, ss=None, main_capacity=1 << 21, spawn_capa
         sso = F.SemiStoch(size=ss["size"], start_iteration=ss["start_iteration"],
                           precision=ss.get("precision", F.SS_FP64), check_period=ss.get("check_period", 0),
                           shared=ss.get("shared", 0))
-    return F.Context(systems, qmcs, sso, main_capacity=main_capacity, spawn_capacity=spawn_capacity)
+    return F.Context(systems, qmcs, sso, main_capacity=main_capacity, spawn_capacity=spawn_capacity, graph=graph)
 
 
 def say(*a):
@@ -71,7 +71,7 @@ def assert_same_lists(ctx, run, instance=0, where=""):
 
 FIELDS = ("iteration", "n_walkers_units", "n_occupied", "ref_pop_units", "n_spawned", "n_spawn_events",
           "death_sum", "spawn_sum", "rejected_sum", "n_rejected_units", "n_sign_flips", "vary_shift",
-          "num_limbs", "shift", "proj_numerator", "tau", "spawn_ratio_max")
+          "num_limbs", "pair_limbs", "n_cluster_spawns", "shift", "proj_numerator", "tau", "spawn_ratio_max")
 
 
 def assert_same_estimators(eg, eo, where=""):

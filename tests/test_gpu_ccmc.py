@@ -1,0 +1,165 @@
+"""Coupled cluster Monte Carlo on the GPU against the oracle (paper Sec. 2.2,
+eq. ccmc; Sec. 2.4): truncated spawning, composite clusters sampled by size
+and by |N_i|, collapsed by second-quantised moves, their spawns and death
+steps annihilated with the rest, and the projected energy with its products
+of pairs of singles, bit for bit.
+"""
+import numpy as np
+import pytest
+
+import brute
+from gpu_helpers import assert_same_estimators, assert_same_lists, gpu_context, oracle_qmc, oracle_system, say
+from oracle import oracle as O
+from paper_1811_11679_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _strong5():
+    h1, eri = synth.molecular_integrals(n_orb=5, n_chol=8, seed=1)
+    return h1, eri * 8.0
+
+
+def _pair(sysd, q, trunc, ints=None, caps=(1 << 20, 1 << 21), graph=False):
+    from paper_1811_11679_amd import fciqmc as F
+    qq = dict(q, method=F.CCMC, ccmc_truncation=trunc)
+    ctx = gpu_context([sysd], [qq], ints=ints, main_capacity=caps[0], spawn_capacity=caps[1], graph=graph)
+    oq = oracle_qmc(sysd, q)
+    oq.method = O.CCMC
+    oq.ccmc_truncation = trunc
+    run = O.Run(oracle_system(sysd, ints), oq)
+    return ctx, run
+
+
+def _compare(ctx, run, blocks, per_block, where):
+    for b in range(blocks):
+        ctx.step(per_block)
+        run.step(per_block)
+        assert_same_lists(ctx, run, where=f"{where} block {b}")
+        assert_same_estimators(ctx.history()[-1], run.estimators(), where=f"{where} block {b}")
+    return ctx.estimators()
+
+
+def test_ccmc_molecular_ccsd_from_reference_bitexact():
+    h1, eri = _strong5()
+    sysd = dict(kind="molecular", n_orb=5, n_alpha=2, n_beta=2)
+    q = dict(tau=0.02, rng_seed=11, init_pop=200.0, target_population=600.0, shift_period=10, shift_damping=0.05,
+             p_single=0.2, fixed_point_bits=8, spawn_cutoff=0.01)
+    say("[case] CCMC molecular 5 orbitals 2+2 (strong), CCSD, 1/256 weights, from D_0")
+    ctx, run = _pair(sysd, q, 2, ints=(h1, eri))
+    e = _compare(ctx, run, blocks=15, per_block=20, where="ccsd molecular")
+    assert e["n_occupied"] > 30 and e["vary_shift"] == 1 and e["pair_limbs"] != [0, 0, 0, 0]
+    ctx.close()
+
+
+def test_ccmc_imported_state_negative_reference_ccs_and_ccsdt():
+    """A state with every single held at |N_i| ~ |N_0| / 2 and N_0 < 0, so
+    clusters of the largest size and both signs of N_0^(1-s) occur."""
+    h1, eri = _strong5()
+    sysd = dict(kind="molecular", n_orb=5, n_alpha=2, n_beta=2)
+    s = O.System.molecular(h1, eri, 2, 2)
+    ref = brute.words_int(s.ref)
+    dets = brute.all_dets(5, 2, 2)
+    singles = [d for d in dets if bin(ref ^ d).count("1") == 2]
+    rng = np.random.default_rng(4)
+    for trunc in (1, 3):
+        amps = {d: int(rng.choice([-1, 1]) * rng.integers(1000, 1600)) for d in singles}
+        keys = np.stack([brute.key_words(d, s.W) for d in [ref] + list(amps)])
+        pops = np.array([-3000] + list(amps.values()), np.int32)
+        q = dict(tau=0.03, rng_seed=5 + trunc, init_pop=1.0, target_population=1e9, p_single=0.3,
+                 fixed_point_bits=8, spawn_cutoff=0.02, initial_shift=-0.15)
+        say(f"[case] CCMC molecular, truncation {trunc}, imported singles with N_0 = -3000")
+        ctx, run = _pair(sysd, q, trunc, ints=(h1, eri))
+        ctx.import_walkers(keys, pops, shift=-0.15, iteration=7)
+        run.import_walkers(keys, pops, shift=-0.15, iteration=7)
+        assert_same_lists(ctx, run, where="import")
+        # right after an import the library computes the population estimators
+        # and, for CCMC, the singles-pair sum on the device (set-up kernels)
+        eg, eo = ctx.estimators(), run.estimators()
+        for f in ("n_walkers_units", "n_occupied", "ref_pop_units", "pair_limbs"):
+            assert eg[f] == eo[f], (f, eg[f], eo[f])
+        assert eo["pair_limbs"] != [0, 0, 0, 0]
+        _compare(ctx, run, blocks=6, per_block=5, where=f"truncation {trunc}")
+        ctx.close()
+
+
+def test_ccmc_hubbard_integer_and_graph_replay():
+    """A Hubbard ring in real space with a Neel reference has O(1) cluster
+    amplitudes, so its CCMC population grows without bound; a short chain from
+    an imported state with |N_i| << N_0 still exercises every step. Blocks of
+    A = 10 iterations run under graph replay when it is on."""
+    sysd = dict(kind="hubbard", n_sites=4, periodic=1, t=1.0, U=4.0, n_alpha=3, n_beta=2)
+    s = O.System.hubbard(4, True, 1.0, 4.0, 3, 2)
+    dets, _ = brute.hubbard_matrix(4, 3, 2, 1.0, 4.0)
+    ref = brute.words_int(s.ref)
+    rng = np.random.default_rng(12)
+    pool = [d for d in dets if 1 <= bin(ref ^ d).count("1") // 2 <= 2]
+    amps = {d: int(rng.integers(-30, 30)) or 7 for d in rng.choice(pool, 10, replace=False).tolist()}
+    keys = np.stack([brute.key_words(d, 1) for d in [ref] + list(amps)])
+    pops = np.array([2000] + list(amps.values()), np.int32)
+    q = dict(tau=0.01, rng_seed=3, init_pop=1.0, target_population=1e9, shift_period=10, shift_damping=0.05,
+             initial_shift=-0.5)
+    for graph in (False, True):
+        say(f"[case] CCMC Hubbard ring 4 sites 3+2, CCSD, integer walkers, imported state, graph replay {graph}")
+        ctx, run = _pair(sysd, q, 2, graph=graph)
+        ctx.import_walkers(keys, pops, shift=-0.5)
+        run.import_walkers(keys, pops, shift=-0.5)
+        e = _compare(ctx, run, blocks=5, per_block=10, where=f"hubbard graph {graph}")
+        assert e["n_occupied"] >= 20 and e["n_walkers_units"] > 5000
+        ctx.close()
+
+
+def test_ccmc_electron_gas_two_word_keys():
+    # 14 electrons in 57 plane waves (114 spin-orbitals: two words per key)
+    sysd = dict(kind="ueg", rs=1.0, ecut_n2=5, n_alpha=7, n_beta=7)
+    q = dict(tau=0.002, rng_seed=9, init_pop=500.0, target_population=2e4, shift_period=10, shift_damping=0.05,
+             fixed_point_bits=8, spawn_cutoff=0.1)
+    say("[case] CCMC electron gas 7+7 in 57 plane waves, CCSD, 1/256 weights")
+    ctx, run = _pair(sysd, q, 2, caps=(1 << 21, 1 << 22))
+    assert ctx.W == 2
+    e = _compare(ctx, run, blocks=6, per_block=25, where="ueg ccsd")
+    assert e["n_occupied"] > 1000
+    ctx.close()
+
+
+def test_ccmc_heatbath_10_orbitals_ccsdt():
+    """Heat-bath doubles, truncation 3 (clusters of up to five excitors). Without
+    the initiator rule CCMC needs N_0 to outweigh the excitors; a 30-orbital
+    system at CCSDT would need far more walkers than a parity test runs."""
+    h1, eri = synth.molecular_integrals(n_orb=10, n_chol=12, seed=6)
+    sysd = dict(kind="molecular", n_orb=10, n_alpha=3, n_beta=3)
+    q = dict(tau=0.01, rng_seed=21, init_pop=5000.0, target_population=2e4, shift_period=10, shift_damping=0.05,
+             p_single=0.1, fixed_point_bits=8, spawn_cutoff=0.05)
+    say("[case] CCMC molecular 10 orbitals 3+3 (heat-bath), CCSDT, 1/256 weights")
+    ctx, run = _pair(sysd, q, 3, ints=(h1, eri))
+    e = _compare(ctx, run, blocks=8, per_block=20, where="mol10 ccsdt")
+    assert e["n_occupied"] > 3000 and e["vary_shift"] == 1
+    ctx.close()
+
+
+def test_ccmc_errors():
+    from paper_1811_11679_amd import fciqmc as F
+    h1, eri = _strong5()
+    sysd = dict(kind="molecular", n_orb=5, n_alpha=2, n_beta=2)
+    q = dict(tau=0.02, init_pop=100.0, target_population=1e9, p_single=0.2, fixed_point_bits=8, spawn_cutoff=0.01)
+    for bad in (dict(initiator=1), dict(tau_search=1), dict(ccmc_truncation=0), dict(ccmc_truncation=7)):
+        with pytest.raises(F.FqError):
+            gpu_context([sysd], [dict(q, method=F.CCMC, **dict(dict(ccmc_truncation=2), **bad))], ints=(h1, eri))
+    with pytest.raises(F.FqError):  # one instance per context
+        gpu_context([sysd] * 2, [dict(q, method=F.CCMC, ccmc_truncation=2)] * 2, ints=(h1, eri))
+    ctx, _ = _pair(sysd, q, 1, ints=(h1, eri))
+    s = O.System.molecular(h1, eri, 2, 2)
+    ref = brute.words_int(s.ref)
+    dets = brute.all_dets(5, 2, 2)
+    dbl = next(d for d in dets if bin(ref ^ d).count("1") == 4)
+    sgl = next(d for d in dets if bin(ref ^ d).count("1") == 2)
+    with pytest.raises(F.FqError):  # beyond the truncation level
+        ctx.import_walkers(np.stack([s.ref, brute.key_words(dbl, s.W)]), np.array([100, 5], np.int32))
+    # no reference population: the step fails and the list is kept
+    ctx.import_walkers(brute.key_words(sgl, s.W)[None, :], np.array([50], np.int32))
+    with pytest.raises(F.FqError) as ei:
+        ctx.step(1)
+    assert ei.value.code == F.FQ_ENOREF
+    k, p = ctx.export()
+    assert len(p) == 1 and p[0] == 50
+    ctx.close()
