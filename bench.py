@@ -37,7 +37,7 @@ METRIC = "walker updates/s per FCIQMC iteration, plain vs batched; annihilation 
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(hist_prev, hist, W, ds_active=False, instances=1):
+def algorithmic_bytes(hist_prev, hist, W, ds_active=False, instances=1, ccmc=None):
     """Bytes each kernel must move per iteration (reads + writes of the data it
     owns). The deterministic slot of a main entry (4 bytes) is read and written
     only while a deterministic space is active; its sort key (8 bytes) is
@@ -60,6 +60,20 @@ def algorithmic_bytes(hist_prev, hist, W, ds_active=False, instances=1):
     # output: skey, key, pop, kdiag, slot, attempt offset and the new-determinant flag
     out["merge"] = nm * (sk + kb + 4 + 8 + ds) + nu * (8 + kb + 8 + 4) + nm2 * (sk + kb + 4 + 8 + ds + 8 + 1)
     out["new_diag"] = nm2 * 8
+    if ccmc is not None:
+        # CCMC (ccmc = (truncation, electrons, b)): the prefix scan reads key and
+        # population and writes 8 bytes per entry; each of the n_c selections
+        # reads the key and population of s excitors (s of expected value
+        # sum_s p(s) s) and each composite record is written as for a spawn
+        trunc, nel, b = ccmc
+        smax = min(trunc + 2, nel)
+        ps = {sz: 2.0 ** -(sz - 1) for sz in range(2, smax)}
+        ps[smax] = 2.0 ** -(smax - 2)
+        s_mean = sum(sz * p for sz, p in ps.items())
+        nex = hist_prev["n_walkers_units"] - abs(hist_prev["ref_pop_units"])
+        nc = -(-nex // (1 << b))
+        out["ccmc_clusters"] = nm * (kb + 4 + 8) + nc * s_mean * (kb + 4) + hist["n_cluster_spawns"] * (8 + kb + 8)
+        out["ccmc_pairs"] = nm2 * (kb + 4)
     return out
 
 
@@ -139,9 +153,10 @@ def cpu_baseline(state, spec, budget_s=20.0, max_iter=50, max_dets=4_000_000):
     sysd = O.System.ueg(s["rs"], s["ecut_n2"], s["n_alpha"], s["n_beta"])
     run = O.Run(sysd, O.make_qmc(tau=q["tau"], seed=q["rng_seed"], init_pop=q["init_pop"],
                                  target_population=q["target_population"], shift_period=q["shift_period"],
-                                 shift_damping=q["shift_damping"], excit_gen=O.EXGEN_UEG, initiator=1,
-                                 initiator_threshold=q["initiator_threshold"], fixed_point_bits=q["fixed_point_bits"],
-                                 spawn_cutoff=q["spawn_cutoff"]))
+                                 shift_damping=q["shift_damping"], excit_gen=O.EXGEN_UEG,
+                                 initiator=q.get("initiator", 1), initiator_threshold=q["initiator_threshold"],
+                                 fixed_point_bits=q["fixed_point_bits"], spawn_cutoff=q["spawn_cutoff"],
+                                 method=q.get("method", 0), ccmc_truncation=q.get("ccmc_truncation", 0)))
     run.import_walkers(keys, pops, shift=sh, iteration=int(e["iteration"]), vary=vary, n_prev=max(1, nprev // k))
     scale = 2.0 ** q["fixed_point_bits"]
     nw_prev = run.estimators()["n_walkers_units"]
@@ -155,10 +170,13 @@ def cpu_baseline(state, spec, budget_s=20.0, max_iter=50, max_dets=4_000_000):
         print(f"# oracle iteration {it}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dt = time.perf_counter() - t0
     out = {"value": upd / dt, "unit": "walker updates/s", "cores": 1, "kind": "oracle",
-           "sample": f"{it} iterations ({e['iteration'] + 1}..{e['iteration'] + it}) from every {k}-th "
-                     f"determinant of the GPU list at the start of the timed window ({len(pops)} of "
-                     f"{len(pops_all)} determinants, {abs(pops.astype('int64')).sum() / scale:.4g} walkers), "
-                     f"single thread"}
+           "sample": (f"{it} iterations ({e['iteration'] + 1}..{e['iteration'] + it}) from every {k}-th "
+                      f"determinant of the GPU list at the start of the timed window ({len(pops)} of "
+                      f"{len(pops_all)} determinants, {abs(pops.astype('int64')).sum() / scale:.4g} walkers), "
+                      f"single thread") if k > 1 else
+                     (f"{it} iterations ({e['iteration'] + 1}..{e['iteration'] + it}) from the whole GPU list at "
+                      f"the start of the timed window ({len(pops)} entries, "
+                      f"{abs(pops.astype('int64')).sum() / scale:.4g} walkers), single thread")}
     out.update(host_cpu())
     return out
 
@@ -384,10 +402,17 @@ def run_mol30(args):
 
 
 def single_spec(args):
-    """The single-instance workloads: 14-electron gas (default) and the
-    54-electron gas with its split-precision deterministic space."""
+    """The single-instance workloads: 14-electron gas (default), the
+    54-electron gas with its split-precision deterministic space, and coupled
+    cluster Monte Carlo at CCSD on the 14-electron gas."""
     from paper_1811_11679_amd import fciqmc as F
     from paper_1811_11679_amd import workloads
+    if args.workload == "ccmc":
+        w = workloads.UEG14_CCSD
+        return dict(name="ccmc", w=w, system=w["system"], qmc=dict(w["qmc"]), ss=None,
+                    equilibration=w["equilibration"],
+                    config={"workload": "ccmc_ccsd_ueg14_rs1_57pw", "method": "CCMC", "truncation": "CCSD",
+                            "electrons": 14, "rs": 1.0, "plane_waves": 57, "fixed_point": "1/256"})
     if args.workload == "ueg14":
         w = workloads.UEG14
         return dict(name="ueg14", w=w, system=w["system"], qmc=dict(w["qmc"]), ss=None,
@@ -482,12 +507,17 @@ def run_single(args):
     dets = sum(h["n_occupied"] for h in prev)
     spawned = sum(h["n_spawned"] for h in hist)
     ds_active = spec["ss"] is not None
+    is_cc = q.get("method", 0) == F.CCMC
+    cc = (q["ccmc_truncation"], s["n_alpha"] + s["n_beta"], q["fixed_point_bits"]) if is_cc else None
     tot_bytes = {}
     for a, b in zip(prevk, hk):
-        for k, v in algorithmic_bytes(a, b, ctx.W, ds_active=ds_active).items():
+        for k, v in algorithmic_bytes(a, b, ctx.W, ds_active=ds_active, ccmc=cc).items():
             tot_bytes[k] = tot_bytes.get(k, 0) + v
     cand = {"spawn": ["spawn"], "merge": ["merge"], "reduce": ["reduce"], "new_diag": ["new_diag"],
             "sort_pass": [f"sort_pass{p}" for p in range(8)]}
+    if is_cc:
+        # the cluster slot holds the prefix scan and the cluster sampler (two launches)
+        cand["ccmc_clusters"] = ["ccmc_clusters"]
     best = max(cand, key=lambda g: sum(ktimes[k] for k in cand[g]))
     launches = niter * len(cand[best])
     avg_ms = sum(ktimes[k] for k in cand[best]) / max(launches, 1)
@@ -530,9 +560,9 @@ def run_single(args):
         "determinant_updates_per_s": dets / dt,
         "spawns_per_s": spawned / dt,
         "stage_ms_per_iteration": {k: v / max(niter, 1) for k, v in stages.items()},
-        # (the two CCMC slots time only the gap between two events on this path)
+        # (the two CCMC slots time only the gap between two events on the FCIQMC path)
         "kernel_ms_per_iteration": {k: v / max(niter, 1) for k, v in ktimes.items()
-                                    if v > 0 and not k.startswith("ccmc")},
+                                    if v > 0 and (is_cc or not k.startswith("ccmc"))},
         "walkers_start": e_start["n_walkers_units"] / scale,
         "walkers_end": hist[-1]["n_walkers_units"] / scale,
         "determinants_start": e_start["n_occupied"],
@@ -583,18 +613,20 @@ def main():
     ap.add_argument("--shift-damping", type=float, default=None, help="ueg54: shift damping (zeta)")
     ap.add_argument("--initial-shift", type=float, default=None, help="ueg54: initial shift (Hartree, relative to H_00)")
     ap.add_argument("--tau", type=float, default=None, help="ueg54: time step")
-    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64", "mol30", "ueg54"],
+    ap.add_argument("--workload", default="ueg14", choices=["ueg14", "batch64", "mol30", "ueg54", "ccmc"],
                     help="ueg14: the plain single-instance path; ueg54: the large single instance; batch64: 64 "
-                         "batched instances vs plain runs; mol30: semi-stochastic molecular runs, FP64 vs split")
+                         "batched instances vs plain runs; mol30: semi-stochastic molecular runs, FP64 vs split; "
+                         "ccmc: coupled cluster Monte Carlo at CCSD on the 14-electron gas")
     ap.add_argument("--replicas", type=int, default=1, help="mol30: replicas sharing one deterministic space")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain device copy of 1 GiB (4 times) for counter calibration")
     args = ap.parse_args()
     big = args.workload == "ueg54"
+    cc = args.workload == "ccmc"  # about 1.8e3 amplitudes, up to ~3e7 spawn records per iteration
     if args.main_capacity is None:
-        args.main_capacity = 330_000_000 if big else 1 << 28
+        args.main_capacity = 330_000_000 if big else (1 << 20 if cc else 1 << 28)
     if args.spawn_capacity is None:
-        args.spawn_capacity = 200_000_000 if big else 1 << 27
+        args.spawn_capacity = 200_000_000 if big else (1 << 26 if cc else 1 << 27)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs is "
               "designed but not implemented", file=sys.stderr)

@@ -50,6 +50,18 @@ UEG54 = dict(
     equilibration=1000,
 )
 
+# coupled cluster Monte Carlo at CCSD on the 14-electron gas (the paper's UEG
+# CCMC comparison, Sec. 4.3): about 1.8e3 amplitudes, N_ex / N_0 near 9 at
+# the CCSD amplitudes, so 1e6 walkers on D_0 hold about 1e7 in total; the
+# population settles within a few hundred iterations
+UEG14_CCSD = dict(
+    system=dict(kind="ueg", rs=1.0, ecut_n2=5, n_alpha=7, n_beta=7),
+    qmc=dict(tau=0.002, rng_seed=7, init_pop=1e6, target_population=8e6, shift_period=10,
+             shift_damping=0.05, initial_shift=0.0, initiator=0, initiator_threshold=3.0,
+             fixed_point_bits=8, spawn_cutoff=0.1, method=3, ccmc_truncation=2),
+    equilibration=1000,
+)
+
 UEG_ECUT_FOR_BASIS = {19: 2, 27: 3, 57: 5, 123: 9}
 
 
