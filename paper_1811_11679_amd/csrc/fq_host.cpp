@@ -319,7 +319,7 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.u[2] = take(8 * (size_t)scap);
     L.u[3] = take(4 * (size_t)scap);
     const size_t nd = (size_t)D * R;
-    const size_t np = (size_t)((D + 15) / 16) * 16;
+    const size_t np = (size_t)((D + 31) / 32) * 32;  // MFMA k steps of 32
     L.ds[0] = take(8 * (size_t)nk * D * (size_t)D);  // K fp64
     L.ds[1] = take(2 * (size_t)nk * np * np);        // K hi bf16
     L.ds[2] = take(2 * (size_t)nk * np * np);        // K lo bf16
@@ -895,7 +895,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     w.ds.n = c->D;
     w.ds.precision = c->has_ss ? c->ss.precision : 0;
     w.ds.K = (const double *)(c->ws + c->L.ds[0]);
-    w.ds.npad = ((c->D + 15) / 16) * 16;
+    w.ds.npad = ((c->D + 31) / 32) * 32;
     w.ds.check_period = c->has_ss ? c->ss.check_period : 0;
     w.ds.shared = c->has_ss ? c->ss.shared : 0;
     w.ds.nk = nk;

@@ -149,7 +149,7 @@ struct UniqList {
 struct DetSpace {
     int32_t n;            // D (per replica equal; total = n * R)
     int32_t precision;
-    int32_t npad;         // D rounded up to 16 (MFMA tiles)
+    int32_t npad;         // D rounded up to 32 (MFMA k steps)
     int32_t check_period; // split mode: FP64 check every check_period iterations
     int32_t shared;       // one D (and one K_DD) for all replicas
     int32_t nk;           // number of K_DD matrices: 1 if shared, else R

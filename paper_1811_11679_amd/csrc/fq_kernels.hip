@@ -1793,9 +1793,10 @@ __global__ __launch_bounds__(256) void k_det_project_fp64(Work w, int mode)
 
 // Split-precision projection on MFMA: y = K c with K and c split into BF16
 // hi + lo planes, y = K_hi c_hi + K_hi c_lo + K_lo c_hi accumulated in FP32
-// (the "bf16x3" scheme). One wavefront computes 16 rows of one replica with
-// v_mfma_f32_16x16x16_bf16; the amplitudes occupy column 0 of the 16 x 16 B tile.
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+// (the "bf16x3" scheme) with v_mfma_f32_16x16x32_bf16. A block computes 16
+// rows of up to 16 replicas (one K_DD shared by all) or of one replica (its
+// amplitudes in column 0 of the 16 x 16 B tile).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int DP_WAVES = 8;  // waves per block of the split projection (split over k)
@@ -1803,9 +1804,12 @@ constexpr int DP_WAVES = 8;  // waves per block of the split projection (split o
 __global__ __launch_bounds__(64 * DP_WAVES) void k_det_project_split(Work w)
 {
     // One block per job (16 rows x up to 16 columns of Y = K C); its waves
-    // take interleaved 16-wide steps of the k range and their FP32 partial
-    // tiles are summed in LDS in wave order. Shared space: the columns are 16
-    // replicas, one K_DD for all. Otherwise: one replica per job, in column 0.
+    // take interleaved 32-wide steps of the k range (gfx950's 16x16x32 BF16
+    // MFMA: each lane holds 8 consecutive k of its row of A and of its column
+    // of B, loaded with the same k order so the dot products pair correctly)
+    // and their FP32 partial tiles are summed in LDS in wave order. Shared
+    // space: the columns are 16 replicas, one K_DD for all. Otherwise: one
+    // replica per job, in column 0.
     const Ctl *c = w.ctl;
     if (c->err || !c->ss_active || w.ds.precision != 1) return;
     __shared__ float s_part[DP_WAVES][64][4];
@@ -1818,7 +1822,7 @@ __global__ __launch_bounds__(64 * DP_WAVES) void k_det_project_split(Work w)
     for (long long job = blockIdx.x; job < jobs; job += gridDim.x) {
         const int rt = (int)(job / cblocks), cb = (int)(job % cblocks);
         const int arow = rt * 16 + (lane & 15);
-        const int kq = 4 * (lane >> 4);
+        const int kq = 8 * (lane >> 4);
         // this lane's column of B (and of the result): a replica
         const int rep = shared ? cb * 16 + (lane & 15) : cb;
         const bool bval = shared ? rep < w.R : (lane & 15) == 0;
@@ -1828,17 +1832,18 @@ __global__ __launch_bounds__(64 * DP_WAVES) void k_det_project_split(Work w)
         const uint16_t *ch = w.ds.Chi + (size_t)(bval ? rep : 0) * np + kq;
         const uint16_t *cl = w.ds.Clo + (size_t)(bval ? rep : 0) * np + kq;
         f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-        for (int kk = 16 * wv; kk < np; kk += 16 * DP_WAVES) {
-            const bf16x4_t ah = *(const bf16x4_t *)(kh + kk);
-            const bf16x4_t al = *(const bf16x4_t *)(kl + kk);
-            bf16x4_t bh = {0, 0, 0, 0}, bl = {0, 0, 0, 0};
+        const bf16x8_t zero = {};
+        for (int kk = 32 * wv; kk < np; kk += 32 * DP_WAVES) {
+            const bf16x8_t ah = *(const bf16x8_t *)(kh + kk);
+            const bf16x8_t al = *(const bf16x8_t *)(kl + kk);
+            bf16x8_t bh = zero, bl = zero;
             if (bval) {
-                bh = *(const bf16x4_t *)(ch + kk);
-                bl = *(const bf16x4_t *)(cl + kk);
+                bh = *(const bf16x8_t *)(ch + kk);
+                bl = *(const bf16x8_t *)(cl + kk);
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) s_part[wv][lane][i] = acc[i];
