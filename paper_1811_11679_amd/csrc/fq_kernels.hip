@@ -1594,8 +1594,11 @@ __device__ double entry_kdiag(const Work &w, const DevSys &sy, const uint64_t (&
 // Each block scans a chunk of the new list, queues the marked entries in LDS
 // and evaluates them one per thread, so no lane idles on unmarked entries;
 // for a single replica the diagonal's tables are read from LDS.
-constexpr int ND_T = 256, ND_CHUNK = 4096;
-static_assert(ND_CHUNK == ND_T * 16, "each thread scans 16 new-determinant flags");
+// Chunks of 16384 flags: new determinants are a few per cent of the list, and
+// a chunk must hold enough of them to fill the block's waves (at 4096 flags a
+// 256-thread block had about one partial wave of work per chunk)
+constexpr int ND_T = 512, ND_CHUNK = 16384;
+static_assert(ND_CHUNK == ND_T * 32, "each thread scans 32 new-determinant flags");
 
 template <int KIND, int W>
 __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
@@ -1603,7 +1606,7 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
     const Ctl *c = w.ctl;
     if (c->err) return;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
-    __shared__ uint32_t s_q[ND_CHUNK];
+    __shared__ uint16_t s_q[ND_CHUNK];  // offsets of the chunk's new determinants
     __shared__ int s_n;
     const long long n = c->n_main_new;
     const DevSys &s0 = w.sys[w.rep[0].sys];
@@ -1650,19 +1653,20 @@ __global__ __launch_bounds__(ND_T) void k_new_diag(Work w)
     for (long long base = (long long)blockIdx.x * ND_CHUNK; base < n; base += (long long)gridDim.x * ND_CHUNK) {
         if (threadIdx.x == 0) s_n = 0;
         __syncthreads();
-        // the merge's new-determinant flags, 16 per thread
+        // the merge's new-determinant flags, 32 per thread in two 16-byte loads
         {
-            const int q0 = threadIdx.x * 16;
+            const int q0 = threadIdx.x * 32;
             const long long i0 = base + q0;
-            if (i0 + 16 <= n) {
-                const uint4 f = *(const uint4 *)(w.newdet + i0);
-                const uint32_t fw[4] = {f.x, f.y, f.z, f.w};
+            if (i0 + 32 <= n) {
+                const uint4 f0 = *(const uint4 *)(w.newdet + i0);
+                const uint4 f1 = *(const uint4 *)(w.newdet + i0 + 16);
+                const uint32_t fw[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
 #pragma unroll
-                for (int b = 0; b < 16; ++b)
-                    if ((fw[b >> 2] >> (8 * (b & 3))) & 0xFFu) s_q[atomicAdd(&s_n, 1)] = (uint32_t)(q0 + b);
+                for (int b = 0; b < 32; ++b)
+                    if ((fw[b >> 2] >> (8 * (b & 3))) & 0xFFu) s_q[atomicAdd(&s_n, 1)] = (uint16_t)(q0 + b);
             } else {
-                for (int b = 0; b < 16 && i0 + b < n; ++b)
-                    if (w.newdet[i0 + b]) s_q[atomicAdd(&s_n, 1)] = (uint32_t)(q0 + b);
+                for (int b = 0; b < 32 && i0 + b < n; ++b)
+                    if (w.newdet[i0 + b]) s_q[atomicAdd(&s_n, 1)] = (uint16_t)(q0 + b);
             }
         }
         __syncthreads();
