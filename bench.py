@@ -77,20 +77,26 @@ def algorithmic_bytes(hist_prev, hist, W, ds_active=False, instances=1, ccmc=Non
     return out
 
 
+def kernel_sources_sha256():
+    """SHA-256 over the device sources (the .hip files and the headers they
+    include, in name order): what HBM counters of the kernels depend on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1811_11679_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h")):
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary of the
     workload, if the kernel sources are the ones it was measured on (else None)."""
-    import glob
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1811_11679_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(f, "rb").read())
-    if h.hexdigest() != rec.get("source_sha256"):
+    if kernel_sources_sha256() != rec.get("source_sha256"):
         return None
     k = rec["kernels"].get(kernel)
     return None if k is None else k["bytes_per_launch"]

@@ -156,7 +156,9 @@ typedef struct {
  * a double, the products (1 / N_0) sgn N_a N_b of pairs of singles
  * (fq_estimators_t.pair_limbs). One instance per context; not with the
  * initiator rule, a deterministic space or tau_search (FQ_EINVAL). A
- * step whose reference holds no walkers fails with FQ_ENOREF. */
+ * step whose reference holds no walkers fails with FQ_ENOREF; fq_step refuses
+ * to start a block of iterations with 2^36 or more units of walkers
+ * (FQ_EOVERFLOW: the prefix of |N_i| is carried in 38-bit words). */
 #define FQ_CCMC 3
 
 /* Semi-stochastic block (tutorial appendix, semi_stoch = {size,

@@ -1188,6 +1188,10 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
     std::vector<hipEvent_t> evs;
     int done = 0;
     while (done < n_iterations) {
+        // CCMC: the prefix of |N_i| travels in look-back words of 38 bits; a
+        // block of iterations starts only with room for its growth
+        if (c->method == FQ_CCMC && c->last[0].n_walkers_units >= (int64_t(1) << 36))
+            return fail(c, FQ_EOVERFLOW, "CCMC: the excip population exceeds 2^36 units");
         // iterations until the next host decision point (shift update, D selection, end)
         int64_t stop = c->t + (n_iterations - done);
         const int64_t next_shift = (c->t / A + 1) * A;
