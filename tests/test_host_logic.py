@@ -66,3 +66,10 @@ def test_byte_model_counts_the_moved_fields():
     b8 = bench.algorithmic_bytes(prev, cur, 8)
     assert b8["merge"] - bench.algorithmic_bytes(prev, cur, 8, instances=2)["merge"] == 0  # long keys keep sort keys
     assert np.isclose(b1["sort_pass1"], 300 * 24)
+    # CCMC at CCSD on 14 electrons: sizes 2, 3, 4 with p = 1/2, 1/4, 1/4 (mean 2.75);
+    # n_c = ceil(N_ex 2^-8) with N_ex = N_w - |N_0| of the previous iteration
+    prev_c = dict(n_occupied=1000, n_walkers_units=256 * 500 + 100, ref_pop_units=-100)
+    cur_c = dict(n_occupied=1000, n_spawned=300, n_spawn_events=200, n_cluster_spawns=40)
+    bc = bench.algorithmic_bytes(prev_c, cur_c, 2, ccmc=(2, 14, 8))
+    assert np.isclose(bc["ccmc_clusters"], 1000 * (16 + 4 + 8) + 500 * 2.75 * (16 + 4) + 40 * (8 + 16 + 8))
+    assert "ccmc_clusters" not in b1
