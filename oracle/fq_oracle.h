@@ -1,7 +1,8 @@
 /*
  * FCIQMC oracle: a plain, single-threaded CPU definition of one projector
  * iteration (spawning, death/cloning, annihilation with the initiator rule,
- * semi-stochastic projection, estimators, shift update).
+ * semi-stochastic projection, estimators, shift update), and of the same
+ * iteration for the density-matrix and coupled cluster methods.
  *
  * TEST INFRASTRUCTURE ONLY. Only the test-suite, the smoke check and the
  * benchmark's CPU-baseline leg may load this library. The product path (the
@@ -20,10 +21,12 @@
  *   sorted main list, hash   appendix "Parallelization"
  *   density matrix (DMQMC,
  *   IP-DMQMC)                Sec. 2.3, eqs. (dmqmc) and (ipdmqmc); Sec. 2.4
+ *   coupled cluster (CCMC)   Sec. 2.2, eq. (ccmc); Sec. 2.4
  *
  * Parity pins (see the tests): brute-force second-quantised Hamiltonian,
  * exact diagonalisation, exhaustive generator enumeration, the rocRAND
- * Philox4x32-10 implementation, expectation values of the stochastic steps.
+ * Philox4x32-10 implementation, expectation values of the stochastic steps,
+ * Jordan-Wigner excitor products and deterministic coupled cluster energies.
  */
 #ifndef FQ_ORACLE_H
 #define FQ_ORACLE_H
