@@ -41,6 +41,9 @@
 namespace fq {
 
 constexpr int CC_T = 256, CC_I = 8, CC_TILE = CC_T * CC_I;
+// prefix entries a cluster block stages in LDS (32 KB): lists of up to 4095
+// entries are searched there, longer ones in global memory
+constexpr int CC_LDS_CUM = 4096;
 
 // ---------------------------------------------------------------------------
 // prefix of |N_i| over the current list (reference masked), N_0, N_ex
@@ -183,6 +186,13 @@ __global__ __launch_bounds__(CC_T) void k_ccmc_clusters(Work w)
     for (int q = 0; q < W; ++q) ref[q] = sy.ref[q];
     const int lane = lane_id();
     const long long stride = (long long)gridDim.x * CC_T;
+    // the prefix, staged in LDS when it fits (every selection searches it)
+    __shared__ long long s_cum[CC_LDS_CUM];
+    const bool staged = n + 1 <= CC_LDS_CUM;
+    if (staged)
+        for (long long i = threadIdx.x; i <= n; i += CC_T) s_cum[i] = w.ccmc_cum[i];
+    __syncthreads();
+    const long long *cum = staged ? s_cum : w.ccmc_cum;
     for (long long base = (long long)blockIdx.x * CC_T; base < nc; base += stride) {
         const long long sel = base + threadIdx.x;
         // up to two records: the spawn (0) and the term's death step (1)
@@ -211,7 +221,7 @@ __global__ __launch_bounds__(CC_T) void k_ccmc_clusters(Work w)
                 long long lo = 0, hi = n;  // last entry whose prefix is <= target
                 while (hi - lo > 1) {
                     const long long mid = (lo + hi) >> 1;
-                    if (w.ccmc_cum[mid] <= target) lo = mid; else hi = mid;
+                    if (cum[mid] <= target) lo = mid; else hi = mid;
                 }
                 uint64_t e[W], he[W], pe[W];
                 bool clash = false;

@@ -163,3 +163,40 @@ def test_ccmc_errors():
     k, p = ctx.export()
     assert len(p) == 1 and p[0] == 50
     ctx.close()
+
+
+def test_ccmc_benchmark_workload_full_size_bitexact():
+    """The CCMC benchmark workload (CCSD on the 14-electron gas, 1e6 walkers on
+    D_0, about 1e7 excips on 1797 amplitudes) under graph replay, as bench.py
+    runs it: after 300 iterations the GPU state is imported into the oracle and
+    one more iteration on each side must give the same list and estimators."""
+    from paper_1811_11679_amd import fciqmc as F
+    from paper_1811_11679_amd import workloads
+    w = workloads.UEG14_CCSD
+    s, q = w["system"], dict(w["qmc"])
+    ctx = F.Context([F.make_system(F.UEG, rs=s["rs"], ecut_n2=s["ecut_n2"], n_alpha=s["n_alpha"], n_beta=s["n_beta"])],
+                    [F.make_qmc(excit_gen=F.UEG, **q)], main_capacity=1 << 20, spawn_capacity=1 << 26, graph=True)
+    ctx.step(300)
+    e0 = ctx.estimators()
+    say(f"[case] CCMC benchmark workload at iteration {e0['iteration']}: {e0['n_walkers_units'] / 256:.4g} excips, "
+        f"{e0['n_occupied']} amplitudes, N_0 {e0['ref_pop_units'] / 256:.4g}")
+    assert e0["n_walkers_units"] > 256 * 5e6 and e0["n_occupied"] > 1500
+    keys, pops = ctx.export()
+    shift, nprev, vary = ctx.shift_state()
+    oq = O.make_qmc(tau=q["tau"], seed=q["rng_seed"], init_pop=q["init_pop"], target_population=q["target_population"],
+                    shift_period=q["shift_period"], shift_damping=q["shift_damping"], excit_gen=O.EXGEN_UEG,
+                    fixed_point_bits=q["fixed_point_bits"], spawn_cutoff=q["spawn_cutoff"], method=O.CCMC,
+                    ccmc_truncation=q["ccmc_truncation"])
+    run = O.Run(O.System.ueg(s["rs"], s["ecut_n2"], s["n_alpha"], s["n_beta"]), oq)
+    run.import_walkers(keys, pops, shift=shift, iteration=int(e0["iteration"]), vary=vary, n_prev=nprev)
+    ctx.step(1)
+    run.step(1)
+    assert_same_lists(ctx, run, where="ccmc full size")
+    assert_same_estimators(ctx.history()[-1], run.estimators(), where="ccmc full size")
+    e1 = ctx.estimators()
+    say(f"[case] one iteration identical: {e1['n_spawned']} spawns, {e1['n_cluster_spawns']} from composite clusters")
+    # about 1e7 selections per iteration; at CCSD most composite clusters are
+    # pairs of doubles, whose quadruples have no death step and reach a double
+    # only by a rare de-excitation, so their records number in the thousands
+    assert e1["n_cluster_spawns"] > 500
+    ctx.close()
