@@ -105,12 +105,12 @@ typedef struct {
                                    with b = 1, 2 an int32 population could need 2^28 or more
                                    spawning attempts, the limit of the random-number counter) */
     double spawn_cutoff;        /* walkers; real mode only */
-    int32_t tau_search;         /* 1: the tutorial's tau_search, one instance per context
-                                   (FQ_EINVAL otherwise). After each shift update tau only
-                                   decreases, to min(tau, 1 / max |H_ji| / p_gen over every
-                                   attempt so far, 1 / (max K_ii - S) over the entries of the
-                                   last death step), each bound applying when positive.
-                                   Export/import keep tau and the running maximum. */
+    int32_t tau_search;         /* 1: the tutorial's tau_search, per instance. After each
+                                   shift update of the instance its tau only decreases, to
+                                   min(tau, 1 / max |H_ji| / p_gen over every attempt of the
+                                   instance so far, 1 / (max K_ii - S) over the instance's
+                                   entries of the last death step), each bound applying when
+                                   positive. Export/import keep tau and the running maximum. */
     int32_t method;             /* FQ_FCIQMC, FQ_DMQMC, FQ_IPDMQMC or FQ_CCMC (the same for
                                    every instance of a context) */
     int32_t ccmc_truncation;    /* FQ_CCMC: highest excitation level of an excitor, 1..6

@@ -375,7 +375,7 @@ struct fq_ctx {
     EstAcc *h_hist = nullptr;
     double *h_shift = nullptr;
     double h00[64] = {0};
-    double rs_max = 0.0;  // time-step search: largest |H_ji| / p_gen so far (device maximum)
+    std::vector<double> rs_max;  // [R] time-step search: largest |H_ji| / p_gen so far
     std::vector<double> h00v;
     bool timing = false;
     bool graph = false;
@@ -458,7 +458,21 @@ void estimators_from_acc(const fq_ctx *c, int r, const EstAcc &a, fq_estimators_
     e.proj_energy = a.n0 != 0 ? num / (double)a.n0 : NAN;
     e.e_ref = c->h00v[r];
     e.tau = c->qmc[r].tau;
-    e.spawn_ratio_max = c->rs_max;
+    e.spawn_ratio_max = c->rs_max[r];
+}
+
+// time-step search: fold the per-iteration maxima of |H_ji| / p_gen of
+// iterations first..last (held in the host copy of the history ring) into each
+// replica's running maximum
+void fold_spawn_ratio(fq_ctx *c, int64_t first, int64_t last)
+{
+    for (int64_t it = first; it <= last; ++it)
+        for (int r = 0; r < c->R; ++r) {
+            const unsigned long long b = c->h_hist[(size_t)(it % HIST_LEN) * c->R + r].rs_bits;
+            double v;
+            std::memcpy(&v, &b, 8);
+            if (v > c->rs_max[r]) c->rs_max[r] = v;
+        }
 }
 
 void set_main_views(fq_ctx *c)
@@ -792,7 +806,6 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
         return FQ_EINVAL;
     if (spawn_capacity >= (1ll << 32)) return FQ_EINVAL;
     for (int r = 0; r < n_instances; ++r)
-        if (qmc[r].tau_search && n_instances > 1) return FQ_EINVAL;  // the search is per context
     *out = nullptr;
     fq_ctx *c = new fq_ctx();
     c->pinned = pinned;
@@ -1073,6 +1086,7 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
 
     c->shift.assign(c->R, 0.0);
     c->vary.assign(c->R, 0);
+    c->rs_max.assign(c->R, 0.0);
     c->nprev.assign(c->R, 0);
     c->last.resize(c->R);
     c->hist.assign(c->R, {});
@@ -1313,6 +1327,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                     HIPCHK(c, h2d(c->stream, c->ws + c->L.ds[3], pos.data(), 4 * pos.size()));
                 }
             }
+            fold_spawn_ratio(c, t0 + 1, tf - 1);
             for (int64_t it = t0 + 1; it < tf; ++it)
                 for (int r = 0; r < c->R; ++r) {
                     fq_estimators_t e;
@@ -1329,11 +1344,7 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
             if (err & ERR_SPAWN_CAP) return fail(c, FQ_ECAPACITY, "spawn capacity exceeded");
             return fail(c, FQ_ECAPACITY, "main list capacity exceeded");
         }
-        if (c->qmc[0].tau_search) {
-            const unsigned long long b = c->h_ctl->rs_max;
-            std::memcpy(&c->rs_max, &b, 8);
-        }
-        bool tau_changed = false;
+        fold_spawn_ratio(c, t0 + 1, stop);
         for (int64_t it = t0 + 1; it <= stop; ++it) {
             for (int r = 0; r < c->R; ++r) {
                 fq_estimators_t e;
@@ -1358,12 +1369,13 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                     // the last death step (the block's last iteration is this one)
                     if (c->qmc[r].tau_search && it == stop) {
                         double tau = c->qmc[r].tau;
-                        if (c->rs_max > 0.0) {
-                            const double bnd = 1.0 / c->rs_max;
+                        if (c->rs_max[r] > 0.0) {
+                            const double bnd = 1.0 / c->rs_max[r];
                             if (bnd < tau) tau = bnd;
                         }
-                        if (c->h_ctl->kd_max != 0) {
-                            const double d = from_ordered_key(c->h_ctl->kd_max) - c->shift[r];
+                        const unsigned long long kd = c->h_hist[(size_t)(stop % HIST_LEN) * c->R + r].kd_key;
+                        if (kd != 0) {
+                            const double d = from_ordered_key(kd) - c->shift[r];
                             if (d > 0.0) {
                                 const double bnd = 1.0 / d;
                                 if (bnd < tau) tau = bnd;
@@ -1371,7 +1383,8 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
                         }
                         if (tau != c->qmc[r].tau) {
                             c->qmc[r].tau = tau;
-                            tau_changed = true;
+                            HIPCHK(c, h2d(c->stream, (char *)c->w.rep + (size_t)r * sizeof(RepParams) + offsetof(RepParams, tau),
+                                          &c->qmc[r].tau, sizeof(double)));
                         }
                     }
                 }
@@ -1384,8 +1397,6 @@ fq_status fq_step(fq_ctx *c, int32_t n_iterations)
         }
         c->t = stop;
         done += nb;
-        if (tau_changed)
-            HIPCHK(c, h2d(c->stream, (char *)c->w.rep + offsetof(RepParams, tau), &c->qmc[0].tau, sizeof(double)));
         for (int r = 0; r < c->R; ++r) c->h_shift[r] = c->shift[r];
         HIPCHK(c, hipMemcpyAsync(c->w.shift, c->h_shift, 8 * c->R, hipMemcpyHostToDevice, c->stream));
         if (c->has_ss && !c->ss_active && c->t >= c->ss.start_iteration) {

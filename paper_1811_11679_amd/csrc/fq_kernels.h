@@ -53,11 +53,7 @@ struct Ctl {
     uint32_t err;
     uint32_t collision;    // equal sort keys with different determinants seen
     uint32_t ss_active;
-    // time-step search (one instance): bits of the largest |H_ji| / p_gen of
-    // any attempt so far (a non-negative double orders as its bits), and the
-    // order-preserving key of the largest K_ii of the last death step (0: none)
-    unsigned long long rs_max;
-    unsigned long long kd_max;
+    uint32_t pad_ts;
     uint32_t tickets[TK_COUNT];
     uint32_t hist[8][256];  // radix-sort digit histogram of the spawned keys
     // CCMC: N_0 and the sum of |N_i| over the excitors at the start of the
@@ -78,6 +74,11 @@ struct EstAcc {
     // CCMC: exact limbs (2^-64) of sum over pairs of singles a < b of
     // H_0,ab sgn(a_a a_b D_0) N_a N_b
     long long pair[4];
+    // time-step search, this iteration: bits of the largest |H_ji| / p_gen of
+    // the replica's attempts (a non-negative double orders as its bits) and
+    // the order-preserving key of the largest K_ii of its death step (0: none)
+    unsigned long long rs_bits;
+    unsigned long long kd_key;
 };
 constexpr int EST_FIELDS = 14;
 // replicas whose estimator partials a block keeps in LDS (the rest are added
@@ -202,7 +203,7 @@ struct Work {
     long long main_cap, spawn_cap, span_cap;
     int32_t R, rb, W, hist_len;
     uint64_t hmask;  // hash bits that enter a sort key (all but in collision tests)
-    int32_t tau_search;  // track the maxima of the time-step search (one instance)
+    int32_t tau_search;  // track the maxima of the time-step search (per replica)
     int32_t lds_tables;  // bytes of UEG tables the spawn kernel stages in LDS (0: read from global)
     int32_t lds_diag;    // bytes of diagonal tables the new-determinant kernel stages in LDS
     // method: 0 FCIQMC; density matrices on pair keys (Sec. 2.3): 1 DMQMC

@@ -89,6 +89,36 @@ __device__ void acc_finish(LocalAcc &a, bool active, long long *tab, int rl, Est
 
 enum { F_NW = 0, F_NOCC, F_N0, F_NSPAWN, F_NUNIQ, F_FLIPS, F_REJU, F_DEATH, F_SPAWN, F_REJ, F_L0, F_L1, F_L2, F_L3 };
 
+// Time-step search maxima, per replica, into the replica's estimator record
+// of the iteration: KD = false the largest |H_ji| / p_gen (as its bits), true
+// the largest K_ii (as an order-preserving key). A thread keeps the running
+// maximum of one replica and hands it over when it moves to another replica
+// and at the end of the kernel; there the wave reduces first when its holders
+// share one replica (the lists are sorted by replica, so they nearly always do).
+template <bool KD>
+__device__ __forceinline__ void ts_put(const Work &w, int rep, double v)
+{
+    if constexpr (KD)
+        atomicMax(&w.acc[rep].kd_key, ordered_key(v));
+    else
+        atomicMax(&w.acc[rep].rs_bits, (unsigned long long)__double_as_longlong(v));
+}
+
+template <bool KD>
+__device__ void ts_finish(const Work &w, double v, int rep, bool has)
+{
+    const uint64_t act = __ballot(has);
+    if (!act) return;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const int r0 = __shfl(rep, leader, 64);
+    if (__ballot(has && rep != r0) == 0) {
+        const double m = wave_max(has ? v : -INFINITY);
+        if (lane_id() == leader) ts_put<KD>(w, r0, m);
+    } else if (has) {
+        ts_put<KD>(w, rep, v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // iteration prologue / epilogue
 // ---------------------------------------------------------------------------
@@ -104,7 +134,6 @@ __global__ void k_begin(Work w)
         c->n_uniq = 0;
         c->n_att = c->n_att_new;
         c->collision = 0;
-        c->kd_max = 0;
         c->ccmc_n0 = 0;
         c->ccmc_nex = 0;
         c->n_single = 0;
@@ -262,8 +291,10 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
     const uint32_t epoch = epoch_of(t, 12);
     const int lane = lane_id(), wid = threadIdx.x >> 6;
     // time-step search: the largest |H_ji| / p_gen of this thread's attempts
-    const bool ts = !MULTI && w.tau_search != 0;
+    // of replica rs_rep
+    const bool ts = w.tau_search != 0;
     double rs_max = 0.0;
+    int rs_rep = 0;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     UegTables lu = w.sys[w.rep[0].sys].u;
     const double *hb_tri = nullptr;  // heat-bath pair weights staged in LDS (LT, molecular)
@@ -468,7 +499,14 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                     }
                     if (!skip) {
                         const double ah = fabs(hv);
-                        if (ts) rs_max = fmax(rs_max, ah / pgen);
+                        if (ts) {
+                            if (MULTI && (int)rep[it] != rs_rep) {
+                                if (rs_max > 0.0) ts_put<false>(w, rs_rep, rs_max);
+                                rs_max = 0.0;
+                                rs_rep = (int)rep[it];
+                            }
+                            rs_max = fmax(rs_max, ah / pgen);
+                        }
                         // DMQMC: the symmetrised Bloch equation's dbeta / 2 at each end
                         const double tau_s = (is_pair(KIND) && w.dm == 1) ? rp.tau * 0.5 : rp.tau;
                         double m;
@@ -576,10 +614,7 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
         if (span == nspans - 1 && threadIdx.x == 0) c->n_spawn = (unsigned long long)(base + tot);
         __syncthreads();
     }
-    if (ts) {
-        rs_max = wave_max(rs_max);
-        if (lane == 0 && rs_max > 0.0) atomicMax(&c->rs_max, (unsigned long long)__double_as_longlong(rs_max));
-    }
+    if (ts) ts_finish<false>(w, rs_max, rs_rep, rs_max > 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1286,8 +1321,9 @@ __global__ __launch_bounds__((MergeCfg<W, MI>::T)) void k_merge(Work w)
     acc.rep = -1;
     bool any = false;
     // time-step search: the largest K_ii of the entries this thread's death steps act on
-    const bool ts = !MULTI && w.tau_search != 0;
+    const bool ts = w.tau_search != 0;
     double kd_max = -INFINITY;
+    int kd_rep = 0;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(&c->tickets[TK_MERGE], 1u);
         __syncthreads();
@@ -1386,7 +1422,14 @@ __global__ __launch_bounds__((MergeCfg<W, MI>::T)) void k_merge(Work w)
                     v = (long long)n0 + w.ds.delta[(size_t)rep * w.ds.n + dsl];
                 } else if (n0 != 0) {
                     const RepParams &rp = w.rep[rep];
-                    if (ts) kd_max = fmax(kd_max, s_kd[a]);
+                    if (ts) {
+                        if (MULTI && rep != kd_rep) {
+                            if (kd_max > -INFINITY) ts_put<true>(w, kd_rep, kd_max);
+                            kd_max = -INFINITY;
+                            kd_rep = rep;
+                        }
+                        kd_max = fmax(kd_max, s_kd[a]);
+                    }
                     const double an = (double)(n0 < 0 ? -(long long)n0 : (long long)n0);
                     const double mm = (rp.tau * (s_kd[a] - w.shift[rep])) * an;
                     uint64_t h = sk;
@@ -1556,10 +1599,7 @@ __global__ __launch_bounds__((MergeCfg<W, MI>::T)) void k_merge(Work w)
         __syncthreads();
     }
     acc_finish(acc, any && acc.rep >= 0, tab, rl, w.acc, w.part_mrg);
-    if (ts) {
-        kd_max = wave_max(kd_max);
-        if (lane_id() == 0 && kd_max > -INFINITY) atomicMax(&c->kd_max, ordered_key(kd_max));
-    }
+    if (ts) ts_finish<true>(w, kd_max, kd_rep, kd_max > -INFINITY);
     if (blockIdx.x == 0 && threadIdx.x == 0 && ntiles == 0) {
         c->n_main_new = 0;
         w.att_off[0] = 0;

@@ -263,9 +263,29 @@ def test_tau_search_lowers_tau_identically():
     assert e["tau"] * e["spawn_ratio_max"] <= 1.0 + 1e-15
 
 
-def test_tau_search_needs_a_single_instance():
-    from paper_1811_11679_amd import fciqmc as F
-    sysd = dict(kind="hubbard", n_sites=8, periodic=1, t=1.0, U=4.0, n_alpha=4, n_beta=4)
-    with pytest.raises(F.FqError):
-        gpu_context([sysd, sysd], [dict(tau=0.01, init_pop=500.0, target_population=1e4, tau_search=1)] * 2,
-                    replicas=[0, 1])
+def test_tau_search_per_replica():
+    # three batched replicas of the gas at different densities, two with time
+    # steps too large and one small enough to stay: each replica's search sees
+    # only its own attempts and death steps, as one oracle run does (one
+    # maximum for the context would lower the first replica's tau to the
+    # densest gas's bound), and lowers only its own tau
+    sysds = [dict(kind="ueg", rs=rs, ecut_n2=2, n_alpha=7, n_beta=7) for rs in (1.0, 2.0, 0.5)]
+    taus = (0.02, 0.08, 0.002)
+    qs = [dict(tau=taus[r], rng_seed=11 + r, init_pop=3e3, target_population=2e4, initiator=1,
+               initiator_threshold=3.0, fixed_point_bits=8, spawn_cutoff=0.1, tau_search=1) for r in range(3)]
+    say("[case] tau search, 3 batched replicas")
+    ctx = gpu_context(sysds, qs, replicas=[0, 1, 2])
+    from oracle import oracle as O
+    runs = [O.Run(oracle_system(sysds[r]), oracle_qmc(sysds[r], qs[r], replica=r)) for r in range(3)]
+    for blk in range(6):
+        ctx.step(20)
+        for r in range(3):
+            runs[r].step(20)
+            assert_same_lists(ctx, runs[r], instance=r, where=f"tau search replica {r} block {blk}")
+            assert_same_estimators(ctx.estimators(r), runs[r].estimators(), where=f"tau search replica {r}")
+    e = [runs[r].estimators() for r in range(3)]
+    assert e[0]["tau"] < taus[0] and e[1]["tau"] < taus[1] and e[2]["tau"] == taus[2]
+    assert e[0]["tau"] > 1.0 / e[2]["spawn_ratio_max"]
+    for x in e:
+        assert x["spawn_ratio_max"] > 0.0 and x["tau"] * x["spawn_ratio_max"] <= 1.0 + 1e-15
+    ctx.close()
