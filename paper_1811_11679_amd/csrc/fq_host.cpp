@@ -228,7 +228,7 @@ size_t table_bytes(const HostSys &s)
 
 struct Layout {
     size_t total = 0;
-    size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge, st_spawn, st_att;
+    size_t ctl, acc, hist, shift, rep, sys, tables, att, span, mpart, st_scan, st_sort, st_red, st_merge, st_att;
     size_t part_red, part_mrg, newdet, bpart;
     size_t main[2][6];
     size_t sp[7];
@@ -295,7 +295,6 @@ Layout make_layout(int R, int W, int64_t mcap, int64_t scap, int64_t tables, int
     L.st_sort = take(8 * 256 * (size_t)tiles_of(scap, SORT_TILE_MIN));
     L.st_red = take(8 * (size_t)tiles_of(scap, 1024));
     L.st_merge = take(8 * (size_t)tiles_of(mcap + scap, 512));
-    L.st_spawn = take(8 * (size_t)(span_capacity(mcap, scap, W) + 2));
     L.st_att = take(8 * (size_t)tiles_of(mcap + scap, 512));
     L.part_red = take(8 * (size_t)PART_MAX_BLOCKS * acc_rows(R) * EST_FIELDS);
     L.part_mrg = take(8 * (size_t)PART_MAX_BLOCKS * acc_rows(R) * EST_FIELDS);
@@ -892,7 +891,6 @@ fq_status init_system(fq_ctx **out, const fq_system *sys, const fq_qmc *qmc, con
     w.st_sort = (unsigned long long *)(c->ws + c->L.st_sort);
     w.st_red = (unsigned long long *)(c->ws + c->L.st_red);
     w.st_merge = (unsigned long long *)(c->ws + c->L.st_merge);
-    w.st_spawn = (unsigned long long *)(c->ws + c->L.st_spawn);
     w.st_att = (unsigned long long *)(c->ws + c->L.st_att);
     w.part_red = (long long *)(c->ws + c->L.part_red);
     w.part_mrg = (long long *)(c->ws + c->L.part_mrg);

@@ -192,7 +192,7 @@ struct Work {
     long long *mpart;      // merge partition [tiles + 1]
     uint8_t *newdet;       // [main_cap]: 1 where the merge wrote a new determinant (K_jj still to compute)
     BoundaryPart *bpart;   // [reduction tiles]
-    unsigned long long *st_scan, *st_sort, *st_red, *st_merge, *st_spawn, *st_att;  // look-back status
+    unsigned long long *st_scan, *st_sort, *st_red, *st_merge, *st_att;  // look-back status
     // per-block estimator partials of the reduction and the merge:
     // [block][acc_rows(R)][EST_FIELDS], folded into acc by the epilogue
     long long *part_red, *part_mrg;

@@ -226,8 +226,11 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_attempts(Work w)
 // spawning (Sec. 2.4): one thread per attempt, parents found through the
 // attempt prefix (load balanced: a heavily populated determinant spreads its
 // attempts over many threads and tiles). A tile of 1024 consecutive attempts
-// finds its spawn count, takes its output offset by decoupled look-back (no
-// contended counter) and writes its records contiguously.
+// finds its spawn count, reserves that many records with one atomic on the
+// spawn counter and writes them contiguously. The records of different tiles
+// land in completion order: the radix sort and the segmented sums downstream
+// make the result independent of it (equal keys are summed as exact
+// integers), and a tile never waits on another.
 // ---------------------------------------------------------------------------
 
 
@@ -288,7 +291,6 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
     if (nspans + 1 > w.span_cap) return;
     const uint32_t t = c->t;
     const bool ss = c->ss_active != 0;
-    const uint32_t epoch = epoch_of(t, 12);
     const int lane = lane_id(), wid = threadIdx.x >> 6;
     // time-step search: the largest |H_ji| / p_gen of this thread's attempts
     // of replica rs_rep
@@ -561,10 +563,10 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                 if (q == wid) before[it] = tot;
                 tot += s_cnt[it][q];
             }
-        if (threadIdx.x < 64) {
-            const long long lb_ = lookback(w.st_spawn, span, epoch, (long long)tot);
-            if (threadIdx.x == 0) s_base = lb_;
-        }
+        // the tile's output range, reserved with one atomic: records land in
+        // tile completion order, which the sort and the segmented sums make
+        // irrelevant (equal keys are summed as exact integers)
+        if (threadIdx.x == 0) s_base = (long long)atomicAdd(&c->n_spawn, (unsigned long long)tot);
         // staged records get their sort key (a hash of the child) in the dense
         // output loop below, not in the divergent per-attempt code
         uint32_t rk[SP_I];
@@ -611,7 +613,6 @@ __global__ __launch_bounds__(SP_T) void k_spawn(Work w)
                     rec[W] = (uint64_t)(uint32_t)amp[it] | ((uint64_t)init[it] << 32);
                 }
         }
-        if (span == nspans - 1 && threadIdx.x == 0) c->n_spawn = (unsigned long long)(base + tot);
         __syncthreads();
     }
     if (ts) ts_finish<false>(w, rs_max, rs_rep, rs_max > 0.0);
