@@ -646,6 +646,11 @@ __global__ __launch_bounds__(256) void k_sort_hist(Work w)
     }
 }
 
+// predecessors a digit's look-back reads per round trip after the first (an
+// instrumented copy measured ~12 round trips per walk at four; eight made
+// each pass slower, the wider reads costing more than the shorter walks)
+constexpr int SORT_LB = 4;
+
 template <int OS_I>
 __global__ __launch_bounds__(OS_T) void k_sort_pass(Work w, int pass, const uint64_t *kin, const uint32_t *iin,
                                                     uint64_t *kout, uint32_t *iout)
@@ -732,17 +737,17 @@ __global__ __launch_bounds__(OS_T) void k_sort_pass(Work w, int pass, const uint
             } else {
                 st_store(st, st_pack(epoch, ST_AGG, cnt));
                 long long j = tile - 1;
-                int width = 1;  // the immediate predecessor first, then four per round trip
+                int width = 1;  // the immediate predecessor first, then SORT_LB per round trip
                 for (;;) {
-                    unsigned long long s4[4];
+                    unsigned long long s4[SORT_LB];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < SORT_LB; ++u)
                         s4[u] = (u < width && j - u >= 0) ? st_load(w.st_sort + (size_t)(j - u) * 256 + d) : 0ull;
                     bool done = false, stop = false;
                     int used = 0;
                     long long add = 0;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < SORT_LB; ++u) {
                         if (done || stop || u >= width) continue;
                         const unsigned long long s = s4[u];
                         const uint32_t e = (uint32_t)(s >> 40);
@@ -759,7 +764,7 @@ __global__ __launch_bounds__(OS_T) void k_sort_pass(Work w, int pass, const uint
                     j -= used;
                     if (done) break;
                     if (used == 0) __builtin_amdgcn_s_sleep(1);
-                    width = 4;
+                    width = SORT_LB;
                 }
                 st_store(st, st_pack(epoch, ST_INC, excl + cnt));
             }
@@ -832,62 +837,148 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
         int32_t am[RD_I];
         uint32_t fl[RD_I];
         bool valid[RD_I];
-#pragma unroll
-        for (int i = 0; i < RD_I; ++i) {
-            const long long e = base + i;
-            valid[i] = e < n;
-            sk[i] = 0;
-            am[i] = 0;
-            fl[i] = 0;
-#pragma unroll
-            for (int q = 0; q < W; ++q) kk[i][q] = 0;
-            if (valid[i]) {
-                sk[i] = skey[e];
-                const uint64_t *rec = w.sp.rec + (size_t)idx[e] * (W + 1);
-#pragma unroll
-                for (int q = 0; q < W; ++q) kk[i][q] = rec[q];
-                const uint64_t ai = rec[W];
-                am[i] = (int32_t)(uint32_t)ai;
-                fl[i] = (uint32_t)(ai >> 32);
-            }
-        }
-        s_lasts[threadIdx.x] = sk[RD_I - 1];
-#pragma unroll
-        for (int q = 0; q < W; ++q) s_lastk[threadIdx.x][q] = kk[RD_I - 1][q];
-        __syncthreads();
-        uint64_t psk;
-        uint64_t pk[W];
-        bool have_prev = base > 0;
-        if (threadIdx.x > 0) {
-            psk = s_lasts[threadIdx.x - 1];
-#pragma unroll
-            for (int q = 0; q < W; ++q) pk[q] = s_lastk[threadIdx.x - 1][q];
-        } else if (base > 0) {
-            psk = skey[base - 1];
-            const uint64_t *rec = w.sp.rec + (size_t)idx[base - 1] * (W + 1);
-#pragma unroll
-            for (int q = 0; q < W; ++q) pk[q] = rec[q];
-        } else {
-            psk = 0;
-#pragma unroll
-            for (int q = 0; q < W; ++q) pk[q] = 0;
-        }
         bool head[RD_I];
         int nh = 0;
+        // first pass with keys of up to two words: the tile's count goes out
+        // before the gathers (below); otherwise after them
+        constexpr bool SHORT = W <= 2;
+        const bool early = SHORT && !second;
+        long long ex = 0, tot = 0;
+        if constexpr (SHORT) {
 #pragma unroll
-        for (int i = 0; i < RD_I; ++i) {
-            head[i] = false;
-            if (valid[i]) {
-                const bool same_s = have_prev && psk == sk[i];
-                const bool same_k = same_s && key_eq<W>(pk, kk[i]);
-                if (same_s && !same_k) atomicOr(&c->collision, 1u);
-                head[i] = !same_k;
-                nh += head[i];
+            for (int i = 0; i < RD_I; ++i) {
+                const long long e = base + i;
+                valid[i] = e < n;
+                sk[i] = valid[i] ? skey[e] : 0;
             }
-            psk = sk[i];
+            s_lasts[threadIdx.x] = sk[RD_I - 1];
+            __syncthreads();
+            const uint64_t psk0 = threadIdx.x > 0 ? s_lasts[threadIdx.x - 1] : (base > 0 ? skey[base - 1] : 0);
+            // First pass, keys of up to two words: a segment starts wherever the
+            // sort key changes (equal keys holding different determinants are a
+            // collision, flagged below, after which the fix-up and the second pass
+            // redo the tile). The tile's segment count then needs no record, so it
+            // is published before the gathers, and the tiles after this one do not
+            // wait on them. (Longer keys keep the single look-back after the
+            // gathers: the early count would cost them a wave per SIMD.)
+            if (early) {
+                int nh0 = 0;
+                uint64_t p = psk0;
+                bool hp = base > 0;
 #pragma unroll
-            for (int q = 0; q < W; ++q) pk[q] = kk[i][q];
-            have_prev = true;
+                for (int i = 0; i < RD_I; ++i) {
+                    if (valid[i]) nh0 += (hp && p == sk[i]) ? 0 : 1;
+                    p = sk[i];
+                    hp = true;
+                }
+                ex = block_excl_scan<long long>((long long)nh0, tot, s_red);
+                if (threadIdx.x == 0) lookback_publish(w.st_red, tile, epoch, tot);
+            }
+#pragma unroll
+            for (int i = 0; i < RD_I; ++i) {
+                am[i] = 0;
+                fl[i] = 0;
+#pragma unroll
+                for (int q = 0; q < W; ++q) kk[i][q] = 0;
+                if (valid[i]) {
+                    const uint64_t *rec = w.sp.rec + (size_t)idx[base + i] * (W + 1);
+#pragma unroll
+                    for (int q = 0; q < W; ++q) kk[i][q] = rec[q];
+                    const uint64_t ai = rec[W];
+                    am[i] = (int32_t)(uint32_t)ai;
+                    fl[i] = (uint32_t)(ai >> 32);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < W; ++q) s_lastk[threadIdx.x][q] = kk[RD_I - 1][q];
+            __syncthreads();
+            uint64_t psk = psk0;
+            uint64_t pk[W];
+            bool have_prev = base > 0;
+            if (threadIdx.x > 0) {
+#pragma unroll
+                for (int q = 0; q < W; ++q) pk[q] = s_lastk[threadIdx.x - 1][q];
+            } else if (base > 0) {
+                const uint64_t *rec = w.sp.rec + (size_t)idx[base - 1] * (W + 1);
+#pragma unroll
+                for (int q = 0; q < W; ++q) pk[q] = rec[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < W; ++q) pk[q] = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < RD_I; ++i) {
+                head[i] = false;
+                if (valid[i]) {
+                    const bool same_s = have_prev && psk == sk[i];
+                    const bool same_k = same_s && key_eq<W>(pk, kk[i]);
+                    if (same_s && !same_k) atomicOr(&c->collision, 1u);
+                    // the second pass follows the key order the fix-up gave each
+                    // collision run
+                    head[i] = early ? !same_s : !same_k;
+                    nh += head[i];
+                }
+                psk = sk[i];
+#pragma unroll
+                for (int q = 0; q < W; ++q) pk[q] = kk[i][q];
+                have_prev = true;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < RD_I; ++i) {
+                const long long e = base + i;
+                valid[i] = e < n;
+                sk[i] = 0;
+                am[i] = 0;
+                fl[i] = 0;
+#pragma unroll
+                for (int q = 0; q < W; ++q) kk[i][q] = 0;
+                if (valid[i]) {
+                    sk[i] = skey[e];
+                    const uint64_t *rec = w.sp.rec + (size_t)idx[e] * (W + 1);
+#pragma unroll
+                    for (int q = 0; q < W; ++q) kk[i][q] = rec[q];
+                    const uint64_t ai = rec[W];
+                    am[i] = (int32_t)(uint32_t)ai;
+                    fl[i] = (uint32_t)(ai >> 32);
+                }
+            }
+            s_lasts[threadIdx.x] = sk[RD_I - 1];
+#pragma unroll
+            for (int q = 0; q < W; ++q) s_lastk[threadIdx.x][q] = kk[RD_I - 1][q];
+            __syncthreads();
+            uint64_t psk;
+            uint64_t pk[W];
+            bool have_prev = base > 0;
+            if (threadIdx.x > 0) {
+                psk = s_lasts[threadIdx.x - 1];
+#pragma unroll
+                for (int q = 0; q < W; ++q) pk[q] = s_lastk[threadIdx.x - 1][q];
+            } else if (base > 0) {
+                psk = skey[base - 1];
+                const uint64_t *rec = w.sp.rec + (size_t)idx[base - 1] * (W + 1);
+#pragma unroll
+                for (int q = 0; q < W; ++q) pk[q] = rec[q];
+            } else {
+                psk = 0;
+#pragma unroll
+                for (int q = 0; q < W; ++q) pk[q] = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < RD_I; ++i) {
+                head[i] = false;
+                if (valid[i]) {
+                    const bool same_s = have_prev && psk == sk[i];
+                    const bool same_k = same_s && key_eq<W>(pk, kk[i]);
+                    if (same_s && !same_k) atomicOr(&c->collision, 1u);
+                    head[i] = !same_k;
+                    nh += head[i];
+                }
+                psk = sk[i];
+#pragma unroll
+                for (int q = 0; q < W; ++q) pk[q] = kk[i][q];
+                have_prev = true;
+            }
         }
         // the open segment at this thread's end (after its last head, or all
         // of its elements without a head), passed to the right
@@ -965,10 +1056,9 @@ __global__ __launch_bounds__(RD_T) void k_reduce(Work w, int second)
             carry_s = es;
             carry_f = ef;
         }
-        long long tot;
-        const long long ex = block_excl_scan<long long>((long long)nh, tot, s_red);
+        if (!early) ex = block_excl_scan<long long>((long long)nh, tot, s_red);
         if (threadIdx.x < 64) {
-            const long long lb_ = lookback(w.st_red, tile, epoch, tot);
+            const long long lb_ = early ? lookback_wait(w.st_red, tile, epoch, tot) : lookback(w.st_red, tile, epoch, tot);
             if (threadIdx.x == 0) s_base = lb_;
         }
         __syncthreads();

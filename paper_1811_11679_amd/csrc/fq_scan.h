@@ -50,19 +50,19 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Decoupled look-back, run by one whole wavefront: publishes this tile's
-// aggregate, then inspects the 64 preceding tiles at a time until it meets an
-// inclusive prefix, publishes its own inclusive prefix and returns the
-// exclusive one (to every lane). It waits only on tiles with smaller tickets,
-// which are resident and never wait on this tile, so every wait ends.
-static __device__ long long lookback(unsigned long long *st, long long tile, uint32_t epoch, long long agg)
+// The two halves of a look-back, for a tile that can publish its aggregate
+// well before it needs its prefix (other work in between shortens the waits
+// of the tiles after it): lookback_publish by one lane, then lookback_wait by
+// one whole wavefront with the same aggregate.
+static __device__ void lookback_publish(unsigned long long *st, long long tile, uint32_t epoch, long long agg)
+{
+    st_store(st + tile, st_pack(epoch, tile == 0 ? ST_INC : ST_AGG, agg));
+}
+
+static __device__ long long lookback_wait(unsigned long long *st, long long tile, uint32_t epoch, long long agg)
 {
     const int lane = lane_id();
-    if (tile == 0) {
-        if (lane == 0) st_store(st, st_pack(epoch, ST_INC, agg));
-        return 0;
-    }
-    if (lane == 0) st_store(st + tile, st_pack(epoch, ST_AGG, agg));
+    if (tile == 0) return 0;
     long long excl = 0;
     long long j = tile - 1;
     for (;;) {
@@ -87,6 +87,17 @@ static __device__ long long lookback(unsigned long long *st, long long tile, uin
     }
     if (lane == 0) st_store(st + tile, st_pack(epoch, ST_INC, excl + agg));
     return excl;
+}
+
+// Decoupled look-back, run by one whole wavefront: publishes this tile's
+// aggregate, then inspects the 64 preceding tiles at a time until it meets an
+// inclusive prefix, publishes its own inclusive prefix and returns the
+// exclusive one (to every lane). It waits only on tiles with smaller tickets,
+// which are resident and never wait on this tile, so every wait ends.
+static __device__ long long lookback(unsigned long long *st, long long tile, uint32_t epoch, long long agg)
+{
+    if (lane_id() == 0) lookback_publish(st, tile, epoch, agg);
+    return lookback_wait(st, tile, epoch, agg);
 }
 
 // exclusive block scan of one value per thread (blockDim = 256)
