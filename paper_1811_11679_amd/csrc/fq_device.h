@@ -114,21 +114,25 @@ __device__ __forceinline__ uint32_t skey_rep(uint64_t s, int rb) { return rb ? (
 // ---------------------------------------------------------------------------
 // bit strings
 // ---------------------------------------------------------------------------
+// Every word is touched with a mask (no array index computed from P): a
+// conditional update of one word lets the compiler turn the loop into an
+// indexed access, which puts longer keys in scratch memory.
 template <int W>
 __device__ __forceinline__ int getbit(const uint64_t (&k)[W], int P)
 {
-    int r = 0;
+    const int wd = P >> 6;
+    uint64_t x = 0;
 #pragma unroll
-    for (int i = 0; i < W; ++i)
-        if ((P >> 6) == i) r = (int)((k[i] >> (P & 63)) & 1u);
-    return r;
+    for (int i = 0; i < W; ++i) x |= (wd == i) ? k[i] : 0ull;
+    return (int)((x >> (P & 63)) & 1u);
 }
 template <int W>
 __device__ __forceinline__ void flipbit(uint64_t (&k)[W], int P)
 {
+    const int wd = P >> 6;
+    const uint64_t m = (uint64_t)1 << (P & 63);
 #pragma unroll
-    for (int i = 0; i < W; ++i)
-        if ((P >> 6) == i) k[i] ^= (uint64_t)1 << (P & 63);
+    for (int i = 0; i < W; ++i) k[i] ^= (wd == i) ? m : 0ull;
 }
 
 // mask of bits [lo, hi) within word i
